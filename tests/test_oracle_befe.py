@@ -1,0 +1,157 @@
+"""Pins for the oracle's BEFE step, residual, JVP and VJP (CPU).
+
+Each test checks the oracle against a property the paper or the mathematics
+fixes, not against itself:
+* laminar Couette flow U = y is a fixed point (Sec. 3.1, eq. befe);
+* the increment identity B_dt - I = (I - dt L)^{-1} dt (L + N) holds for
+  every dt (Sec. 2, eq. mycalc), with L + N formed without any solve;
+* for large dt, B_dt - I tends to -L^{-1}(L + N) at rate 1/dt (eq. largedt);
+* outputs are divergence free and meet the wall values (Sec. 3.2);
+* N is quadratic, so the central difference equals the JVP for any step
+  (Sec. 2, eq. finitediff) and the linearisation N_U is exact;
+* translations in x and z, the reflection z -> -z and the rotation
+  (x, y) -> (-x, -y) commute with Phi (symmetries of plane Couette flow);
+* the VJP satisfies <w, J v> = <J^T w, v> and equals the transpose of the
+  dense Jacobian assembled column by column from JVPs.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import pack
+from oracle.befe import Befe
+from oracle.grid import Grid
+from paper_1804_05087_amd import synth
+
+BOX = (2 * math.pi / 1.14, 2 * math.pi / 2.5)
+
+
+def _setup(dims=(8, 13, 8), re=400.0, dt=100.0, seed=0):
+    g = Grid(*dims, *BOX)
+    B = Befe(g, re, dt)
+    u = synth.perturbation_field(*dims, *BOX, seed=seed)
+    return g, B, u
+
+
+def test_laminar_is_fixed_point():
+    g, B, _ = _setup((16, 17, 16))
+    lam = synth.laminar_field(16, 17, 16)
+    r = B.residual(lam)
+    assert np.abs(r).max() <= 1e-15
+    assert np.abs(B.phi(lam) - lam).max() <= 1e-15
+
+
+@pytest.mark.parametrize("dt", [1e-3, 1.0, 100.0, 1e6])
+def test_increment_identity(dt):
+    g, B, u = _setup(dt=dt)
+    lhs = B.phi(u) - u
+    Lu_plus_N = B.laplacian(u) / B.re + B.nonlinear(u)
+    rhs = B.solver.solve(Lu_plus_N)
+    # Phi(u) - u cancels O(|u|) terms: allow the rounding of u itself
+    assert np.abs(lhs - rhs).max() <= 1e-13 * np.abs(lhs).max() + 1e-15 * np.abs(u).max()
+
+
+def test_large_dt_limit():
+    g = Grid(8, 13, 8, *BOX)
+    u = synth.perturbation_field(8, 13, 8, *BOX, seed=1)
+    Binf = Befe(g, 400.0, np.inf)
+    target = Binf.solver.solve(Binf.laplacian(u) / 400.0 + Binf.nonlinear(u))
+    scaled = []
+    for dt in (1e4, 1e6, 1e8):
+        B = Befe(g, 400.0, dt)
+        err = np.linalg.norm(B.phi(u) - u - target) / np.linalg.norm(target)
+        scaled.append(err * dt)
+    # first-order convergence: err * dt approaches a constant
+    assert abs(scaled[1] - scaled[2]) < 1e-2 * scaled[2]
+    assert abs(scaled[0] - scaled[2]) < 1e-1 * scaled[2]
+    assert scaled[2] < 1e3
+
+
+def test_divergence_and_walls():
+    g, B, u = _setup((8, 17, 8))
+    phi = B.phi(u)
+    assert np.abs(B.divergence(phi)).max() < 1e-13
+    top, bot = B.wall_values(phi)
+    top[0, 0, 0] -= 1.0
+    bot[0, 0, 0] += 1.0
+    assert np.abs(top).max() < 1e-14 and np.abs(bot).max() < 1e-14
+    du = synth.random_admissible(8, 17, 8, *BOX, seed=4)
+    j = B.jvp(u, du)
+    assert np.abs(B.divergence(j)).max() < 1e-13
+    t, b = B.wall_values(j)
+    assert np.abs(t).max() < 1e-14 and np.abs(b).max() < 1e-14
+
+
+def test_jvp_is_exact_central_difference():
+    g, B, u = _setup((8, 13, 8), dt=10.0)
+    du = synth.random_admissible(8, 13, 8, *BOX, seed=9, scale=0.3)
+    for op in ("phi", "residual"):
+        f = B.phi if op == "phi" else B.residual
+        jv = B.jvp(u, du, op)
+        cd = (f(u + du) - f(u - du)) / 2.0
+        assert np.abs(jv - cd).max() <= 1e-12 * np.abs(jv).max()
+        h = 1e-6
+        fd = (f(u + h * du) - f(u - h * du)) / (2 * h)
+        assert np.abs(jv - fd).max() <= 1e-7 * np.abs(jv).max()
+
+
+def test_translation_and_reflection_symmetry():
+    g, B, u = _setup((8, 13, 8))
+    phi = B.phi(u)
+    sx, sz = 0.37, 1.1
+    ph = np.exp(1j * (g.kx()[:, None, None] * sx + g.kz()[None, :, None] * sz))
+    assert np.abs(B.phi(u * ph) - phi * ph).max() < 1e-14
+    neg = np.array([(g.nx - i) % g.nx for i in range(g.nx)])
+
+    def reflect_z(a):
+        out = np.conj(a[:, neg])
+        out[2] *= -1
+        return out
+
+    assert np.abs(B.phi(reflect_z(u)) - reflect_z(phi)).max() < 1e-14
+    sgn = (-1.0) ** np.arange(g.ny)
+
+    def rotate_xy(a):
+        out = a[:, neg] * sgn
+        out[0] *= -1
+        out[1] *= -1
+        return out
+
+    assert np.abs(B.phi(rotate_xy(u)) - rotate_xy(phi)).max() < 1e-14
+
+
+@pytest.mark.parametrize("op", ["phi", "residual"])
+def test_vjp_dot_product(op):
+    g, B, u = _setup((8, 13, 8), dt=10.0)
+    v = synth.random_admissible(8, 13, 8, *BOX, seed=21)
+    w = synth.random_spectral(8, 13, 8, seed=22)
+    Jv = B.jvp(u, v, op)
+    JTw = B.vjp(u, w, op)
+    lhs = pack.packed_dot(w, Jv, g)
+    rhs = pack.packed_dot(JTw, v, g)
+    assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + abs(rhs) + 1e-30) * 10
+
+
+def test_dense_jacobian_transpose_and_structure():
+    dims = (4, 7, 4)
+    g, B, u = _setup(dims, dt=100.0)
+    n = pack.packed_length(g)
+    J = np.zeros((n, n))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        J[:, k] = pack.pack(B.jvp(u, pack.unpack(e, g)), g)
+    rng = np.random.default_rng(3)
+    for k in rng.choice(n, 12, replace=False):
+        e = np.zeros(n)
+        e[k] = 1.0
+        row = pack.pack(B.vjp(u, pack.unpack(e, g)), g)
+        assert np.abs(row - J[k]).max() <= 1e-13 * np.abs(J).max()
+    # J_Phi maps into the admissible subspace: rank = admissible dimension,
+    # so J_r = (J_Phi - I)/dt has eigenvalue -1/dt with multiplicity n - m.
+    N = g.N
+    m = (2 * N - 4) * 2 * ((g.nx - 1) * (g.nz - 1) - 1) // 2 + 2 * (N - 1)
+    s = np.linalg.svd(J, compute_uv=False)
+    rank = int(np.sum(s > 1e-10 * s[0]))
+    assert rank == m
