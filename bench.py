@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Benchmark of the Stokes-preconditioned BEFE hot path on one MI355X.
+
+Workload (default): plane Couette flow, Re = 1000, box 2pi/1.14 x 2 x 2pi/2.5,
+grid 48 x 65 x 48 (Fourier x Chebyshev x Fourier), dt = T = 100, initial field
+= laminar flow + the seeded divergence-free perturbation (energy 1e-2, seed 0).
+
+A timed step is one evaluation of Phi_dt(u) = (I - dt L)^{-1}(u + dt N(u)) in
+FP64 on a field resident in HBM; `value` is FP64 evaluations per second. The
+same JSON line also reports the mixed-precision Phi rate, the JVP rates (the
+GMRES matvec), a Newton-GMRES solve, the roofline position of the dominant
+kernel (timed live with HIP events) and the CPU oracle timed on a bounded
+sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "couette_48x65x48_re1000_dt100": dict(nx=48, ny=65, nz=48, re=1000.0, dt=100.0,
+                                           lx=2 * math.pi / 1.14, lz=2 * math.pi / 2.5),
+    "couette_16x17x16_re400_dt100": dict(nx=16, ny=17, nz=16, re=400.0, dt=100.0,
+                                          lx=2 * math.pi / 1.14, lz=2 * math.pi / 2.5),
+    "couette_32x33x32_re400_dt100": dict(nx=32, ny=33, nz=32, re=400.0, dt=100.0,
+                                          lx=2 * math.pi / 1.14, lz=2 * math.pi / 2.5),
+    "couette_96x97x96_re2000_dt100": dict(nx=96, ny=97, nz=96, re=2000.0, dt=100.0,
+                                           lx=4 * math.pi, lz=2 * math.pi),
+}
+DEFAULT = "couette_48x65x48_re1000_dt100"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(w, fp32=False, jvp=False):
+    """Compulsory HBM bytes per launch of each kernel (read once + written once)."""
+    nx, ny, nz = w["nx"], w["ny"], w["nz"]
+    nzm, nzh, px, pz = nz // 2, nz // 2 + 1, 3 * nx // 2, 3 * nz // 2
+    c = 8 if fp32 else 16            # complex element of the transform path
+    r = 4 if fp32 else 8
+    canon = 3 * nx * nzh * ny * 16   # FP64 canonical field
+    yv1 = ny * nzm * nx * c          # one y-valued spectral field
+    xp1 = ny * px * nzm * c          # one x-physical field
+    n1 = ny
+    stride = ((10 * n1 + 12) + 1) // 2 * 2
+    modes = nx * nzh
+    return {
+        "k_synth_y": 3 * nx * nzm * ny * 16 + 5 * yv1,
+        "k_fft_x_inv": 5 * yv1 + 6 * xp1,
+        "k_z_product": 6 * xp1 + 3 * xp1 + (6 * ny * px * pz * r if jvp else 0),
+        "k_fft_x_fwd": 3 * xp1 + 3 * yv1,
+        "k_analysis_rhs": 3 * yv1 + 2 * canon,
+        "k_stokes_solve": 2 * canon + modes * stride * 8,
+    }
+
+
+def time_loop(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1000.0, wall
+
+
+def kernel_profile(P, fn, reps):
+    P.profile_read(reset=True)
+    P.profile_enable(True)
+    for _ in range(reps):
+        fn()
+    prof = P.profile_read(reset=True)
+    P.profile_enable(False)
+    return prof
+
+
+def cpu_baseline(w, u_np, budget_s=12.0):
+    """The CPU oracle timed on a bounded sample of the same workload.
+
+    Sample: the full dealiased nonlinear term plus the dense per-mode solve on
+    a random quarter of the Fourier modes, repeated until `budget_s` seconds;
+    the time of one full evaluation is extrapolated linearly in the number of
+    modes (factorisations excluded, like the GPU plan creation)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle.befe import Befe
+    from oracle.grid import Grid
+    g = Grid(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"])
+    valid = [(i, j) for i in range(g.nx) for j in range(g.nzh) if g.valid()[i, j]]
+    rng = np.random.default_rng(0)
+    sub = [valid[k] for k in rng.choice(len(valid), max(1, len(valid) // 4), replace=False)]
+    with threadpool_limits(limits=1):
+        B = Befe(g, w["re"], w["dt"], modes=sub)
+        tn = ts = 0.0
+        reps = 0
+        t_start = time.perf_counter()
+        while True:
+            t0 = time.perf_counter()
+            n = B.nonlinear(u_np)
+            t1 = time.perf_counter()
+            B.solver.solve(u_np / w["dt"] + n, 1.0, -1.0)
+            t2 = time.perf_counter()
+            tn += t1 - t0
+            ts += t2 - t1
+            reps += 1
+            if time.perf_counter() - t_start > budget_s:
+                break
+    per_eval = (tn + ts * len(valid) / len(sub)) / reps
+    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{reps} x (full nonlinear term + dense solve on {len(sub)} of "
+                       f"{len(valid)} modes), extrapolated to all modes; 1 thread")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-newton", action="store_true")
+    ap.add_argument("--newton-krylov", type=int, default=200)
+    ap.add_argument("--newton-max", type=int, default=10)
+    ap.add_argument("--newton-rtol", type=float, default=1e-3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(this build runs on a single MI355X; see DESIGN.md for how it would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1804_05087_amd import SP_FP64, SP_MIXED, SP_OP_RESIDUAL, Plan, synth
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    u_np = synth.perturbation_field(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], seed=0)
+    u = torch.from_numpy(u_np).to(dev)
+    du_np = synth.random_admissible(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], seed=1)
+    du = torch.from_numpy(du_np).to(dev)
+    t0 = time.perf_counter()
+    P = Plan(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], w["re"], w["dt"], device=dev)
+    plan_s = time.perf_counter() - t0
+    out = P.empty()
+    log("workload", args.workload, "plan", round(plan_s, 3), "s")
+
+    # ---- FP64 Phi: the headline
+    gpu_s, wall_s = time_loop(torch, lambda: P.befe_step(u, out), args.steps, args.warmup)
+    ms_per_step = 1000.0 * gpu_s / args.steps
+    evals = args.steps / gpu_s
+    log("phi fp64", evals, "evals/s", ms_per_step, "ms/eval; wall", wall_s)
+    res = {}
+    steps2 = max(10, args.steps // 2)
+    P.set_precision(SP_MIXED)
+    s, _ = time_loop(torch, lambda: P.befe_step(u, out), steps2, args.warmup)
+    res["phi_mixed_evals_per_s"] = steps2 / s
+    P.linearize(u)
+    s, _ = time_loop(torch, lambda: P.jvp_lin(du, SP_OP_RESIDUAL, out), steps2, args.warmup)
+    res["jvp_mixed_evals_per_s"] = steps2 / s
+    P.set_precision(SP_FP64)
+    P.linearize(u)
+    s, _ = time_loop(torch, lambda: P.jvp_lin(du, SP_OP_RESIDUAL, out), steps2, args.warmup)
+    res["jvp_fp64_evals_per_s"] = steps2 / s
+    log("rates", res)
+
+    # ---- per-kernel durations inside the FP64 Phi loop (HIP events, plan stream)
+    prof = kernel_profile(P, lambda: P.befe_step(u, out), max(20, min(200, args.steps)))
+    ab = algorithmic_bytes(w)
+    kernels = {}
+    for name, (cnt, ms) in prof.items():
+        avg_us = 1000.0 * ms / cnt
+        entry = {"launches": cnt, "avg_us": round(avg_us, 3)}
+        if name in ab:
+            entry["alg_bytes"] = ab[name]
+            entry["achieved_GBs"] = round(ab[name] / (avg_us * 1e-6) / 1e9, 1)
+        kernels[name] = entry
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
+    d = kernels[dom]
+    achieved = d.get("achieved_GBs", 0.0)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "bytes_per_launch": d.get("alg_bytes"), "avg_us": d["avg_us"],
+                "traffic": None}
+    sum_us = sum(k["avg_us"] * k["launches"] for k in kernels.values()) / max(
+        1, kernels["k_stokes_solve"]["launches"])
+    log("kernels", kernels)
+
+    # ---- Newton-GMRES to ||r|| < 1e-10 (FP64 and mixed Jacobian actions)
+    newton = {}
+    if not args.no_newton:
+        for name, prec in (("fp64", SP_FP64), ("mixed", SP_MIXED)):
+            P.set_precision(prec)
+            uu = u.clone()
+            torch.cuda.synchronize()
+            rep = P.newton_gmres(uu, max_newton=args.newton_max, max_krylov=args.newton_krylov,
+                                 gmres_rtol=args.newton_rtol, newton_tol=1e-10)
+            lam = torch.from_numpy(synth.laminar_field(w["nx"], w["ny"], w["nz"])).to(dev)
+            newton[name] = {
+                "converged": rep["converged"], "seconds": round(rep["seconds"], 4),
+                "newton_iters": rep["newton_iters"], "total_krylov": rep["total_krylov"],
+                "total_actions": rep["total_actions"],
+                "final_res_norm": rep["res_norm"][-1],
+                "dist_to_laminar_L2": P.norm((uu - lam).contiguous()),
+                "res_history": [float(f"{x:.3e}") for x in rep["res_norm"]],
+                "krylov": rep["krylov"],
+            }
+            log("newton", name, newton[name])
+        P.set_precision(SP_FP64)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, u_np)
+        log("cpu baseline", cpu)
+
+    line = {
+        "metric": "phi_dt_evals_per_s_fp64",
+        "value": round(evals, 2),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded divergence-free perturbation of laminar Couette flow)",
+        "config": {"workload": args.workload, "grid": [w["nx"], w["ny"], w["nz"]],
+                   "re": w["re"], "dt": w["dt"], "box": [w["lx"], 2.0, w["lz"]],
+                   "parallelism": "single-gpu"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "rates": {k: round(v, 2) for k, v in res.items()},
+        "kernel_us_per_eval": round(sum_us, 3),
+        "kernels": kernels,
+        "newton": newton,
+        "plan_seconds": round(plan_s, 4),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * sp.h -- C ABI of the MI355X Stokes-preconditioned BEFE library.
+ *
+ * The library evaluates one large Backwards-Euler / Forwards-Euler step of
+ * plane Couette flow,
+ *
+ *     Phi_dt(u) = (I - dt L)^{-1} (u + dt N(u)),        (paper Sec. 2, eq. befe)
+ *
+ * with L = (1/Re) Laplacian, N(u) = u x curl(u) (the advective term; its
+ * gradient part is absorbed by the pressure), the no-slip walls, the
+ * incompressibility constraint and the pressure carried inside the implicit
+ * solve (Sec. 2, after eq. befe; Sec. 3.2: exact direct inversion, divergence
+ * free to machine accuracy by the influence-matrix technique). The root of the
+ * Stokes-preconditioned operator G = B_T - I (Sec. 2, eq. Gstokes) is sought by
+ * Newton's method (eqs. linear, biglin) with unrestarted GMRES (eq. Kspace).
+ *
+ * Discretisation (Sec. 3.2): Fourier in x and z, Chebyshev in y on the
+ * Gauss-Lobatto grid y_j = cos(pi j / N), N = ny - 1; products are formed on
+ * the 3/2-padded grid (3nx/2) x ny x (3nz/2). The per-mode implicit solve is
+ * the Chebyshev-tau system with momentum imposed on T_0..T_{N-2}, no-slip
+ * walls and continuity on every coefficient T_0..T_N.
+ *
+ * FIELD LAYOUT (every field argument, "canonical layout"):
+ *   device pointer to interleaved complex128 (re, im) numbers, C order
+ *   [3][nx][nz/2+1][ny]: velocity component, Fourier index i in x (m_x = i
+ *   for i < nx/2, i - nx otherwise), m_z = 0..nz/2, Chebyshev coefficient n.
+ *   Inputs must be zero at the Nyquist indices (i = nx/2, m_z = nz/2), have a
+ *   Hermitian m_z = 0 plane (entry at -m_x = conjugate of the one at +m_x) and a
+ *   real (0,0) mode; outputs have the same form up to rounding.
+ *   The full step works on the total velocity; laminar Couette flow u = y e_x
+ *   is its fixed point. Linearised and adjoint steps use homogeneous walls.
+ *
+ * OWNERSHIP: the caller owns every field buffer (e.g. torch tensors). The plan
+ * owns its precomputed operator data and internal scratch (device memory it
+ * allocates at creation) and, unless a workspace is supplied, the Krylov
+ * basis of sp_newton_gmres. Output buffers must not alias inputs unless stated.
+ *
+ * STREAMS: a plan is bound to one HIP stream (given at creation, NULL = the
+ * null stream). Every call is enqueued on it and returns without waiting,
+ * except where "synchronises" is stated. A plan is not thread safe.
+ *
+ * ERRORS: every call returns an sp_status. Parameters are validated on the
+ * host before any HIP call; HIP failures return SP_ERR_HIP; a per-plan message
+ * is available from sp_last_error. Nothing throws across the ABI.
+ */
+#ifndef SP_H
+#define SP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SP_OK = 0,
+  SP_ERR_INVALID = -1,       /* bad parameter or NULL pointer                */
+  SP_ERR_SHAPE = -2,         /* grid not supported by the kernels            */
+  SP_ERR_HIP = -3,           /* a HIP runtime call failed                    */
+  SP_ERR_NOMEM = -4,         /* device allocation failed                      */
+  SP_ERR_NOT_CONVERGED = -5, /* Newton stopped before the tolerance          */
+  SP_ERR_NONFINITE = -6      /* a residual norm was NaN or Inf               */
+} sp_status;
+
+/* Arithmetic of sp_befe_step and of the Jacobian actions (sp_jvp / sp_vjp and
+ * the GMRES matvecs). SP_MIXED: transforms, products and y-contractions in
+ * FP32 with FP32 accumulation; the implicit per-mode solves stay FP64. The
+ * Newton residual (sp_residual) and the GMRES orthogonalisation are always
+ * FP64. */
+typedef enum { SP_FP64 = 0, SP_MIXED = 1 } sp_precision;
+
+/* Which Jacobian: of Phi_dt, or of r = (Phi_dt(u) - u)/dt (= G^Stokes/T). */
+typedef enum { SP_OP_PHI = 0, SP_OP_RESIDUAL = 1 } sp_op;
+
+typedef struct {
+  int32_t nx, ny, nz;          /* nx, nz even >= 4 with 3nx/2, 3nz/2 of the form
+                                  2^a 3^b; 5 <= ny <= 129                     */
+  double lx, lz;               /* periodic box lengths (> 0); y in [-1, 1]     */
+  double re;                   /* Reynolds number, L = (1/Re) Laplacian (> 0)  */
+  double dt;                   /* BEFE step = T of G^Stokes_T (> 0, finite)    */
+  double wall_upper, wall_lower; /* wall velocities in x at y = +1 / -1       */
+  int32_t precision;           /* sp_precision of the Jacobian actions         */
+} sp_params;
+
+typedef struct sp_plan sp_plan;
+
+/* Validates *params, precomputes the per-mode solve data (Chebyshev-tau
+ * factorisations and influence matrices for this Re and dt), uploads it and
+ * allocates scratch. hip_stream: a hipStream_t or NULL. Synchronises. */
+sp_status sp_plan_create(const sp_params* params, void* hip_stream, sp_plan** out);
+sp_status sp_plan_destroy(sp_plan* plan);
+/* Recomputes the per-mode data for a new dt (> 0). Synchronises. */
+sp_status sp_plan_set_dt(sp_plan* plan, double dt);
+/* Selects the precision of subsequent Jacobian actions. */
+sp_status sp_plan_set_precision(sp_plan* plan, int32_t precision);
+/* shape4 = {3, nx, nz/2+1, ny}; packed_n = 3 ny (nx-1)(nz-1). */
+sp_status sp_state_shape(const sp_plan* plan, int64_t shape4[4], int64_t* packed_n);
+/* Device bytes of a Krylov workspace for sp_newton_gmres with max_krylov. */
+sp_status sp_plan_workspace_bytes(const sp_plan* plan, int32_t max_krylov, size_t* bytes);
+/* Supplies that workspace (caller-owned device memory, 256-byte aligned). The
+ * plan keeps the pointer until it is replaced or the plan destroyed. */
+sp_status sp_plan_set_workspace(sp_plan* plan, void* dev_ptr, size_t bytes);
+
+/* N(u): the dealiased advective term u x curl(u) as Chebyshev coefficients
+ * (Sec. 3.2, pseudospectral product). out must not alias u. */
+sp_status sp_nonlinear(sp_plan* plan, const double* u, double* out);
+
+/* The implicit solve: out = S(g), the velocity solving
+ * (1/Re) Lap phi - phi/dt - grad p = -g, div phi = 0, with the wall velocities
+ * when inhomogeneous != 0 and zero walls otherwise (Sec. 2, after eq. befe;
+ * Sec. 3.2). The two highest Chebyshev coefficients of g are not used
+ * (tau method). out may alias g. */
+sp_status sp_stokes_solve(sp_plan* plan, const double* g, double* out, int32_t inhomogeneous);
+
+/* Phi_dt(u) (Sec. 2, eq. befe) in the plan's precision (SP_MIXED: FP32
+ * transforms, products and y-contractions; FP64 implicit solve). out may
+ * alias u. */
+sp_status sp_befe_step(sp_plan* plan, const double* u, double* out);
+
+/* r = (Phi_dt(u) - u)/dt, FP64. If host_norm != NULL, synchronises and stores
+ * the volume-normalised L2 norm sqrt((1/V) int |r|^2 dV) there (returns
+ * SP_ERR_NONFINITE if it is NaN/Inf). r_out must not alias u. */
+sp_status sp_residual(sp_plan* plan, const double* u, double* r_out, double* host_norm);
+
+/* Volume-normalised L2 norm of a field. Synchronises. */
+sp_status sp_norm(sp_plan* plan, const double* a, double* host_norm);
+
+/* Caches the base state u (and its vorticity) used by the *_lin calls below
+ * (the linearisation point U of Sec. 2, eq. linear). */
+sp_status sp_linearize(sp_plan* plan, const double* u);
+
+/* Jacobian-vector product about the cached base state: the exact
+ * linearisation N_U(du) = du x Omega + U x curl(du) with homogeneous walls
+ * (Sec. 2, after eq. factor2). SP_OP_PHI: J_Phi du; SP_OP_RESIDUAL:
+ * (J_Phi du - du)/dt. out must not alias du. */
+sp_status sp_jvp_lin(sp_plan* plan, int32_t op, const double* du, double* out);
+/* sp_linearize(u) followed by sp_jvp_lin. */
+sp_status sp_jvp(sp_plan* plan, int32_t op, const double* u, const double* du, double* out);
+
+/* Vector-Jacobian product about the cached base state: the adjoint of the
+ * JVP in the packed Euclidean inner product (the product of the packed real
+ * vectors of sp_pack). out must not alias w. */
+sp_status sp_vjp_lin(sp_plan* plan, int32_t op, const double* w, double* out);
+sp_status sp_vjp(sp_plan* plan, int32_t op, const double* u, const double* w, double* out);
+
+/* Canonical layout <-> packed real float64 vector of length 3 ny (nx-1)(nz-1):
+ * for each component c and Chebyshev index n: the (0,0) mode (real part), the
+ * m_z = 0 modes m_x = 1..nx/2-1 as (re, im), then for m_z = 1..nz/2-1 every
+ * non-Nyquist m_x in FFT order as (re, im). sp_unpack writes the Hermitian
+ * m_z = 0 plane and zero Nyquist entries. */
+sp_status sp_pack(sp_plan* plan, const double* canonical, double* packed);
+sp_status sp_unpack(sp_plan* plan, const double* packed, double* canonical);
+
+typedef struct {
+  int32_t max_newton;   /* Newton steps (<= 64)                                 */
+  int32_t max_krylov;   /* GMRES iterations per Newton step (unrestarted)       */
+  double gmres_rtol;    /* stop GMRES when its residual <= rtol * ||r||          */
+  double newton_tol;    /* stop Newton when the L2 norm of r < newton_tol        */
+  int32_t jvp_mode;     /* 0: exact JVP; 1: finite difference [G(U+eps u)-G(U)]/eps */
+  double fd_eps;        /* relative step of jvp_mode 1 (eps = fd_eps ||U||/||u||)  */
+} sp_newton_opts;
+
+typedef struct {
+  int32_t converged, newton_iters, total_krylov, total_actions;
+  double seconds;
+  double res_norm[65];       /* L2 norm of r before each Newton step           */
+  int32_t krylov[64];        /* GMRES iterations of each Newton step           */
+  double gmres_relres[64];   /* final GMRES relative residual of each step      */
+} sp_newton_report;
+
+/* Newton-GMRES on r(U) = (Phi_dt(U) - U)/dt = 0 (Sec. 2): U <- U - du with
+ * J_r du = r solved by unrestarted GMRES (x0 = 0, classical Gram-Schmidt with
+ * reorthogonalisation, Givens rotations) in the packed Euclidean product.
+ * u_inout: initial guess in, final iterate out. Synchronises. Returns SP_OK on
+ * convergence, SP_ERR_NOT_CONVERGED otherwise (report filled either way). */
+sp_status sp_newton_gmres(sp_plan* plan, double* u_inout, const sp_newton_opts* opts,
+                          sp_newton_report* report);
+
+/* Per-kernel timing (tracing aid): when on != 0, every kernel the plan launches
+ * is bracketed by HIP events on the plan's stream, which adds a small gap
+ * between launches; leave it off for throughput measurements. */
+sp_status sp_profile_enable(sp_plan* plan, int32_t on);
+/* Synchronises, then writes for each kernel that ran since the last reset its
+ * name (names: n_max slots of 32 chars, NUL terminated), launch count and
+ * summed duration in ms; *n_out = number of kernels written. Clears the
+ * counters if reset != 0. */
+sp_status sp_profile_read(sp_plan* plan, int32_t n_max, char* names, int64_t* counts,
+                          double* total_ms, int32_t* n_out, int32_t reset);
+
+const char* sp_status_string(sp_status s);
+const char* sp_last_error(const sp_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SP_H */

@@ -1,0 +1,245 @@
+"""Stokes-preconditioned Newton-Krylov for plane Couette flow on one MI355X.
+
+Python face of libsp.so (see include/sp.h). ``Plan`` marshals torch tensors
+(complex128, canonical layout [3][nx][nz/2+1][ny], on the GPU) to the C ABI;
+``PhiFunction`` exposes Phi_dt to torch autograd on packed float64 vectors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+from . import _lib
+from ._lib import SP_FP64, SP_MIXED, SP_OP_PHI, SP_OP_RESIDUAL, SPError
+
+__all__ = ["Plan", "PhiFunction", "SPError", "SP_FP64", "SP_MIXED", "SP_OP_PHI",
+           "SP_OP_RESIDUAL", "couette_box"]
+
+
+def couette_box():
+    """The plane Couette box of the paper's Channelflow runs (Sec. 3.3)."""
+    return 2 * math.pi / 1.14, 2 * math.pi / 2.5
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Plan:
+    """A plan for one grid, Reynolds number and BEFE step dt on one GPU."""
+
+    def __init__(self, nx: int, ny: int, nz: int, lx: float, lz: float, re: float, dt: float,
+                 wall_upper: float = 1.0, wall_lower: float = -1.0, precision: int = SP_FP64,
+                 device=None):
+        torch = _torch()
+        self.lib = _lib.load()
+        dev = torch.device(device if device is not None else "cuda")
+        if dev.type != "cuda":
+            raise ValueError("Plan needs a GPU device")
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.stream = torch.cuda.current_stream(self.device)
+        prm = _lib.sp_params(nx, ny, nz, lx, lz, re, dt, wall_upper, wall_lower, precision)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = self.lib.sp_plan_create(C.byref(prm), C.c_void_p(self.stream.cuda_stream),
+                                         C.byref(h))
+        if st != 0:
+            raise SPError(st, self.lib.sp_status_string(st).decode())
+        self.h = h
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.lx, self.lz, self.re, self.dt = lx, lz, re, dt
+        self.shape = (3, nx, nz // 2 + 1, ny)
+        self.packed_n = 3 * ny * (nx - 1) * (nz - 1)
+        self._ws = None
+
+    # ------------------------------------------------------------------ helpers
+    def _check(self, st: int):
+        if st != 0:
+            msg = self.lib.sp_last_error(self.h).decode()
+            raise SPError(st, f"{self.lib.sp_status_string(st).decode()}: {msg}")
+
+    def _field(self, t, name="field"):
+        torch = _torch()
+        if t.dtype != torch.complex128 or tuple(t.shape) != self.shape:
+            raise ValueError(f"{name} must be complex128 of shape {self.shape}")
+        if t.device != self.device or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous tensor on {self.device}")
+        return C.c_void_p(t.data_ptr())
+
+    def _packed(self, t, name="packed"):
+        torch = _torch()
+        if t.dtype != torch.float64 or tuple(t.shape) != (self.packed_n,):
+            raise ValueError(f"{name} must be float64 of shape ({self.packed_n},)")
+        if t.device != self.device or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous tensor on {self.device}")
+        return C.c_void_p(t.data_ptr())
+
+    def empty(self):
+        torch = _torch()
+        return torch.empty(self.shape, dtype=torch.complex128, device=self.device)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sp_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ configuration
+    def set_dt(self, dt: float):
+        self._check(self.lib.sp_plan_set_dt(self.h, dt))
+        self.dt = dt
+
+    def set_precision(self, precision: int):
+        self._check(self.lib.sp_plan_set_precision(self.h, precision))
+
+    # ------------------------------------------------------------------ operators
+    def nonlinear(self, u, out=None):
+        out = self.empty() if out is None else out
+        self._check(self.lib.sp_nonlinear(self.h, self._field(u, "u"), self._field(out, "out")))
+        return out
+
+    def stokes_solve(self, g, out=None, inhomogeneous: bool = False):
+        out = self.empty() if out is None else out
+        self._check(self.lib.sp_stokes_solve(self.h, self._field(g, "g"), self._field(out, "out"),
+                                             1 if inhomogeneous else 0))
+        return out
+
+    def befe_step(self, u, out=None):
+        out = self.empty() if out is None else out
+        self._check(self.lib.sp_befe_step(self.h, self._field(u, "u"), self._field(out, "out")))
+        return out
+
+    def residual(self, u, out=None, norm: bool = False):
+        out = self.empty() if out is None else out
+        nrm = C.c_double(0.0)
+        self._check(self.lib.sp_residual(self.h, self._field(u, "u"), self._field(out, "out"),
+                                         C.byref(nrm) if norm else None))
+        return (out, nrm.value) if norm else out
+
+    def norm(self, a) -> float:
+        nrm = C.c_double(0.0)
+        self._check(self.lib.sp_norm(self.h, self._field(a, "a"), C.byref(nrm)))
+        return nrm.value
+
+    def linearize(self, u):
+        self._check(self.lib.sp_linearize(self.h, self._field(u, "u")))
+
+    def jvp_lin(self, du, op: int = SP_OP_PHI, out=None):
+        out = self.empty() if out is None else out
+        self._check(self.lib.sp_jvp_lin(self.h, op, self._field(du, "du"), self._field(out, "out")))
+        return out
+
+    def jvp(self, u, du, op: int = SP_OP_PHI, out=None):
+        out = self.empty() if out is None else out
+        self._check(self.lib.sp_jvp(self.h, op, self._field(u, "u"), self._field(du, "du"),
+                                    self._field(out, "out")))
+        return out
+
+    def vjp_lin(self, w, op: int = SP_OP_PHI, out=None):
+        out = self.empty() if out is None else out
+        self._check(self.lib.sp_vjp_lin(self.h, op, self._field(w, "w"), self._field(out, "out")))
+        return out
+
+    def vjp(self, u, w, op: int = SP_OP_PHI, out=None):
+        out = self.empty() if out is None else out
+        self._check(self.lib.sp_vjp(self.h, op, self._field(u, "u"), self._field(w, "w"),
+                                    self._field(out, "out")))
+        return out
+
+    def pack(self, a, out=None):
+        torch = _torch()
+        out = torch.empty(self.packed_n, dtype=torch.float64, device=self.device) \
+            if out is None else out
+        self._check(self.lib.sp_pack(self.h, self._field(a, "a"), self._packed(out, "out")))
+        return out
+
+    def unpack(self, x, out=None):
+        out = self.empty() if out is None else out
+        self._check(self.lib.sp_unpack(self.h, self._packed(x, "x"), self._field(out, "out")))
+        return out
+
+    def profile_enable(self, on: bool = True):
+        self._check(self.lib.sp_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self, reset: bool = True):
+        """{kernel name: (launches, total ms)} since the last reset (synchronises)."""
+        nmax = 64
+        names = C.create_string_buffer(32 * nmax)
+        counts = (C.c_int64 * nmax)()
+        ms = (C.c_double * nmax)()
+        n = C.c_int32(0)
+        self._check(self.lib.sp_profile_read(self.h, nmax, names, counts, ms, C.byref(n),
+                                             1 if reset else 0))
+        out = {}
+        for k in range(n.value):
+            nm = names.raw[32 * k: 32 * k + 32].split(b"\0", 1)[0].decode()
+            out[nm] = (int(counts[k]), float(ms[k]))
+        return out
+
+    def newton_gmres(self, u, max_newton: int = 5, max_krylov: int = 40,
+                     gmres_rtol: float = 1e-4, newton_tol: float = 1e-10, jvp_mode: int = 0,
+                     fd_eps: float = 1e-7):
+        """Newton-GMRES in place on u; returns the report as a dict."""
+        opts = _lib.sp_newton_opts(max_newton, max_krylov, gmres_rtol, newton_tol, jvp_mode,
+                                   fd_eps)
+        rep = _lib.sp_newton_report()
+        st = self.lib.sp_newton_gmres(self.h, self._field(u, "u"), C.byref(opts), C.byref(rep))
+        if st not in (0, _lib.SP_ERR_NOT_CONVERGED):
+            self._check(st)
+        n = rep.newton_iters
+        return {
+            "converged": bool(rep.converged),
+            "newton_iters": n,
+            "total_krylov": rep.total_krylov,
+            "total_actions": rep.total_actions,
+            "seconds": rep.seconds,
+            "res_norm": list(rep.res_norm[: n + 1]),
+            "krylov": list(rep.krylov[:n]),
+            "gmres_relres": list(rep.gmres_relres[:n]),
+        }
+
+
+def _make_phi_function():
+    torch = _torch()
+
+    class PhiFunction(torch.autograd.Function):
+        """Phi_dt on packed float64 vectors; backward is the library's VJP."""
+
+        @staticmethod
+        def forward(ctx, x, plan):
+            u = plan.unpack(x.contiguous())
+            y = plan.pack(plan.befe_step(u))
+            ctx.plan = plan
+            ctx.save_for_backward(x.detach().clone())
+            return y
+
+        @staticmethod
+        def backward(ctx, gy):
+            (x,) = ctx.saved_tensors
+            plan = ctx.plan
+            u = plan.unpack(x)
+            w = plan.unpack(gy.contiguous())
+            gx = plan.pack(plan.vjp(u, w, SP_OP_PHI))
+            return gx, None
+
+    return PhiFunction
+
+
+class _LazyPhi:
+    _fn = None
+
+    def __getattr__(self, name):
+        if _LazyPhi._fn is None:
+            _LazyPhi._fn = _make_phi_function()
+        return getattr(_LazyPhi._fn, name)
+
+
+PhiFunction = _LazyPhi()

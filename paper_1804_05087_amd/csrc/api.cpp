@@ -1,0 +1,219 @@
+// C ABI entry points: stream-ordered compositions of the kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "sp_internal.h"
+
+using namespace sp;
+
+#define SP_TRY_HIP(expr, what)                                  \
+  do {                                                          \
+    sp_status _s = hip_check(p, (expr), what);                  \
+    if (_s != SP_OK) return _s;                                 \
+  } while (0)
+
+static size_t canon_count(const sp_plan* p) {
+  return (size_t)3 * p->d.nx * p->d.nzh * p->d.ny;
+}
+
+namespace sp {
+
+// a2-a5: N(u) (or its linearisation, mode 1) into p->nv (y-valued spectral).
+static sp_status nonlinear_to_nv(sp_plan* p, const double2* u, int mode, bool fp32) {
+  SP_TRY_HIP(launch_synth_y(p, u, fp32), "synth_y");
+  SP_TRY_HIP(launch_fft_x_inv(p, fp32), "fft_x_inv");
+  SP_TRY_HIP(launch_z_product(p, mode, fp32), "z_product");
+  SP_TRY_HIP(launch_fft_x_fwd(p, fp32), "fft_x_fwd");
+  return SP_OK;
+}
+
+sp_status host_norm_of(sp_plan* p, const double2* a, double* out) {
+  int nb = 0;
+  SP_TRY_HIP(launch_norm_partial(p, a, p->partial, &nb), "norm_partial");
+  SP_TRY_HIP(hipMemcpyAsync(p->h_partial, p->partial, nb * sizeof(double), hipMemcpyDeviceToHost,
+                            p->stream),
+             "copy partials");
+  SP_TRY_HIP(hipStreamSynchronize(p->stream), "sync");
+  double s = 0.0;
+  for (int i = 0; i < nb; ++i) s += p->h_partial[i];
+  *out = std::sqrt(s);
+  if (!std::isfinite(*out)) return set_error(p, SP_ERR_NONFINITE, "norm is not finite");
+  return SP_OK;
+}
+
+sp_status befe_into(sp_plan* p, const double2* u, double2* out, bool fp32) {
+  sp_status s = nonlinear_to_nv(p, u, 0, fp32);
+  if (s) return s;
+  SP_TRY_HIP(launch_analysis_rhs(p, u, p->d.inv_dt, p->g, fp32), "analysis_rhs");
+  SP_TRY_HIP(launch_stokes_solve(p, p->g, out, 1), "stokes_solve");
+  return SP_OK;
+}
+
+sp_status residual_into(sp_plan* p, const double2* u, double2* r) {
+  sp_status s = befe_into(p, u, p->t1, false);
+  if (s) return s;
+  SP_TRY_HIP(launch_axpby(p, p->t1, p->d.inv_dt, u, -p->d.inv_dt, r, canon_count(p)), "axpby");
+  return SP_OK;
+}
+
+sp_status linearize(sp_plan* p, const double2* u) {
+  const bool fp32 = (p->precision == SP_MIXED);
+  SP_TRY_HIP(launch_synth_y(p, u, fp32), "synth_y");
+  SP_TRY_HIP(launch_fft_x_inv(p, fp32), "fft_x_inv");
+  SP_TRY_HIP(launch_z_product(p, 2, fp32), "z_product(base)");
+  p->base_valid = true;
+  return SP_OK;
+}
+
+sp_status jvp_lin(sp_plan* p, int op, const double2* du, double2* out) {
+  if (!p->base_valid) return set_error(p, SP_ERR_INVALID, "no base state: call sp_linearize");
+  const bool fp32 = (p->precision == SP_MIXED);
+  sp_status s = nonlinear_to_nv(p, du, 1, fp32);
+  if (s) return s;
+  SP_TRY_HIP(launch_analysis_rhs(p, du, p->d.inv_dt, p->g, fp32), "analysis_rhs");
+  if (op == SP_OP_PHI) {
+    SP_TRY_HIP(launch_stokes_solve(p, p->g, out, 0), "stokes_solve");
+  } else {
+    SP_TRY_HIP(launch_stokes_solve(p, p->g, p->t2, 0), "stokes_solve");
+    SP_TRY_HIP(launch_axpby(p, p->t2, p->d.inv_dt, du, -p->d.inv_dt, out, canon_count(p)),
+               "axpby");
+  }
+  return SP_OK;
+}
+
+}  // namespace sp
+
+#define CHECK_PLAN()                      \
+  do {                                    \
+    if (!p) return SP_ERR_INVALID;        \
+  } while (0)
+#define CHECK_PTR(x)                                                     \
+  do {                                                                   \
+    if (!(x)) return set_error(p, SP_ERR_INVALID, "null pointer: " #x); \
+  } while (0)
+
+extern "C" sp_status sp_nonlinear(sp_plan* p, const double* u, double* out) {
+  CHECK_PLAN();
+  CHECK_PTR(u);
+  CHECK_PTR(out);
+  if (u == out) return set_error(p, SP_ERR_INVALID, "sp_nonlinear: out aliases u");
+  sp_status s = nonlinear_to_nv(p, (const double2*)u, 0, false);
+  if (s) return s;
+  SP_TRY_HIP(launch_analysis_rhs(p, nullptr, 0.0, (double2*)out, false), "analysis_rhs");
+  return SP_OK;
+}
+
+extern "C" sp_status sp_stokes_solve(sp_plan* p, const double* g, double* out,
+                                     int32_t inhomogeneous) {
+  CHECK_PLAN();
+  CHECK_PTR(g);
+  CHECK_PTR(out);
+  const double2* src = (const double2*)g;
+  if (g == out) {
+    SP_TRY_HIP(hipMemcpyAsync(p->g, g, canon_count(p) * sizeof(double2), hipMemcpyDeviceToDevice,
+                              p->stream),
+               "copy g");
+    src = p->g;
+  }
+  SP_TRY_HIP(launch_stokes_solve(p, src, (double2*)out, inhomogeneous ? 1 : 0), "stokes_solve");
+  return SP_OK;
+}
+
+extern "C" sp_status sp_befe_step(sp_plan* p, const double* u, double* out) {
+  CHECK_PLAN();
+  CHECK_PTR(u);
+  CHECK_PTR(out);
+  return befe_into(p, (const double2*)u, (double2*)out, p->precision == SP_MIXED);
+}
+
+extern "C" sp_status sp_residual(sp_plan* p, const double* u, double* r_out, double* host_norm) {
+  CHECK_PLAN();
+  CHECK_PTR(u);
+  CHECK_PTR(r_out);
+  if (u == r_out) return set_error(p, SP_ERR_INVALID, "sp_residual: r_out aliases u");
+  sp_status s = residual_into(p, (const double2*)u, (double2*)r_out);
+  if (s) return s;
+  if (host_norm) return host_norm_of(p, (const double2*)r_out, host_norm);
+  return SP_OK;
+}
+
+extern "C" sp_status sp_norm(sp_plan* p, const double* a, double* host_norm) {
+  CHECK_PLAN();
+  CHECK_PTR(a);
+  CHECK_PTR(host_norm);
+  return host_norm_of(p, (const double2*)a, host_norm);
+}
+
+extern "C" sp_status sp_linearize(sp_plan* p, const double* u) {
+  CHECK_PLAN();
+  CHECK_PTR(u);
+  return linearize(p, (const double2*)u);
+}
+
+extern "C" sp_status sp_jvp_lin(sp_plan* p, int32_t op, const double* du, double* out) {
+  CHECK_PLAN();
+  CHECK_PTR(du);
+  CHECK_PTR(out);
+  if (op != SP_OP_PHI && op != SP_OP_RESIDUAL) return set_error(p, SP_ERR_INVALID, "bad op");
+  if (du == out) return set_error(p, SP_ERR_INVALID, "sp_jvp: out aliases du");
+  return jvp_lin(p, op, (const double2*)du, (double2*)out);
+}
+
+extern "C" sp_status sp_jvp(sp_plan* p, int32_t op, const double* u, const double* du,
+                            double* out) {
+  CHECK_PLAN();
+  CHECK_PTR(u);
+  if (du == out) return set_error(p, SP_ERR_INVALID, "sp_jvp: out aliases du");
+  sp_status s = sp_linearize(p, u);
+  if (s) return s;
+  return sp_jvp_lin(p, op, du, out);
+}
+
+extern "C" sp_status sp_pack(sp_plan* p, const double* canonical, double* packed) {
+  CHECK_PLAN();
+  CHECK_PTR(canonical);
+  CHECK_PTR(packed);
+  SP_TRY_HIP(launch_pack(p, (const double2*)canonical, packed), "pack");
+  return SP_OK;
+}
+
+extern "C" sp_status sp_unpack(sp_plan* p, const double* packed, double* canonical) {
+  CHECK_PLAN();
+  CHECK_PTR(canonical);
+  CHECK_PTR(packed);
+  SP_TRY_HIP(launch_unpack(p, packed, (double2*)canonical), "unpack");
+  return SP_OK;
+}
+
+extern "C" sp_status sp_profile_enable(sp_plan* p, int32_t on) {
+  CHECK_PLAN();
+  p->prof.on = (on != 0);
+  return SP_OK;
+}
+
+extern "C" sp_status sp_profile_read(sp_plan* p, int32_t n_max, char* names, int64_t* counts,
+                                     double* total_ms, int32_t* n_out, int32_t reset) {
+  CHECK_PLAN();
+  CHECK_PTR(n_out);
+  SP_TRY_HIP(hipStreamSynchronize(p->stream), "sync");
+  p->prof.collect();
+  int n = 0;
+  for (int k = 0; k < KID_COUNT; ++k) {
+    if (p->prof.count[k] == 0) continue;
+    if (n < n_max) {
+      if (names) {
+        std::strncpy(names + 32 * n, kernel_name(k), 31);
+        names[32 * n + 31] = 0;
+      }
+      if (counts) counts[n] = p->prof.count[k];
+      if (total_ms) total_ms[n] = p->prof.ms[k];
+    }
+    ++n;
+  }
+  *n_out = n < n_max ? n : n_max;
+  if (reset) p->prof.reset();
+  return SP_OK;
+}

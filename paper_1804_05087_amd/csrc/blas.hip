@@ -1,0 +1,128 @@
+// Device BLAS-1/2 for GMRES on canonical fields in the packed Euclidean
+// inner product: <a, b> = sum over stored entries of w (a.re b.re + a.im b.im),
+// w = 1 for m_z > 0 and for the (0,0) mode, 1/2 for the other m_z = 0 modes
+// (each stored twice, at +m_x and -m_x), 0 at Nyquist entries.
+#include <hip/hip_runtime.h>
+
+#include "sp_internal.h"
+
+namespace sp {
+
+__device__ inline double packed_weight(size_t t, int nx, int ny, int nzh) {
+  const int j = (int)((t / ny) % nzh);
+  const int i = (int)((t / ((size_t)ny * nzh)) % nx);
+  if (i == nx / 2 || j == nzh - 1) return 0.0;
+  if (j > 0) return 1.0;
+  return (i == 0) ? 1.0 : 0.5;
+}
+
+// partial[v * nb + block] = block's share of <V_v, w>, v = 0..nvec-1.
+// V is nvec contiguous canonical vectors of n complex entries.
+__global__ void __launch_bounds__(256)
+    k_multidot(const double2* __restrict__ V, int nvec, const double2* __restrict__ w,
+               double* __restrict__ partial, size_t n, int nx, int ny, int nzh) {
+  __shared__ double red[256];
+  const size_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const size_t lo = blockIdx.x * chunk;
+  const size_t hi = (lo + chunk < n) ? lo + chunk : n;
+  for (int v = 0; v < nvec; ++v) {
+    const double2* a = V + (size_t)v * n;
+    double acc = 0.0;
+    for (size_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+      const double wt = packed_weight(t, nx, ny, nzh);
+      acc += wt * (a[t].x * w[t].x + a[t].y * w[t].y);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(size_t)v * gridDim.x + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+// out[v] = sum_b partial[v * nb + b] (+ add[v] if add != NULL); one block per v.
+__global__ void __launch_bounds__(256)
+    k_reduce_rows(const double* __restrict__ partial, int nb, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int v = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += partial[(size_t)v * nb + b];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[v] = red[0];
+}
+
+// w = beta * w + alpha * sum_v h[v] V_v   (h in device memory)
+__global__ void __launch_bounds__(256)
+    k_multiaxpy(const double2* __restrict__ V, int nvec, const double* __restrict__ h,
+                double alpha, double beta, double2* __restrict__ w, size_t n) {
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
+       t += (size_t)gridDim.x * blockDim.x) {
+    double rx = 0.0, ry = 0.0;
+    for (int v = 0; v < nvec; ++v) {
+      const double c = h[v];
+      const double2 a = V[(size_t)v * n + t];
+      rx += c * a.x;
+      ry += c * a.y;
+    }
+    const double2 o = w[t];
+    w[t] = make_double2(beta * o.x + alpha * rx, beta * o.y + alpha * ry);
+  }
+}
+
+// x = s * y
+__global__ void k_scale(const double2* __restrict__ y, double s, double2* __restrict__ x,
+                        size_t n) {
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
+       t += (size_t)gridDim.x * blockDim.x)
+    x[t] = make_double2(s * y[t].x, s * y[t].y);
+}
+
+static int nblocks_for(size_t n) {
+  size_t b = (n + 255) / 256;
+  if (b > 1024) b = 1024;
+  return (int)b;
+}
+
+hipError_t launch_multidot(sp_plan* p, const double2* V, int nvec, const double2* w,
+                           double* partial, double* out, int* nb_out) {
+  const size_t n = (size_t)3 * p->d.nx * p->d.nzh * p->d.ny;
+  int nb = nblocks_for(n);
+  if (nb > 256) nb = 256;
+  SP_PROF_BEGIN(p, KID_MULTIDOT);
+  hipLaunchKernelGGL(k_multidot, dim3(nb), dim3(256), 0, p->stream, V, nvec, w, partial, n, p->d.nx,
+                     p->d.ny, p->d.nzh);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_rows, dim3(nvec), dim3(256), 0, p->stream, partial, nb, out);
+  SP_PROF_END(p, KID_MULTIDOT);
+  if (nb_out) *nb_out = nb;
+  return hipGetLastError();
+}
+
+hipError_t launch_multiaxpy(sp_plan* p, const double2* V, int nvec, const double* h, double alpha,
+                            double beta, double2* w) {
+  const size_t n = (size_t)3 * p->d.nx * p->d.nzh * p->d.ny;
+  SP_PROF_BEGIN(p, KID_MULTIAXPY);
+  hipLaunchKernelGGL(k_multiaxpy, dim3(nblocks_for(n)), dim3(256), 0, p->stream, V, nvec, h, alpha,
+                     beta, w, n);
+  SP_PROF_END(p, KID_MULTIAXPY);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(sp_plan* p, const double2* y, double s, double2* x) {
+  const size_t n = (size_t)3 * p->d.nx * p->d.nzh * p->d.ny;
+  SP_PROF_BEGIN(p, KID_SCALE);
+  hipLaunchKernelGGL(k_scale, dim3(nblocks_for(n)), dim3(256), 0, p->stream, y, s, x, n);
+  SP_PROF_END(p, KID_SCALE);
+  return hipGetLastError();
+}
+
+}  // namespace sp

@@ -1,0 +1,839 @@
+// Device kernels of the BEFE step for gfx950 (MI355X).
+//
+// Data flow of one evaluation (paper Sec. 3.2: derivatives in spectral space,
+// products on a physical grid, Chebyshev in y, Fourier in x and z):
+//
+//  canonical u [3][nx][nz/2+1][ny] (Chebyshev coefficients)
+//   --synth_y-->  yv [5][ny][nzm][nx]   values at y_j of u, du/dy, v, w, dw/dy
+//   --fft_x_inv-> xp [6][ny][px][nzm]   u, v, w, curl u: x physical (3/2 padded)
+//   --z_product-> np [3][ny][px][nzm]   z c2r (padded) . u x omega . z r2c
+//   --fft_x_fwd-> nv [3][ny][nzm][nx]   x forward FFT, truncated
+//   --analysis_rhs-> g canonical        Chebyshev coefficients + u/dt
+//   --stokes_solve-> Phi canonical      per-mode tau/influence-matrix solve (FP64)
+//
+// nzm = nz/2 (the z Nyquist mode is never stored in intermediates), px = 3nx/2,
+// pz = 3nz/2. Every kernel is templated on the real type R of the transform
+// path (double, or float for the mixed-precision Jacobian actions); the
+// implicit solve is FP64 only.
+#include <hip/hip_runtime.h>
+
+#include "solve_core.h"
+#include "sp_internal.h"
+
+namespace sp {
+
+template <typename R>
+struct V2;
+template <>
+struct V2<double> {
+  using T = double2;
+};
+template <>
+struct V2<float> {
+  using T = float2;
+};
+
+__device__ inline double2 mk(double a, double b) { return make_double2(a, b); }
+__device__ inline float2 mk(float a, float b) { return make_float2(a, b); }
+__device__ inline double2 cadd(double2 a, double2 b) { return mk(a.x + b.x, a.y + b.y); }
+__device__ inline float2 cadd(float2 a, float2 b) { return mk(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return mk(a.x - b.x, a.y - b.y); }
+__device__ inline float2 csub(float2 a, float2 b) { return mk(a.x - b.x, a.y - b.y); }
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline float2 cmul(float2 a, float2 b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cscale(double2 a, double s) { return mk(a.x * s, a.y * s); }
+__device__ inline float2 cscale(float2 a, float s) { return mk(a.x * s, a.y * s); }
+__device__ inline double2 conjc(double2 a) { return mk(a.x, -a.y); }
+__device__ inline float2 conjc(float2 a) { return mk(a.x, -a.y); }
+// s * i * a for s = +-1
+__device__ inline double2 sidot(double2 a, double s) { return mk(-s * a.y, s * a.x); }
+__device__ inline float2 sidot(float2 a, float s) { return mk(-s * a.y, s * a.x); }
+
+template <typename R>
+__device__ inline typename V2<R>::T to_r2(double2 a) {
+  return mk((R)a.x, (R)a.y);
+}
+
+// ---------------------------------------------------------------------------
+// Batched in-LDS Stockham FFT of nl lines of length P (line l at a[l*P]).
+// Mixed radix 2/3/4 with the factor list of `pl`; tw[q] = exp(-2 pi i q / P).
+// sign = -1: forward (unscaled), +1: inverse (unscaled). Returns the buffer
+// holding the result (a or b). Must be called by the whole block.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ typename V2<R>::T* lds_fft(typename V2<R>::T* a, typename V2<R>::T* b, int nl,
+                                      const FFTPlan1D& pl, const typename V2<R>::T* tw,
+                                      R sign) {
+  using C = typename V2<R>::T;
+  const int P = pl.P;
+  int Ns = 1;
+  for (int s = 0; s < pl.nrad; ++s) {
+    const int Rd = pl.rad[s];
+    const int nb = P / Rd;
+    const int tstride = P / (Ns * Rd);
+    for (int t = threadIdx.x; t < nl * nb; t += blockDim.x) {
+      const int l = t / nb;
+      const int j = t - l * nb;
+      const C* x = a + l * P;
+      C* y = b + l * P;
+      const int k = j % Ns;
+      C v[4];
+      for (int r = 0; r < Rd; ++r) v[r] = x[j + r * nb];
+      if (Ns > 1) {
+        for (int r = 1; r < Rd; ++r) {
+          C w = tw[(k * r * tstride) % P];
+          if (sign > 0) w = conjc(w);
+          v[r] = cmul(v[r], w);
+        }
+      }
+      C o[4];
+      if (Rd == 2) {
+        o[0] = cadd(v[0], v[1]);
+        o[1] = csub(v[0], v[1]);
+      } else if (Rd == 3) {
+        const R h = (R)0.86602540378443864676;  // sqrt(3)/2
+        C t1 = cadd(v[1], v[2]);
+        C d = csub(v[1], v[2]);
+        C m = csub(v[0], cscale(t1, (R)0.5));
+        C e = sidot(cscale(d, h), sign);
+        o[0] = cadd(v[0], t1);
+        o[1] = cadd(m, e);
+        o[2] = csub(m, e);
+      } else {  // 4
+        C s0 = cadd(v[0], v[2]);
+        C s1 = csub(v[0], v[2]);
+        C s2 = cadd(v[1], v[3]);
+        C s3 = sidot(csub(v[1], v[3]), sign);
+        o[0] = cadd(s0, s2);
+        o[2] = csub(s0, s2);
+        o[1] = cadd(s1, s3);
+        o[3] = csub(s1, s3);
+      }
+      const int base = (j / Ns) * Ns * Rd + k;
+      for (int r = 0; r < Rd; ++r) y[base + r * Ns] = o[r];
+    }
+    __syncthreads();
+    C* tmp = a;
+    a = b;
+    b = tmp;
+    Ns *= Rd;
+  }
+  return a;
+}
+
+// ---------------------------------------------------------------------------
+// synth_y: values at the Gauss-Lobatto points of u, du/dy, v, w, dw/dy.
+// out[f][y][kz][mx] = sum_n M_f[y][n] u[c_f][mx][kz][n], M in {T, T.D}.
+// Block: 16 mx x 16 y tile of one (field, kz).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_synth_y(const double2* __restrict__ u, const R* __restrict__ T, const R* __restrict__ TD,
+              typename V2<R>::T* __restrict__ yv, int nx, int ny, int nzh, int nzm) {
+  using C = typename V2<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  C* Us = reinterpret_cast<C*>(smem_raw);            // [16][ny]
+  R* Ms = reinterpret_cast<R*>(Us + 16 * ny);         // [16][ny]
+  const int f = blockIdx.z % 5;
+  const int kz = blockIdx.z / 5;
+  const int comp = (f < 2) ? 0 : (f == 2 ? 1 : 2);
+  const R* M = (f == 1 || f == 4) ? TD : T;
+  const int mx0 = blockIdx.x * 16;
+  const int y0 = blockIdx.y * 16;
+  for (int idx = threadIdx.x; idx < 16 * ny; idx += 256) {
+    const int ml = idx / ny;
+    const int n = idx - ml * ny;
+    const int mx = mx0 + ml;
+    C val = mk((R)0, (R)0);
+    if (mx < nx) val = to_r2<R>(u[(((size_t)comp * nx + mx) * nzh + kz) * ny + n]);
+    Us[idx] = val;
+    const int yl = ml;
+    const int yy = y0 + yl;
+    Ms[idx] = (yy < ny) ? M[(size_t)yy * ny + n] : (R)0;
+  }
+  __syncthreads();
+  const int ty = threadIdx.x / 16;
+  const int tm = threadIdx.x % 16;
+  const int yy = y0 + ty;
+  const int mx = mx0 + tm;
+  if (yy < ny && mx < nx) {
+    R ar = 0, ai = 0;
+    const C* us = Us + tm * ny;
+    const R* ms = Ms + ty * ny;
+    for (int n = 0; n < ny; ++n) {
+      const R m = ms[n];
+      ar += m * us[n].x;
+      ai += m * us[n].y;
+    }
+    yv[(((size_t)f * ny + yy) * nzm + kz) * nx + mx] = mk(ar, ai);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fft_x_inv: build u, v, w, omega_x, omega_y, omega_z lines along x from the
+// y-valued fields (multiplying by i k_x, i k_z), zero-pad to px and inverse FFT.
+// Block: (y, output field f, chunk of kc z-modes).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_fft_x_inv(const typename V2<R>::T* __restrict__ yv, typename V2<R>::T* __restrict__ xp,
+                const typename V2<R>::T* __restrict__ tw, FFTPlan1D pl, int nx, int ny, int nzm,
+                int kc, R alpha, R gamma) {
+  using C = typename V2<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  const int px = pl.P;
+  C* A = reinterpret_cast<C*>(smem_raw);
+  C* B = A + kc * px;
+  const int y = blockIdx.x;
+  const int f = blockIdx.y;
+  const int kz0 = blockIdx.z * kc;
+  const int nl = min(kc, nzm - kz0);
+  for (int t = threadIdx.x; t < nl * px; t += blockDim.x) A[t] = mk((R)0, (R)0);
+  __syncthreads();
+  const size_t fs = (size_t)ny * nzm * nx;  // field stride in yv
+  for (int t = threadIdx.x; t < nl * nx; t += blockDim.x) {
+    const int l = t / nx;
+    const int i = t - l * nx;
+    if (i == nx / 2) continue;
+    const int kz = kz0 + l;
+    const int mxv = (i < nx / 2) ? i : i - nx;
+    const int pos = (i < nx / 2) ? i : i - nx + px;
+    const size_t off = ((size_t)y * nzm + kz) * nx + i;
+    const R kxv = alpha * (R)mxv;
+    const R kzv = gamma * (R)kz;
+    C val;
+    if (f == 0) {
+      val = yv[0 * fs + off];
+    } else if (f == 1) {
+      val = yv[2 * fs + off];
+    } else if (f == 2) {
+      val = yv[3 * fs + off];
+    } else if (f == 3) {  // dw/dy - i kz v
+      val = csub(yv[4 * fs + off], sidot(cscale(yv[2 * fs + off], kzv), (R)1));
+    } else if (f == 4) {  // i kz u - i kx w
+      val = sidot(csub(cscale(yv[0 * fs + off], kzv), cscale(yv[3 * fs + off], kxv)), (R)1);
+    } else {  // i kx v - du/dy
+      val = csub(sidot(cscale(yv[2 * fs + off], kxv), (R)1), yv[1 * fs + off]);
+    }
+    A[l * px + pos] = val;
+  }
+  __syncthreads();
+  C* res = lds_fft<R>(A, B, nl, pl, tw, (R)1);
+  for (int t = threadIdx.x; t < nl * px; t += blockDim.x) {
+    const int x = t / nl;
+    const int l = t - x * nl;
+    xp[(((size_t)f * ny + y) * px + x) * nzm + kz0 + l] = res[l * px + x];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// z_product: per (y, x) z-line. Fields are paired (u,v), (w,ox), (oy,oz) into
+// complex lines a + i b of the Hermitian-extended spectra, inverse FFT gives
+// the two real lines at once. mode 0: n = u x omega; mode 1: n = du x Omega +
+// U x domega with (U, Omega) from `base`; mode 2: store the six physical
+// fields into `base`. The product is packed as (nx + i ny, nz), forward FFT,
+// unpacked and scaled by 1/(px pz).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_z_product(const typename V2<R>::T* __restrict__ xp, typename V2<R>::T* __restrict__ np,
+                R* __restrict__ base, const typename V2<R>::T* __restrict__ tw, FFTPlan1D pl,
+                int ny, int px, int nzm, int xc, int mode, R scale) {
+  using C = typename V2<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  const int pz = pl.P;
+  const int y = blockIdx.x;
+  const int x0 = blockIdx.y * xc;
+  const int nxl = min(xc, px - x0);
+  C* A = reinterpret_cast<C*>(smem_raw);
+  C* B = A + xc * 3 * pz;
+  const size_t fs = (size_t)ny * px * nzm;
+  for (int t = threadIdx.x; t < nxl * 3 * pz; t += blockDim.x) {
+    const int m = t % pz;
+    const int lj = t / pz;  // x_l * 3 + j
+    const int j = lj % 3;
+    const int xl = lj / 3;
+    const size_t off = ((size_t)y * px + (x0 + xl)) * nzm;
+    C val = mk((R)0, (R)0);
+    if (m < nzm) {
+      C a = xp[(2 * j) * fs + off + m];
+      C b = xp[(2 * j + 1) * fs + off + m];
+      if (m == 0) {
+        a.y = 0;
+        b.y = 0;
+      }
+      val = mk(a.x - b.y, a.y + b.x);
+    } else if (m > pz - nzm) {
+      const int mm = pz - m;
+      C a = conjc(xp[(2 * j) * fs + off + mm]);
+      C b = conjc(xp[(2 * j + 1) * fs + off + mm]);
+      val = mk(a.x - b.y, a.y + b.x);
+    }
+    A[t] = val;
+  }
+  __syncthreads();
+  C* res = lds_fft<R>(A, B, nxl * 3, pl, tw, (R)1);
+  C* oth = (res == A) ? B : A;
+  const size_t bs = (size_t)ny * px * pz;  // base field stride
+  for (int t = threadIdx.x; t < nxl * pz; t += blockDim.x) {
+    const int xl = t / pz;
+    const int z = t - xl * pz;
+    const C p0 = res[(xl * 3 + 0) * pz + z];
+    const C p1 = res[(xl * 3 + 1) * pz + z];
+    const C p2 = res[(xl * 3 + 2) * pz + z];
+    const R u = p0.x, v = p0.y, w = p1.x, ox = p1.y, oy = p2.x, oz = p2.y;
+    const size_t bo = ((size_t)y * px + (x0 + xl)) * pz + z;
+    R nxv, nyv, nzv;
+    if (mode == 0) {
+      nxv = v * oz - w * oy;
+      nyv = w * ox - u * oz;
+      nzv = u * oy - v * ox;
+    } else if (mode == 1) {
+      const R U = base[0 * bs + bo], V = base[1 * bs + bo], W = base[2 * bs + bo];
+      const R OX = base[3 * bs + bo], OY = base[4 * bs + bo], OZ = base[5 * bs + bo];
+      nxv = (v * OZ - w * OY) + (V * oz - W * oy);
+      nyv = (w * OX - u * OZ) + (W * ox - U * oz);
+      nzv = (u * OY - v * OX) + (U * oy - V * ox);
+    } else {
+      base[0 * bs + bo] = u;
+      base[1 * bs + bo] = v;
+      base[2 * bs + bo] = w;
+      base[3 * bs + bo] = ox;
+      base[4 * bs + bo] = oy;
+      base[5 * bs + bo] = oz;
+      continue;
+    }
+    oth[(xl * 2 + 0) * pz + z] = mk(nxv, nyv);
+    oth[(xl * 2 + 1) * pz + z] = mk(nzv, (R)0);
+  }
+  if (mode == 2) return;  // uniform across the block
+  __syncthreads();
+  C* fin = lds_fft<R>(oth, res, nxl * 2, pl, tw, (R)-1);
+  const size_t ns = (size_t)ny * px * nzm;
+  for (int t = threadIdx.x; t < nxl * nzm; t += blockDim.x) {
+    const int xl = t / nzm;
+    const int m = t - xl * nzm;
+    const C a = fin[(xl * 2 + 0) * pz + m];
+    const C am = conjc(fin[(xl * 2 + 0) * pz + (pz - m) % pz]);
+    const C cz = fin[(xl * 2 + 1) * pz + m];
+    const C sx = cscale(cadd(a, am), (R)0.5 * scale);
+    const C d = csub(a, am);  // 2 i Ny
+    const C sy = mk(d.y * (R)0.5 * scale, -d.x * (R)0.5 * scale);
+    const size_t off = ((size_t)y * px + (x0 + xl)) * nzm + m;
+    np[0 * ns + off] = sx;
+    np[1 * ns + off] = sy;
+    np[2 * ns + off] = cscale(cz, scale);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fft_x_fwd: forward FFT along x of the three product fields, truncation to
+// the kept m_x (Nyquist zero). Block: (y, component, chunk of kc z-modes).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_fft_x_fwd(const typename V2<R>::T* __restrict__ np, typename V2<R>::T* __restrict__ nv,
+                const typename V2<R>::T* __restrict__ tw, FFTPlan1D pl, int nx, int ny, int nzm,
+                int kc) {
+  using C = typename V2<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  const int px = pl.P;
+  C* A = reinterpret_cast<C*>(smem_raw);
+  C* B = A + kc * px;
+  const int y = blockIdx.x;
+  const int c = blockIdx.y;
+  const int kz0 = blockIdx.z * kc;
+  const int nl = min(kc, nzm - kz0);
+  for (int t = threadIdx.x; t < nl * px; t += blockDim.x) {
+    const int x = t / nl;
+    const int l = t - x * nl;
+    A[l * px + x] = np[(((size_t)c * ny + y) * px + x) * nzm + kz0 + l];
+  }
+  __syncthreads();
+  C* res = lds_fft<R>(A, B, nl, pl, tw, (R)-1);
+  for (int t = threadIdx.x; t < nl * nx; t += blockDim.x) {
+    const int l = t / nx;
+    const int i = t - l * nx;
+    C val = mk((R)0, (R)0);
+    if (i != nx / 2) {
+      const int pos = (i < nx / 2) ? i : i - nx + px;
+      val = res[l * px + pos];
+    }
+    nv[(((size_t)c * ny + y) * nzm + kz0 + l) * nx + i] = val;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// analysis_rhs: g[c][mx][kz][n] = sum_j Tinv[n][j] nv[c][j][kz][mx] + a x[c][mx][kz][n].
+// x may be NULL (a ignored). kz = nz/2 (Nyquist) rows get a x only.
+// Block: 16 mx x 16 n tile of one (component, kz).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_analysis_rhs(const typename V2<R>::T* __restrict__ nv, const R* __restrict__ Tinv,
+                   const double2* __restrict__ x, double a, double2* __restrict__ g, int nx, int ny,
+                   int nzh, int nzm) {
+  using C = typename V2<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  C* Ns = reinterpret_cast<C*>(smem_raw);   // [16 mx][ny]
+  R* Ts = reinterpret_cast<R*>(Ns + 16 * ny);  // [16 n][ny]
+  const int c = blockIdx.z % 3;
+  const int kz = blockIdx.z / 3;
+  const int mx0 = blockIdx.x * 16;
+  const int n0 = blockIdx.y * 16;
+  const bool nyq = (kz >= nzm);
+  if (!nyq) {
+    for (int idx = threadIdx.x; idx < 16 * ny; idx += 256) {
+      const int j = idx / 16;
+      const int ml = idx % 16;
+      const int mx = mx0 + ml;
+      Ns[ml * ny + j] =
+          (mx < nx) ? nv[(((size_t)c * ny + j) * nzm + kz) * nx + mx] : mk((R)0, (R)0);
+      const int nl = idx / ny;
+      const int jj = idx - nl * ny;
+      const int n = n0 + nl;
+      Ts[idx] = (n < ny) ? Tinv[(size_t)n * ny + jj] : (R)0;
+    }
+  }
+  __syncthreads();
+  const int tm = threadIdx.x / 16;
+  const int tn = threadIdx.x % 16;
+  const int mx = mx0 + tm;
+  const int n = n0 + tn;
+  if (mx < nx && n < ny) {
+    double rr = 0.0, ri = 0.0;
+    if (!nyq) {
+      R ar = 0, ai = 0;
+      const C* ns = Ns + tm * ny;
+      const R* ts = Ts + tn * ny;
+      for (int j = 0; j < ny; ++j) {
+        ar += ts[j] * ns[j].x;
+        ai += ts[j] * ns[j].y;
+      }
+      rr = (double)ar;
+      ri = (double)ai;
+    }
+    const size_t o = (((size_t)c * nx + mx) * nzh + kz) * ny + n;
+    if (x != nullptr) {
+      rr += a * x[o].x;
+      ri += a * x[o].y;
+    }
+    g[o] = make_double2(rr, ri);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stokes_solve: per-mode implicit solve (FP64). One 64-lane block per mode.
+// out = S(g): velocity of (1/Re) Lap phi - phi/dt - grad p = -g, div phi = 0,
+// walls (wall_upper, wall_lower) for the (0,0) mode when inhomogeneous, else 0.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64)
+    k_stokes_solve(const double2* __restrict__ g, double2* __restrict__ out,
+                   const double* __restrict__ modedata, const double* __restrict__ hw_g,
+                   int stride, int nx, int ny, int nzh, double alpha, double gamma, double re,
+                   double inv_dt, double wu, double wl, int inhomogeneous) {
+  extern __shared__ unsigned char smem_raw[];
+  const int N = ny - 1;
+  const int n1 = ny;
+  double* rec = reinterpret_cast<double*>(smem_raw);
+  double* hw = rec + stride;
+  cd* Fpar = reinterpret_cast<cd*>(hw + 3 * n1);
+  cd* Fv = Fpar + n1;
+  cd* Fperp = Fv + n1;
+  cd* A = Fperp + n1;
+  cd* divF = A + n1;
+  cd* P = divF + n1;
+  cd* W = P + n1;
+  cd* Rv = W + n1;
+  cd* V = Rv + n1;
+  cd* Rp = V + n1;
+  cd* U = Rp + n1;
+
+  const int mode = blockIdx.x;
+  const int i = mode / nzh;
+  const int j = mode - i * nzh;
+  const int tid = threadIdx.x;
+  const size_t cs = (size_t)nx * nzh * ny;  // component stride
+  const size_t mo = ((size_t)i * nzh + j) * ny;
+  const bool nyq = (i == nx / 2) || (j == nzh - 1);
+  if (nyq) {
+    for (int n = tid; n < n1; n += 64) {
+      out[mo + n] = make_double2(0.0, 0.0);
+      out[cs + mo + n] = make_double2(0.0, 0.0);
+      out[2 * cs + mo + n] = make_double2(0.0, 0.0);
+    }
+    return;
+  }
+  const double* src = modedata + (size_t)mode * stride;
+  for (int t = tid; t < stride; t += 64) rec[t] = src[t];
+  for (int t = tid; t < 3 * n1; t += 64) hw[t] = hw_g[t];
+  const int mxv = (i < nx / 2) ? i : i - nx;
+  const double kx = alpha * mxv;
+  const double kz = gamma * j;
+  const double k2 = kx * kx + kz * kz;
+  const bool mean = (i == 0 && j == 0);
+  const double k = sqrt(k2);
+  const double lam = k2 + re * inv_dt;
+  for (int n = tid; n < n1; n += 64) {
+    cd fu, fv, fw;
+    if (n <= N - 2) {
+      const double2 a = g[mo + n];
+      const double2 b = g[cs + mo + n];
+      const double2 c = g[2 * cs + mo + n];
+      fu = cd(re * a.x, re * a.y);
+      fv = cd(re * b.x, re * b.y);
+      fw = cd(re * c.x, re * c.y);
+    }
+    if (mean) {
+      Fpar[n] = fu;
+      Fperp[n] = fw;
+      Fv[n] = cd(0.0);
+    } else {
+      Fpar[n] = (fu * kx + fw * kz) * (1.0 / k);
+      Fperp[n] = (fu * kz - fw * kx) * (1.0 / k);
+      Fv[n] = fv;
+    }
+    A[n] = cd(0.0);
+    W[n] = cd(0.0);
+  }
+  __syncthreads();
+  const int n1r = n1;
+  const ModeLayout L{n1r};
+  SweepView helm(rec + L.helm(), n1);
+  SweepView pois(rec + L.pois(), n1);
+  if (tid < 2) {
+    if (mean) {
+      const int p = tid;
+      cd bu(0.0);
+      if (inhomogeneous) bu = cd(p == 0 ? 0.5 * (wu + wl) : 0.5 * (wu - wl));
+      for (int n = p; n <= N; n += 2) {
+        Rv[n] = -Fpar[n];
+        Rp[n] = -Fperp[n];
+      }
+      sweep_solve<cd>(helm, hw, N, p, Rv, bu, P, W);
+      sweep_solve<cd>(helm, hw, N, p, Rp, cd(0.0), U, W);
+    } else {
+      const int pv = tid;
+      const int po = 1 - pv;
+      deriv_parity<cd>(N, pv, Fv, A);
+      for (int n = po; n <= N; n += 2) divF[n] = mul_i(Fpar[n] * k) + A[n];
+      sweep_solve<cd>(pois, hw, N, po, divF, cd(0.0), P, W);
+      deriv_parity<cd>(N, po, P, A);
+      for (int n = pv; n <= N; n += 2) Rv[n] = A[n] - Fv[n];
+      sweep_solve<cd>(helm, hw, N, pv, Rv, cd(0.0), V, W);
+      cd la(0.0);
+      for (int n = pv; n <= N; n += 2) la = la + V[n] * ((double)n * n);
+      const int m = (N % 2 == pv) ? N : N - 1;
+      cd lb = V[m] * lam;
+      if (m == N - 1) lb = lb + P[N] * (2.0 * N);
+      const double* Mi = rec + L.minv() + 4 * pv;
+      const cd ca = -(la * Mi[0] + lb * Mi[1]);
+      const cd cb = -(la * Mi[2] + lb * Mi[3]);
+      const double* vdel = rec + L.vdel();
+      const double* vb = rec + L.vb();
+      for (int n = pv; n <= N; n += 2) V[n] = V[n] + ca * vdel[n] + cb * vb[n];
+      deriv_parity<cd>(N, pv, V, A);
+      for (int n = po; n <= N; n += 2) Rp[n] = -Fperp[n];
+      sweep_solve<cd>(helm, hw, N, po, Rp, cd(0.0), U, W);
+    }
+  }
+  __syncthreads();
+  for (int n = tid; n < n1; n += 64) {
+    cd uo, vo, wo;
+    if (mean) {
+      uo = P[n];
+      wo = U[n];
+    } else {
+      const cd upar = mul_i(A[n]) * (1.0 / k);
+      uo = (upar * kx + U[n] * kz) * (1.0 / k);
+      wo = (upar * kz - U[n] * kx) * (1.0 / k);
+      vo = V[n];
+    }
+    out[mo + n] = make_double2(uo.re, uo.im);
+    out[cs + mo + n] = make_double2(vo.re, vo.im);
+    out[2 * cs + mo + n] = make_double2(wo.re, wo.im);
+  }
+}
+
+// out = a x + b y (x or y may be NULL, meaning zero)
+__global__ void k_axpby(const double2* __restrict__ x, double a, const double2* __restrict__ y,
+                        double b, double2* __restrict__ out, size_t n) {
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
+       t += (size_t)gridDim.x * blockDim.x) {
+    double rx = 0, ix = 0;
+    if (x) {
+      rx = a * x[t].x;
+      ix = a * x[t].y;
+    }
+    if (y) {
+      rx += b * y[t].x;
+      ix += b * y[t].y;
+    }
+    out[t] = make_double2(rx, ix);
+  }
+}
+
+// Per-block partial sums of (1/2) sum_modes w_m sum_c a^H G a (volume-normalised
+// squared L2 norm), w_m = 1 (m_z = 0) or 2 (m_z > 0), Nyquist excluded, with the
+// Chebyshev Gram matrix G_nm = int T_n T_m dy = 1/(1-(n+m)^2) + 1/(1-(n-m)^2)
+// for n + m even (0 otherwise) evaluated on the fly.
+__global__ void __launch_bounds__(256)
+    k_norm_partial(const double2* __restrict__ a, double* __restrict__ partial, int nx, int ny,
+                   int nzh) {
+  __shared__ double red[256];
+  const int ncol = 3 * nx * nzh;
+  double acc = 0.0;
+  for (int col = blockIdx.x * blockDim.x + threadIdx.x; col < ncol;
+       col += gridDim.x * blockDim.x) {
+    const int j = col % nzh;
+    const int i = (col / nzh) % nx;
+    if (i == nx / 2 || j == nzh - 1) continue;
+    const double2* v = a + (size_t)col * ny;
+    double s = 0.0;
+    for (int n = 0; n < ny; ++n) {
+      double tr = 0.0, ti = 0.0;
+      for (int m = (n & 1); m < ny; m += 2) {
+        const double sp = (double)(n + m), dm = (double)(n - m);
+        const double gnm = 1.0 / (1.0 - sp * sp) + 1.0 / (1.0 - dm * dm);
+        tr += gnm * v[m].x;
+        ti += gnm * v[m].y;
+      }
+      s += v[n].x * tr + v[n].y * ti;
+    }
+    acc += (j == 0 ? 1.0 : 2.0) * s;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = 0.5 * red[0];
+}
+
+// Packed real vector <-> canonical (see sp.h for the order).
+__global__ void k_pack(const double2* __restrict__ c, double* __restrict__ packed, int nx, int ny,
+                       int nzh) {
+  const int nz = 2 * (nzh - 1);
+  const int per_n = (nx - 1) * (nz - 1);  // reals per (component, n)
+  const int total = 3 * ny * per_n;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    const int cn = t / per_n;
+    const int r = t - cn * per_n;
+    const int comp = cn / ny;
+    const int n = cn - comp * ny;
+    int i, j, part;
+    if (r == 0) {
+      i = 0; j = 0; part = 0;
+    } else if (r < 1 + 2 * (nx / 2 - 1)) {
+      const int q = r - 1;
+      i = 1 + q / 2; j = 0; part = q & 1;
+    } else {
+      const int q = r - 1 - 2 * (nx / 2 - 1);
+      const int mi = q / 2;  // index over (j - 1, i without Nyquist)
+      part = q & 1;
+      j = 1 + mi / (nx - 1);
+      int ii = mi % (nx - 1);
+      i = (ii < nx / 2) ? ii : ii + 1;
+    }
+    const double2 v = c[(((size_t)comp * nx + i) * nzh + j) * ny + n];
+    packed[t] = part ? v.y : v.x;
+  }
+}
+
+__global__ void k_unpack(const double* __restrict__ packed, double2* __restrict__ c, int nx,
+                         int ny, int nzh) {
+  const int nz = 2 * (nzh - 1);
+  const size_t total = (size_t)3 * nx * nzh * ny;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * blockDim.x) {
+    const int n = t % ny;
+    const int j = (t / ny) % nzh;
+    const int i = (t / ((size_t)ny * nzh)) % nx;
+    const int comp = t / ((size_t)ny * nzh * nx);
+    const size_t cbase = ((size_t)comp * ny + n) * (size_t)((nx - 1) * (nz - 1));
+    double2 v = make_double2(0.0, 0.0);
+    if (i != nx / 2 && j != nzh - 1) {
+      if (j == 0) {
+        if (i == 0) {
+          v = make_double2(packed[cbase], 0.0);
+        } else {
+          const int ip = (i < nx / 2) ? i : nx - i;
+          const size_t o = cbase + 1 + 2 * (ip - 1);
+          v = make_double2(packed[o], packed[o + 1]);
+          if (i > nx / 2) v.y = -v.y;
+        }
+      } else {
+        const int ii = (i < nx / 2) ? i : i - 1;
+        const size_t o = cbase + 1 + 2 * (nx / 2 - 1) + 2 * ((size_t)(j - 1) * (nx - 1) + ii);
+        v = make_double2(packed[o], packed[o + 1]);
+      }
+    }
+    c[t] = v;
+  }
+}
+
+// ----------------------------------- launchers -----------------------------------
+
+static int chunk_for(int P, int total, size_t elem) {
+  // largest chunk whose two ping-pong buffers fit in 64 KiB of LDS
+  int k = (int)((64 * 1024) / (2 * P * elem));
+  if (k < 1) k = 1;
+  if (k > total) k = total;
+  return k;
+}
+
+hipError_t launch_synth_y(sp_plan* p, const double2* u, bool fp32) {
+  const Dims& d = p->d;
+  dim3 grid((d.nx + 15) / 16, (d.ny + 15) / 16, d.nzm * 5);
+  SP_PROF_BEGIN(p, KID_SYNTH_Y);
+  if (fp32) {
+    size_t sh = 16 * d.ny * (sizeof(float2) + sizeof(float));
+    hipLaunchKernelGGL(k_synth_y<float>, grid, dim3(256), sh, p->stream, u, p->f_T, p->f_TD,
+                       (float2*)p->yv, d.nx, d.ny, d.nzh, d.nzm);
+  } else {
+    size_t sh = 16 * d.ny * (sizeof(double2) + sizeof(double));
+    hipLaunchKernelGGL(k_synth_y<double>, grid, dim3(256), sh, p->stream, u, p->d_T, p->d_TD,
+                       (double2*)p->yv, d.nx, d.ny, d.nzh, d.nzm);
+  }
+  SP_PROF_END(p, KID_SYNTH_Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_x_inv(sp_plan* p, bool fp32) {
+  const Dims& d = p->d;
+  const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
+  const int kc = chunk_for(d.px, d.nzm, el);
+  dim3 grid(d.ny, 6, (d.nzm + kc - 1) / kc);
+  const size_t sh = 2 * (size_t)kc * d.px * el;
+  SP_PROF_BEGIN(p, KID_FFT_X_INV);
+  if (fp32)
+    hipLaunchKernelGGL(k_fft_x_inv<float>, grid, dim3(256), sh, p->stream, (const float2*)p->yv,
+                       (float2*)p->xp, p->f_twx, p->fx, d.nx, d.ny, d.nzm, kc, (float)d.alpha,
+                       (float)d.gamma);
+  else
+    hipLaunchKernelGGL(k_fft_x_inv<double>, grid, dim3(256), sh, p->stream, (const double2*)p->yv,
+                       (double2*)p->xp, p->d_twx, p->fx, d.nx, d.ny, d.nzm, kc, d.alpha, d.gamma);
+  SP_PROF_END(p, KID_FFT_X_INV);
+  return hipGetLastError();
+}
+
+hipError_t launch_z_product(sp_plan* p, int mode, bool fp32) {
+  const Dims& d = p->d;
+  const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
+  int xc = (int)((64 * 1024) / (2 * 3 * d.pz * el));
+  if (xc < 1) xc = 1;
+  if (xc > d.px) xc = d.px;
+  dim3 grid(d.ny, (d.px + xc - 1) / xc);
+  const size_t sh = 2 * (size_t)xc * 3 * d.pz * el;
+  const double scale = 1.0 / ((double)d.px * d.pz);
+  SP_PROF_BEGIN(p, KID_Z_PRODUCT);
+  if (fp32)
+    hipLaunchKernelGGL(k_z_product<float>, grid, dim3(256), sh, p->stream, (const float2*)p->xp,
+                       (float2*)p->np, p->base32, p->f_twz, p->fz, d.ny, d.px, d.nzm, xc, mode,
+                       (float)scale);
+  else
+    hipLaunchKernelGGL(k_z_product<double>, grid, dim3(256), sh, p->stream, (const double2*)p->xp,
+                       (double2*)p->np, p->base, p->d_twz, p->fz, d.ny, d.px, d.nzm, xc, mode,
+                       scale);
+  SP_PROF_END(p, KID_Z_PRODUCT);
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_x_fwd(sp_plan* p, bool fp32) {
+  const Dims& d = p->d;
+  const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
+  const int kc = chunk_for(d.px, d.nzm, el);
+  dim3 grid(d.ny, 3, (d.nzm + kc - 1) / kc);
+  const size_t sh = 2 * (size_t)kc * d.px * el;
+  SP_PROF_BEGIN(p, KID_FFT_X_FWD);
+  if (fp32)
+    hipLaunchKernelGGL(k_fft_x_fwd<float>, grid, dim3(256), sh, p->stream, (const float2*)p->np,
+                       (float2*)p->nv, p->f_twx, p->fx, d.nx, d.ny, d.nzm, kc);
+  else
+    hipLaunchKernelGGL(k_fft_x_fwd<double>, grid, dim3(256), sh, p->stream, (const double2*)p->np,
+                       (double2*)p->nv, p->d_twx, p->fx, d.nx, d.ny, d.nzm, kc);
+  SP_PROF_END(p, KID_FFT_X_FWD);
+  return hipGetLastError();
+}
+
+hipError_t launch_analysis_rhs(sp_plan* p, const double2* x, double a, double2* g, bool fp32) {
+  const Dims& d = p->d;
+  dim3 grid((d.nx + 15) / 16, (d.ny + 15) / 16, d.nzh * 3);
+  SP_PROF_BEGIN(p, KID_ANALYSIS);
+  if (fp32) {
+    size_t sh = 16 * d.ny * (sizeof(float2) + sizeof(float));
+    hipLaunchKernelGGL(k_analysis_rhs<float>, grid, dim3(256), sh, p->stream,
+                       (const float2*)p->nv, p->f_Tinv, x, a, g, d.nx, d.ny, d.nzh, d.nzm);
+  } else {
+    size_t sh = 16 * d.ny * (sizeof(double2) + sizeof(double));
+    hipLaunchKernelGGL(k_analysis_rhs<double>, grid, dim3(256), sh, p->stream,
+                       (const double2*)p->nv, p->d_Tinv, x, a, g, d.nx, d.ny, d.nzh, d.nzm);
+  }
+  SP_PROF_END(p, KID_ANALYSIS);
+  return hipGetLastError();
+}
+
+hipError_t launch_stokes_solve(sp_plan* p, const double2* g, double2* out, int inhomogeneous) {
+  const Dims& d = p->d;
+  const size_t sh = (size_t)p->mode_stride * sizeof(double) + 3 * (size_t)d.ny * sizeof(double) +
+                    11 * (size_t)d.ny * sizeof(cd);
+  SP_PROF_BEGIN(p, KID_SOLVE);
+  hipLaunchKernelGGL(k_stokes_solve, dim3(d.nx * d.nzh), dim3(64), sh, p->stream, g, out,
+                     p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh, d.alpha, d.gamma, d.re,
+                     d.inv_dt, d.wall_upper, d.wall_lower, inhomogeneous);
+  SP_PROF_END(p, KID_SOLVE);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(sp_plan* p, const double2* x, double a, const double2* y, double b,
+                        double2* out, size_t n) {
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  SP_PROF_BEGIN(p, KID_AXPBY);
+  hipLaunchKernelGGL(k_axpby, dim3(blocks), dim3(256), 0, p->stream, x, a, y, b, out, n);
+  SP_PROF_END(p, KID_AXPBY);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_partial(sp_plan* p, const double2* a, double* partial, int* nblocks) {
+  const Dims& d = p->d;
+  const int ncol = 3 * d.nx * d.nzh;
+  int blocks = (ncol + 255) / 256;
+  if (blocks > p->npartial) blocks = p->npartial;
+  SP_PROF_BEGIN(p, KID_NORM);
+  hipLaunchKernelGGL(k_norm_partial, dim3(blocks), dim3(256), 0, p->stream, a, partial, d.nx,
+                     d.ny, d.nzh);
+  *nblocks = blocks;
+  SP_PROF_END(p, KID_NORM);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(sp_plan* p, const double2* c, double* packed) {
+  const Dims& d = p->d;
+  const int total = 3 * d.ny * (d.nx - 1) * (d.nz - 1);
+  int blocks = (total + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  SP_PROF_BEGIN(p, KID_PACK);
+  hipLaunchKernelGGL(k_pack, dim3(blocks), dim3(256), 0, p->stream, c, packed, d.nx, d.ny, d.nzh);
+  SP_PROF_END(p, KID_PACK);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(sp_plan* p, const double* packed, double2* c) {
+  const Dims& d = p->d;
+  const size_t total = (size_t)3 * d.nx * d.nzh * d.ny;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  SP_PROF_BEGIN(p, KID_UNPACK);
+  hipLaunchKernelGGL(k_unpack, dim3(blocks), dim3(256), 0, p->stream, packed, c, d.nx, d.ny,
+                     d.nzh);
+  SP_PROF_END(p, KID_UNPACK);
+  return hipGetLastError();
+}
+
+}  // namespace sp

@@ -1,0 +1,133 @@
+// Internal definitions shared by the host code and the kernels of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sp.h"
+#include "prof.h"
+
+namespace sp {
+
+// Per-mode record of the implicit-solve data (doubles), for one Fourier mode.
+// Offsets in units of doubles; n1 = N + 1.
+//   [0      , 4 n1 + 2) Helmholtz (D^2 - lam) sweep data, lam = k^2 + Re/dt
+//   [4n1 + 2, 8 n1 + 4) Poisson   (D^2 - k^2) sweep data (unused for (0,0))
+//   [8n1 + 4, 9 n1 + 4) influence basis v_delta (even n: class 0, odd n: class 1)
+//   [9n1 + 4,10 n1 + 4) influence basis v_b
+//   [10n1 + 4,10n1 + 12) 2x2 inverse influence matrices of class 0 and class 1
+// Each sweep block: inv_den[n1], cc[n1], q[n1], Q[n1], inv_sum_q[2].
+struct ModeLayout {
+  int n1;
+  __host__ __device__ int helm() const { return 0; }
+  __host__ __device__ int pois() const { return 4 * n1 + 2; }
+  __host__ __device__ int vdel() const { return 8 * n1 + 4; }
+  __host__ __device__ int vb() const { return 9 * n1 + 4; }
+  __host__ __device__ int minv() const { return 10 * n1 + 4; }
+  __host__ __device__ int stride() const { return ((10 * n1 + 12) + 1) / 2 * 2; }
+};
+
+struct FFTPlan1D {
+  int P = 0;
+  int nrad = 0;
+  int rad[12] = {0};
+};
+
+struct Dims {
+  int nx, ny, nz, N, nzh, nzm, px, pz;
+  double alpha, gamma, re, dt, inv_dt, wall_upper, wall_lower;
+};
+
+}  // namespace sp
+
+struct sp_plan {
+  sp_params prm;
+  sp::Dims d;
+  hipStream_t stream = nullptr;
+  int precision = SP_FP64;
+  std::string last_error;
+
+  // constant operator data (device)
+  double* d_T = nullptr;      // [ny][ny] synthesis T[j][n] = T_n(y_j)
+  double* d_TD = nullptr;     // [ny][ny] T . D (values of d/dy)
+  double* d_Tinv = nullptr;   // [ny][ny] analysis
+  double* d_G = nullptr;      // [ny][ny] Gram matrix int T_n T_m
+  double* d_hw = nullptr;     // [3][ny] Helmholtz right-hand-side weights
+  double* d_mode = nullptr;   // per-mode solve records
+  int mode_stride = 0;
+  double2* d_twx = nullptr;   // [px] exp(-2 pi i k / px)
+  double2* d_twz = nullptr;   // [pz]
+  float2* f_twx = nullptr;
+  float2* f_twz = nullptr;
+  float* f_T = nullptr;
+  float* f_TD = nullptr;
+  float* f_Tinv = nullptr;
+  sp::FFTPlan1D fx, fz;
+
+  // scratch (device)
+  void* d_scratch = nullptr;
+  size_t scratch_bytes = 0;
+  void* yv = nullptr;         // [5][ny][nzm][nx] complex (real type of the path)
+  void* xp = nullptr;         // [6][ny][px][nzm] complex
+  void* np = nullptr;         // [3][ny][px][nzm] complex
+  void* nv = nullptr;         // [3][ny][nzm][nx] complex
+  double2* g = nullptr;       // canonical rhs
+  double2* t1 = nullptr;      // canonical temporaries
+  double2* t2 = nullptr;
+  double2* t3 = nullptr;
+  double* base = nullptr;     // [6][ny][px][pz] physical U, Omega (FP64)
+  float* base32 = nullptr;    // same, FP32 copy for the mixed path
+  double* partial = nullptr;  // reduction partials
+  double* h_partial = nullptr;  // pinned host mirror
+  int npartial = 0;
+  bool base_valid = false;
+
+  sp::Profiler prof;
+
+  // Krylov workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+};
+
+namespace sp {
+
+// host helpers (plan.cpp)
+sp_status set_error(sp_plan* p, sp_status s, const std::string& msg);
+sp_status hip_check(sp_plan* p, hipError_t e, const char* what);
+sp_status build_mode_data(sp_plan* p);
+
+// kernel launchers (kernels.hip); all enqueue on p->stream
+hipError_t launch_synth_y(sp_plan* p, const double2* u, bool fp32);
+hipError_t launch_fft_x_inv(sp_plan* p, bool fp32);
+// mode 0: u x omega ; 1: linearised du x Omega + U x dw (needs base) ;
+// 2: store U, Omega into base (no product) ; 3: adjoint (see kernels.hip)
+hipError_t launch_z_product(sp_plan* p, int mode, bool fp32);
+hipError_t launch_fft_x_fwd(sp_plan* p, bool fp32);
+hipError_t launch_analysis_rhs(sp_plan* p, const double2* x, double a, double2* g, bool fp32);
+hipError_t launch_stokes_solve(sp_plan* p, const double2* g, double2* out, int inhomogeneous);
+hipError_t launch_axpby(sp_plan* p, const double2* x, double a, const double2* y, double b,
+                        double2* out, size_t n);
+hipError_t launch_norm_partial(sp_plan* p, const double2* a, double* partial, int* nblocks);
+hipError_t launch_pack(sp_plan* p, const double2* c, double* packed);
+hipError_t launch_unpack(sp_plan* p, const double* packed, double2* c);
+
+// GMRES BLAS (blas.hip)
+hipError_t launch_multidot(sp_plan* p, const double2* V, int nvec, const double2* w,
+                           double* partial, double* out, int* nb_out);
+hipError_t launch_multiaxpy(sp_plan* p, const double2* V, int nvec, const double* h, double alpha,
+                            double beta, double2* w);
+hipError_t launch_scale(sp_plan* p, const double2* y, double s, double2* x);
+constexpr int kMultidotBlocks = 256;
+
+// compositions (api.cpp)
+sp_status host_norm_of(sp_plan* p, const double2* a, double* out);
+sp_status befe_into(sp_plan* p, const double2* u, double2* out, bool fp32);
+sp_status residual_into(sp_plan* p, const double2* u, double2* r);
+sp_status linearize(sp_plan* p, const double2* u);
+sp_status jvp_lin(sp_plan* p, int op, const double2* du, double2* out);
+sp_status vjp_lin(sp_plan* p, int op, const double2* w, double2* out);
+
+}  // namespace sp
