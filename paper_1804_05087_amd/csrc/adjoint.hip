@@ -1,24 +1,453 @@
-// Vector-Jacobian products (placeholder until the adjoint kernels land).
+// Vector-Jacobian products: the adjoint of the linearised BEFE step.
+//
+// With S_0 the homogeneous implicit solve and N_U(du) = du x Omega + U x curl(du),
+// J_Phi du = S_0(du/dt + N_U du). Its adjoint in the Parseval inner product
+// <a, b> = sum over stored modes of w_m Re(conj(a) . b) (w_m = 1 for m_z = 0,
+// 2 for m_z > 0) is
+//   J_Phi^+ w = a/dt + N_U^+ a,  a = S_0^+ w,
+// where every stage is replaced by its adjoint in reverse order:
+//   S_0^+        : per mode, the transposed influence-matrix/tau solve (FP64)
+//   analysis^+   : Tinv^T along y
+//   truncate+FFT^+ : zero-pad + inverse FFT (scaled by 1/(px pz))
+//   product^+    : du_bar = Omega x lam, dw_bar = lam x U (physical space)
+//   pad+iFFT^+   : forward FFT + truncation
+//   curl/synth^+ : conj(i k) factors and T^T, (T.D)^T along y.
+// The packed-Euclidean adjoint used by GMRES and autograd follows by scaling
+// the (0,0) mode (counted once in the packed vector, its Parseval weight is 1
+// while every other stored mode carries half of a conjugate pair).
 #include <hip/hip_runtime.h>
 
+#include "device_common.h"
+#include "solve_core.h"
 #include "sp_internal.h"
 
 namespace sp {
-sp_status vjp_lin(sp_plan* p, int op, const double2* w, double2* out) {
-  (void)op; (void)w; (void)out;
-  return set_error(p, SP_ERR_INVALID, "vjp not available");
+
+// ---------------------------------------------------------------------------
+// stokes_solve_adj: out = S_0^+ w per mode (conjugate transpose of the solve
+// with homogeneous walls). One 64-lane block per mode; lanes 0 and 1 run the
+// two parity classes, the other lanes help with the elementwise parts.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64)
+    k_stokes_solve_adj(const double2* __restrict__ w, double2* __restrict__ out,
+                       const double* __restrict__ modedata, const double* __restrict__ hw_g,
+                       int stride, int nx, int ny, int nzh, double alpha, double gamma, double re,
+                       double inv_dt) {
+  extern __shared__ unsigned char smem_raw[];
+  const int N = ny - 1;
+  const int n1 = ny;
+  double* rec = reinterpret_cast<double*>(smem_raw);
+  double* hw = rec + stride;
+  cd* Upb = reinterpret_cast<cd*>(hw + 3 * n1);  // adjoint of u_par
+  cd* Ub = Upb + n1;                              // adjoint of u_perp
+  cd* Vb = Ub + n1;                               // adjoint of v
+  cd* A = Vb + n1;
+  cd* Tm = A + n1;
+  cd* W = Tm + n1;
+  cd* Rb = W + n1;
+  cd* Pb = Rb + n1;
+  cd* Db = Pb + n1;
+  cd* Fpb = Db + n1;
+  cd* Fpp = Fpb + n1;
+  cd* Fvb = Fpp + n1;
+
+  const int mode = blockIdx.x;
+  const int i = mode / nzh;
+  const int j = mode - i * nzh;
+  const int tid = threadIdx.x;
+  const size_t cs = (size_t)nx * nzh * ny;
+  const size_t mo = ((size_t)i * nzh + j) * ny;
+  const bool nyq = (i == nx / 2) || (j == nzh - 1);
+  if (nyq) {
+    for (int n = tid; n < n1; n += 64) {
+      out[mo + n] = make_double2(0.0, 0.0);
+      out[cs + mo + n] = make_double2(0.0, 0.0);
+      out[2 * cs + mo + n] = make_double2(0.0, 0.0);
+    }
+    return;
+  }
+  const double* src = modedata + (size_t)mode * stride;
+  for (int t = tid; t < stride; t += 64) rec[t] = src[t];
+  for (int t = tid; t < 3 * n1; t += 64) hw[t] = hw_g[t];
+  const int mxv = (i < nx / 2) ? i : i - nx;
+  const double kx = alpha * mxv;
+  const double kz = gamma * j;
+  const double k2 = kx * kx + kz * kz;
+  const bool mean = (i == 0 && j == 0);
+  const double k = sqrt(k2);
+  const double lam = k2 + re * inv_dt;
+  for (int n = tid; n < n1; n += 64) {
+    const double2 a = w[mo + n];
+    const double2 b = w[cs + mo + n];
+    const double2 c = w[2 * cs + mo + n];
+    const cd ub(a.x, a.y), vb(b.x, b.y), wb(c.x, c.y);
+    if (mean) {
+      Upb[n] = ub;
+      Ub[n] = wb;
+    } else {
+      Upb[n] = (ub * kx + wb * kz) * (1.0 / k);
+      Ub[n] = (ub * kz - wb * kx) * (1.0 / k);
+    }
+    Vb[n] = vb;
+    Pb[n] = cd(0.0);
+    Fvb[n] = cd(0.0);
+    Fpb[n] = cd(0.0);
+    Fpp[n] = cd(0.0);
+  }
+  __syncthreads();
+  const ModeLayout L{n1};
+  SweepView helm(rec + L.helm(), n1);
+  SweepView pois(rec + L.pois(), n1);
+  if (tid < 2) {
+    if (mean) {
+      const int p = tid;
+      sweep_solve_T<cd>(helm, hw, N, p, Upb, Rb, W);
+      for (int n = p; n <= N; n += 2) Fpb[n] = -Rb[n];
+      sweep_solve_T<cd>(helm, hw, N, p, Ub, Rb, W);
+      for (int n = p; n <= N; n += 2) Fpp[n] = -Rb[n];
+    } else {
+      const int pv = tid;
+      const int po = 1 - pv;
+      // u_perp = H(-F_perp)
+      sweep_solve_T<cd>(helm, hw, N, po, Ub, Rb, W);
+      for (int n = po; n <= N; n += 2) Fpp[n] = -Rb[n];
+      // u_par = i D v / k
+      for (int n = po; n <= N; n += 2) A[n] = mul_i(-Upb[n]) * (1.0 / k);
+      deriv_T_parity<cd>(N, po, A, Tm);
+      for (int n = pv; n <= N; n += 2) Vb[n] = Vb[n] + Tm[n];
+      // v = v_p + c_delta v_delta + c_b v_b, (c_delta, c_b) = -Minv (l_a, l_b)
+      const double* vdel = rec + L.vdel();
+      const double* vbs = rec + L.vb();
+      cd ca(0.0), cbb(0.0);
+      for (int n = pv; n <= N; n += 2) {
+        ca = ca + Vb[n] * vdel[n];
+        cbb = cbb + Vb[n] * vbs[n];
+      }
+      const double* Mi = rec + L.minv() + 4 * pv;
+      const cd la = -(ca * Mi[0] + cbb * Mi[2]);
+      const cd lb = -(ca * Mi[1] + cbb * Mi[3]);
+      for (int n = pv; n <= N; n += 2) Vb[n] = Vb[n] + la * ((double)n * n);
+      const int m = (N % 2 == pv) ? N : N - 1;
+      Vb[m] = Vb[m] + lb * lam;
+      if (m == N - 1) Pb[N] = Pb[N] + lb * (2.0 * N);
+      // v_p = H(D P - F_v)
+      sweep_solve_T<cd>(helm, hw, N, pv, Vb, Rb, W);
+      for (int n = pv; n <= N; n += 2) Fvb[n] = -Rb[n];
+      deriv_T_parity<cd>(N, pv, Rb, Tm);
+      for (int n = po; n <= N; n += 2) Pb[n] = Pb[n] + Tm[n];
+      // P = Pois(div F), div F = i k F_par + D F_v
+      sweep_solve_T<cd>(pois, hw, N, po, Pb, Db, W);
+      for (int n = po; n <= N; n += 2) Fpb[n] = mul_i(-Db[n]) * k;
+      deriv_T_parity<cd>(N, po, Db, Tm);
+      for (int n = pv; n <= N; n += 2) Fvb[n] = Fvb[n] + Tm[n];
+    }
+  }
+  __syncthreads();
+  for (int n = tid; n < n1; n += 64) {
+    cd gu, gv, gw;
+    if (n <= N - 2) {
+      if (mean) {
+        gu = Fpb[n] * re;
+        gw = Fpp[n] * re;
+      } else {
+        gu = (Fpb[n] * kx + Fpp[n] * kz) * (re / k);
+        gw = (Fpb[n] * kz - Fpp[n] * kx) * (re / k);
+        gv = Fvb[n] * re;
+      }
+    }
+    out[mo + n] = make_double2(gu.re, gu.im);
+    out[cs + mo + n] = make_double2(gv.re, gv.im);
+    out[2 * cs + mo + n] = make_double2(gw.re, gw.im);
+  }
 }
+
+// ---------------------------------------------------------------------------
+// adj_z: per (y, x) z-line, in place on xp. Reads the three adjoint product
+// fields lam (z spectral), forms them in physical space (Hermitian-extended
+// inverse FFT of the pair (lam_x + i lam_y) and of lam_z), applies the
+// transposed linearised product with the cached base state,
+//   du_bar = Omega x lam,  domega_bar = lam x U,
+// and returns the six fields to z spectral space (forward FFT of three packed
+// pairs, unpacked), scaled by `scale`.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_adj_z(typename V2<R>::T* __restrict__ xp, const R* __restrict__ base,
+            const typename V2<R>::T* __restrict__ tw, FFTPlan1D pl, int ny, int px, int nzm,
+            int xc, R scale) {
+  using C = typename V2<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  const int pz = pl.P;
+  const int y = blockIdx.x;
+  const int x0 = blockIdx.y * xc;
+  const int nxl = min(xc, px - x0);
+  C* A = reinterpret_cast<C*>(smem_raw);
+  C* B = A + xc * 3 * pz;
+  const size_t fs = (size_t)ny * px * nzm;
+  for (int t = threadIdx.x; t < nxl * 2 * pz; t += blockDim.x) {
+    const int m = t % pz;
+    const int lj = t / pz;  // x_l * 2 + j
+    const int jj = lj % 2;
+    const int xl = lj / 2;
+    const size_t off = ((size_t)y * px + (x0 + xl)) * nzm;
+    C val = mk((R)0, (R)0);
+    const int fa = (jj == 0) ? 0 : 2;
+    if (m < nzm) {
+      C a = xp[fa * fs + off + m];
+      C b = (jj == 0) ? xp[1 * fs + off + m] : mk((R)0, (R)0);
+      if (m == 0) {
+        a.y = 0;
+        b.y = 0;
+      }
+      val = mk(a.x - b.y, a.y + b.x);
+    } else if (m > pz - nzm) {
+      const int mm = pz - m;
+      C a = conjc(xp[fa * fs + off + mm]);
+      C b = (jj == 0) ? conjc(xp[1 * fs + off + mm]) : mk((R)0, (R)0);
+      val = mk(a.x - b.y, a.y + b.x);
+    }
+    A[(xl * 3 + jj) * pz + m] = val;
+  }
+  __syncthreads();
+  // inverse FFT of the two used lines of every x (line 2 of each x is idle)
+  for (int t = threadIdx.x; t < nxl * pz; t += blockDim.x) {
+    const int xl = t / pz;
+    const int z = t - xl * pz;
+    A[(xl * 3 + 2) * pz + z] = mk((R)0, (R)0);
+  }
+  __syncthreads();
+  C* res = lds_fft<R>(A, B, nxl * 3, pl, tw, (R)1);
+  C* oth = (res == A) ? B : A;
+  const size_t bs = (size_t)ny * px * pz;
+  for (int t = threadIdx.x; t < nxl * pz; t += blockDim.x) {
+    const int xl = t / pz;
+    const int z = t - xl * pz;
+    const C p0 = res[(xl * 3 + 0) * pz + z];
+    const C p1 = res[(xl * 3 + 1) * pz + z];
+    const R lx = p0.x, ly = p0.y, lz = p1.x;
+    const size_t bo = ((size_t)y * px + (x0 + xl)) * pz + z;
+    const R U = base[0 * bs + bo], V = base[1 * bs + bo], W = base[2 * bs + bo];
+    const R OX = base[3 * bs + bo], OY = base[4 * bs + bo], OZ = base[5 * bs + bo];
+    const R dux = OY * lz - OZ * ly;
+    const R duy = OZ * lx - OX * lz;
+    const R duz = OX * ly - OY * lx;
+    const R dox = ly * W - lz * V;
+    const R doy = lz * U - lx * W;
+    const R doz = lx * V - ly * U;
+    oth[(xl * 3 + 0) * pz + z] = mk(dux, duy);
+    oth[(xl * 3 + 1) * pz + z] = mk(duz, dox);
+    oth[(xl * 3 + 2) * pz + z] = mk(doy, doz);
+  }
+  __syncthreads();
+  C* fin = lds_fft<R>(oth, res, nxl * 3, pl, tw, (R)-1);
+  for (int t = threadIdx.x; t < nxl * 3 * nzm; t += blockDim.x) {
+    const int m = t % nzm;
+    const int lj = t / nzm;
+    const int jj = lj % 3;
+    const int xl = lj / 3;
+    const C a = fin[(xl * 3 + jj) * pz + m];
+    const C am = conjc(fin[(xl * 3 + jj) * pz + (pz - m) % pz]);
+    const C s1 = cscale(cadd(a, am), (R)0.5 * scale);
+    const C d = csub(a, am);
+    const C s2 = mk(d.y * (R)0.5 * scale, -d.x * (R)0.5 * scale);
+    const size_t off = ((size_t)y * px + (x0 + xl)) * nzm + m;
+    xp[(2 * jj) * fs + off] = s1;
+    xp[(2 * jj + 1) * fs + off] = s2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adj_synth: adjoint of (synthesis + curl combination), plus a * x:
+//   u_bar = T^T (F0 - i kz F4) - (T.D)^T F5
+//   v_bar = T^T (F1 + i kz F3 - i kx F5)
+//   w_bar = T^T (F2 + i kx F4) + (T.D)^T F3
+// F: six truncated y-valued fields [6][ny][nzm][nx] (u, v, w, omega adjoints).
+// Block: 8 mx x 32 n tile of one (component, kz).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_adj_synth(const typename V2<R>::T* __restrict__ F, const R* __restrict__ T,
+                const R* __restrict__ TD, const double2* __restrict__ x, double a,
+                double2* __restrict__ out, int nx, int ny, int nzh, int nzm, R alpha, R gamma) {
+  using C = typename V2<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  C* G1 = reinterpret_cast<C*>(smem_raw);  // [8][ny]
+  C* G2 = G1 + 8 * ny;                      // [8][ny]
+  const int c = blockIdx.z % 3;
+  const int kz = blockIdx.z / 3;
+  const int mx0 = blockIdx.x * 8;
+  const int n0 = blockIdx.y * 32;
+  const bool nyq = (kz >= nzm);
+  const size_t fs = (size_t)ny * nzm * nx;
+  if (!nyq) {
+    for (int idx = threadIdx.x; idx < 8 * ny; idx += 256) {
+      const int ml = idx % 8;
+      const int jj = idx / 8;
+      const int mx = mx0 + ml;
+      C g1 = mk((R)0, (R)0), g2 = mk((R)0, (R)0);
+      if (mx < nx && mx != nx / 2) {
+        const int mxv = (mx < nx / 2) ? mx : mx - nx;
+        const R kxv = alpha * (R)mxv;
+        const R kzv = gamma * (R)kz;
+        const size_t off = ((size_t)jj * nzm + kz) * nx + mx;
+        if (c == 0) {
+          g1 = csub(F[0 * fs + off], sidot(cscale(F[4 * fs + off], kzv), (R)1));
+          g2 = cscale(F[5 * fs + off], (R)-1);
+        } else if (c == 1) {
+          g1 = cadd(F[1 * fs + off], sidot(csub(cscale(F[3 * fs + off], kzv),
+                                                cscale(F[5 * fs + off], kxv)),
+                                           (R)1));
+        } else {
+          g1 = cadd(F[2 * fs + off], sidot(cscale(F[4 * fs + off], kxv), (R)1));
+          g2 = F[3 * fs + off];
+        }
+      }
+      G1[ml * ny + jj] = g1;
+      G2[ml * ny + jj] = g2;
+    }
+  }
+  __syncthreads();
+  const int tm = threadIdx.x / 32;
+  const int tn = threadIdx.x % 32;
+  const int mx = mx0 + tm;
+  const int n = n0 + tn;
+  if (mx < nx && n < ny) {
+    double rr = 0.0, ri = 0.0;
+    if (!nyq) {
+      R ar = 0, ai = 0;
+      const C* g1 = G1 + tm * ny;
+      const C* g2 = G2 + tm * ny;
+      for (int jj = 0; jj < ny; ++jj) {
+        const R t = T[(size_t)jj * ny + n];
+        const R td = TD[(size_t)jj * ny + n];
+        ar += t * g1[jj].x + td * g2[jj].x;
+        ai += t * g1[jj].y + td * g2[jj].y;
+      }
+      rr = (double)ar;
+      ri = (double)ai;
+    }
+    const size_t o = (((size_t)c * nx + mx) * nzh + kz) * ny + n;
+    if (x != nullptr) {
+      rr += a * x[o].x;
+      ri += a * x[o].y;
+    }
+    out[o] = make_double2(rr, ri);
+  }
+}
+
+// Scale the (0,0) mode of a canonical field in place.
+__global__ void k_mean_scale(double2* __restrict__ a, double s, int nx, int nzh, int ny) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * ny) return;
+  const int c = t / ny;
+  const int n = t - c * ny;
+  const size_t o = ((size_t)c * nx * nzh) * ny + n;
+  a[o] = make_double2(a[o].x * s, a[o].y * s);
+}
+
+// ----------------------------------- launchers -----------------------------------
+
+hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out) {
+  const Dims& d = p->d;
+  const size_t sh = (size_t)p->mode_stride * sizeof(double) + 3 * (size_t)d.ny * sizeof(double) +
+                    12 * (size_t)d.ny * sizeof(cd);
+  SP_PROF_BEGIN(p, KID_SOLVE_ADJ);
+  hipLaunchKernelGGL(k_stokes_solve_adj, dim3(d.nx * d.nzh), dim3(64), sh, p->stream, w, out,
+                     p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh, d.alpha, d.gamma, d.re,
+                     d.inv_dt);
+  SP_PROF_END(p, KID_SOLVE_ADJ);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_z(sp_plan* p, bool fp32) {
+  const Dims& d = p->d;
+  const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
+  int xc = (int)((64 * 1024) / (2 * 3 * d.pz * el));
+  if (xc < 1) xc = 1;
+  if (xc > d.px) xc = d.px;
+  dim3 grid(d.ny, (d.px + xc - 1) / xc);
+  const size_t sh = 2 * (size_t)xc * 3 * d.pz * el;
+  const double scale = 1.0 / ((double)d.px * d.pz);
+  SP_PROF_BEGIN(p, KID_ADJ_Z);
+  if (fp32)
+    hipLaunchKernelGGL(k_adj_z<float>, grid, dim3(256), sh, p->stream, (float2*)p->xp, p->base32,
+                       p->f_twz, p->fz, d.ny, d.px, d.nzm, xc, (float)scale);
+  else
+    hipLaunchKernelGGL(k_adj_z<double>, grid, dim3(256), sh, p->stream, (double2*)p->xp, p->base,
+                       p->d_twz, p->fz, d.ny, d.px, d.nzm, xc, scale);
+  SP_PROF_END(p, KID_ADJ_Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_synth(sp_plan* p, const double2* x, double a, double2* out, bool fp32) {
+  const Dims& d = p->d;
+  dim3 grid((d.nx + 7) / 8, (d.ny + 31) / 32, d.nzh * 3);
+  SP_PROF_BEGIN(p, KID_ADJ_SYNTH);
+  if (fp32) {
+    size_t sh = 2 * 8 * (size_t)d.ny * sizeof(float2);
+    hipLaunchKernelGGL(k_adj_synth<float>, grid, dim3(256), sh, p->stream, (const float2*)p->yv,
+                       p->f_T, p->f_TD, x, a, out, d.nx, d.ny, d.nzh, d.nzm, (float)d.alpha,
+                       (float)d.gamma);
+  } else {
+    size_t sh = 2 * 8 * (size_t)d.ny * sizeof(double2);
+    hipLaunchKernelGGL(k_adj_synth<double>, grid, dim3(256), sh, p->stream, (const double2*)p->yv,
+                       p->d_T, p->d_TD, x, a, out, d.nx, d.ny, d.nzh, d.nzm, d.alpha, d.gamma);
+  }
+  SP_PROF_END(p, KID_ADJ_SYNTH);
+  return hipGetLastError();
+}
+
+hipError_t launch_mean_scale(sp_plan* p, double2* a, double s) {
+  const Dims& d = p->d;
+  SP_PROF_BEGIN(p, KID_MEAN_SCALE);
+  hipLaunchKernelGGL(k_mean_scale, dim3((3 * d.ny + 255) / 256), dim3(256), 0, p->stream, a, s,
+                     d.nx, d.nzh, d.ny);
+  SP_PROF_END(p, KID_MEAN_SCALE);
+  return hipGetLastError();
+}
+
+#define SP_TRY_HIP(expr, what)                 \
+  do {                                         \
+    sp_status _s = hip_check(p, (expr), what); \
+    if (_s != SP_OK) return _s;                \
+  } while (0)
+
+sp_status vjp_lin(sp_plan* p, int op, const double2* w, double2* out) {
+  if (!p->base_valid) return set_error(p, SP_ERR_INVALID, "no base state: call sp_linearize");
+  const bool fp32 = (p->precision == SP_MIXED);
+  const Dims& d = p->d;
+  const size_t n = (size_t)3 * d.nx * d.nzh * d.ny;
+  // packed-Euclidean -> Parseval: the (0,0) mode counts twice relative to the rest
+  SP_TRY_HIP(hipMemcpyAsync(p->t1, w, n * sizeof(double2), hipMemcpyDeviceToDevice, p->stream),
+             "copy w");
+  SP_TRY_HIP(launch_mean_scale(p, p->t1, 2.0), "mean_scale");
+  SP_TRY_HIP(launch_stokes_solve_adj(p, p->t1, p->t2), "stokes_solve_adj");
+  SP_TRY_HIP(launch_synth_tab(p, p->t2, 1, p->nv, fp32), "analysis^T");
+  SP_TRY_HIP(launch_fft_x_inv_gen(p, p->nv, p->xp, 3, 1, fp32), "pad+ifft_x");
+  SP_TRY_HIP(launch_adj_z(p, fp32), "adj_z");
+  SP_TRY_HIP(launch_fft_x_fwd_gen(p, p->xp, p->yv, 6, fp32), "fft_x+truncate");
+  SP_TRY_HIP(launch_adj_synth(p, p->t2, d.inv_dt, out, fp32), "adj_synth");
+  SP_TRY_HIP(launch_mean_scale(p, out, 0.5), "mean_scale");
+  if (op == SP_OP_RESIDUAL)
+    SP_TRY_HIP(launch_axpby(p, out, d.inv_dt, w, -d.inv_dt, out, n), "axpby");
+  return SP_OK;
+}
+
 }  // namespace sp
 
 using namespace sp;
 
 extern "C" sp_status sp_vjp_lin(sp_plan* p, int32_t op, const double* w, double* out) {
   if (!p) return SP_ERR_INVALID;
+  if (!w || !out) return set_error(p, SP_ERR_INVALID, "null pointer");
+  if (op != SP_OP_PHI && op != SP_OP_RESIDUAL) return set_error(p, SP_ERR_INVALID, "bad op");
+  if (w == out) return set_error(p, SP_ERR_INVALID, "sp_vjp: out aliases w");
   return vjp_lin(p, op, (const double2*)w, (double2*)out);
 }
 
 extern "C" sp_status sp_vjp(sp_plan* p, int32_t op, const double* u, const double* w, double* out) {
   if (!p) return SP_ERR_INVALID;
+  if (!u) return set_error(p, SP_ERR_INVALID, "null pointer");
   sp_status s = sp_linearize(p, u);
   if (s) return s;
   return sp_vjp_lin(p, op, w, out);

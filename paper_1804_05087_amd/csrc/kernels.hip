@@ -17,131 +17,39 @@
 // implicit solve is FP64 only.
 #include <hip/hip_runtime.h>
 
+#include "device_common.h"
 #include "solve_core.h"
 #include "sp_internal.h"
 
 namespace sp {
 
-template <typename R>
-struct V2;
-template <>
-struct V2<double> {
-  using T = double2;
-};
-template <>
-struct V2<float> {
-  using T = float2;
-};
-
-__device__ inline double2 mk(double a, double b) { return make_double2(a, b); }
-__device__ inline float2 mk(float a, float b) { return make_float2(a, b); }
-__device__ inline double2 cadd(double2 a, double2 b) { return mk(a.x + b.x, a.y + b.y); }
-__device__ inline float2 cadd(float2 a, float2 b) { return mk(a.x + b.x, a.y + b.y); }
-__device__ inline double2 csub(double2 a, double2 b) { return mk(a.x - b.x, a.y - b.y); }
-__device__ inline float2 csub(float2 a, float2 b) { return mk(a.x - b.x, a.y - b.y); }
-__device__ inline double2 cmul(double2 a, double2 b) {
-  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ inline float2 cmul(float2 a, float2 b) {
-  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ inline double2 cscale(double2 a, double s) { return mk(a.x * s, a.y * s); }
-__device__ inline float2 cscale(float2 a, float s) { return mk(a.x * s, a.y * s); }
-__device__ inline double2 conjc(double2 a) { return mk(a.x, -a.y); }
-__device__ inline float2 conjc(float2 a) { return mk(a.x, -a.y); }
-// s * i * a for s = +-1
-__device__ inline double2 sidot(double2 a, double s) { return mk(-s * a.y, s * a.x); }
-__device__ inline float2 sidot(float2 a, float s) { return mk(-s * a.y, s * a.x); }
-
-template <typename R>
-__device__ inline typename V2<R>::T to_r2(double2 a) {
-  return mk((R)a.x, (R)a.y);
-}
-
 // ---------------------------------------------------------------------------
-// Batched in-LDS Stockham FFT of nl lines of length P (line l at a[l*P]).
-// Mixed radix 2/3/4 with the factor list of `pl`; tw[q] = exp(-2 pi i q / P).
-// sign = -1: forward (unscaled), +1: inverse (unscaled). Returns the buffer
-// holding the result (a or b). Must be called by the whole block.
-// ---------------------------------------------------------------------------
-template <typename R>
-__device__ typename V2<R>::T* lds_fft(typename V2<R>::T* a, typename V2<R>::T* b, int nl,
-                                      const FFTPlan1D& pl, const typename V2<R>::T* tw,
-                                      R sign) {
-  using C = typename V2<R>::T;
-  const int P = pl.P;
-  int Ns = 1;
-  for (int s = 0; s < pl.nrad; ++s) {
-    const int Rd = pl.rad[s];
-    const int nb = P / Rd;
-    const int tstride = P / (Ns * Rd);
-    for (int t = threadIdx.x; t < nl * nb; t += blockDim.x) {
-      const int l = t / nb;
-      const int j = t - l * nb;
-      const C* x = a + l * P;
-      C* y = b + l * P;
-      const int k = j % Ns;
-      C v[4];
-      for (int r = 0; r < Rd; ++r) v[r] = x[j + r * nb];
-      if (Ns > 1) {
-        for (int r = 1; r < Rd; ++r) {
-          C w = tw[(k * r * tstride) % P];
-          if (sign > 0) w = conjc(w);
-          v[r] = cmul(v[r], w);
-        }
-      }
-      C o[4];
-      if (Rd == 2) {
-        o[0] = cadd(v[0], v[1]);
-        o[1] = csub(v[0], v[1]);
-      } else if (Rd == 3) {
-        const R h = (R)0.86602540378443864676;  // sqrt(3)/2
-        C t1 = cadd(v[1], v[2]);
-        C d = csub(v[1], v[2]);
-        C m = csub(v[0], cscale(t1, (R)0.5));
-        C e = sidot(cscale(d, h), sign);
-        o[0] = cadd(v[0], t1);
-        o[1] = cadd(m, e);
-        o[2] = csub(m, e);
-      } else {  // 4
-        C s0 = cadd(v[0], v[2]);
-        C s1 = csub(v[0], v[2]);
-        C s2 = cadd(v[1], v[3]);
-        C s3 = sidot(csub(v[1], v[3]), sign);
-        o[0] = cadd(s0, s2);
-        o[2] = csub(s0, s2);
-        o[1] = cadd(s1, s3);
-        o[3] = csub(s1, s3);
-      }
-      const int base = (j / Ns) * Ns * Rd + k;
-      for (int r = 0; r < Rd; ++r) y[base + r * Ns] = o[r];
-    }
-    __syncthreads();
-    C* tmp = a;
-    a = b;
-    b = tmp;
-    Ns *= Rd;
-  }
-  return a;
-}
-
-// ---------------------------------------------------------------------------
-// synth_y: values at the Gauss-Lobatto points of u, du/dy, v, w, dw/dy.
-// out[f][y][kz][mx] = sum_n M_f[y][n] u[c_f][mx][kz][n], M in {T, T.D}.
+// synth_y: y-contractions of canonical coefficient fields.
+// out[f][y][kz][mx] = sum_n M_f[y][n] u[c_f][mx][kz][n] for the fields of `tab`
+// (component c_f, matrix M_f in {M0, M1, M2}). Forward use: values at the
+// Gauss-Lobatto points of u, du/dy, v, w, dw/dy (M = T, T.D); adjoint use:
+// Tinv^T applied to the three components.
 // Block: 16 mx x 16 y tile of one (field, kz).
 // ---------------------------------------------------------------------------
+struct FieldTab {
+  int n;
+  int comp[8];
+  int mat[8];
+};
+
 template <typename R>
 __global__ void __launch_bounds__(256)
-    k_synth_y(const double2* __restrict__ u, const R* __restrict__ T, const R* __restrict__ TD,
+    k_synth_y(const double2* __restrict__ u, FieldTab tab, const R* __restrict__ M0,
+              const R* __restrict__ M1, const R* __restrict__ M2,
               typename V2<R>::T* __restrict__ yv, int nx, int ny, int nzh, int nzm) {
   using C = typename V2<R>::T;
   extern __shared__ unsigned char smem_raw[];
   C* Us = reinterpret_cast<C*>(smem_raw);            // [16][ny]
   R* Ms = reinterpret_cast<R*>(Us + 16 * ny);         // [16][ny]
-  const int f = blockIdx.z % 5;
-  const int kz = blockIdx.z / 5;
-  const int comp = (f < 2) ? 0 : (f == 2 ? 1 : 2);
-  const R* M = (f == 1 || f == 4) ? TD : T;
+  const int f = blockIdx.z % tab.n;
+  const int kz = blockIdx.z / tab.n;
+  const int comp = tab.comp[f];
+  const R* M = (tab.mat[f] == 0) ? M0 : (tab.mat[f] == 1 ? M1 : M2);
   const int mx0 = blockIdx.x * 16;
   const int y0 = blockIdx.y * 16;
   for (int idx = threadIdx.x; idx < 16 * ny; idx += 256) {
@@ -151,8 +59,7 @@ __global__ void __launch_bounds__(256)
     C val = mk((R)0, (R)0);
     if (mx < nx) val = to_r2<R>(u[(((size_t)comp * nx + mx) * nzh + kz) * ny + n]);
     Us[idx] = val;
-    const int yl = ml;
-    const int yy = y0 + yl;
+    const int yy = y0 + ml;
     Ms[idx] = (yy < ny) ? M[(size_t)yy * ny + n] : (R)0;
   }
   __syncthreads();
@@ -174,15 +81,17 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------
-// fft_x_inv: build u, v, w, omega_x, omega_y, omega_z lines along x from the
-// y-valued fields (multiplying by i k_x, i k_z), zero-pad to px and inverse FFT.
+// fft_x_inv: zero-pad lines along x to px and inverse FFT.
+// plain == 0: the six output fields u, v, w, omega_x, omega_y, omega_z are
+// built from the five y-valued fields (u, du/dy, v, w, dw/dy) with i k_x, i k_z;
+// plain != 0: output field f is input field f.
 // Block: (y, output field f, chunk of kc z-modes).
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ void __launch_bounds__(256)
     k_fft_x_inv(const typename V2<R>::T* __restrict__ yv, typename V2<R>::T* __restrict__ xp,
                 const typename V2<R>::T* __restrict__ tw, FFTPlan1D pl, int nx, int ny, int nzm,
-                int kc, R alpha, R gamma) {
+                int kc, R alpha, R gamma, int plain) {
   using C = typename V2<R>::T;
   extern __shared__ unsigned char smem_raw[];
   const int px = pl.P;
@@ -206,7 +115,9 @@ __global__ void __launch_bounds__(256)
     const R kxv = alpha * (R)mxv;
     const R kzv = gamma * (R)kz;
     C val;
-    if (f == 0) {
+    if (plain) {
+      val = yv[f * fs + off];
+    } else if (f == 0) {
       val = yv[0 * fs + off];
     } else if (f == 1) {
       val = yv[2 * fs + off];
@@ -687,39 +598,64 @@ static int chunk_for(int P, int total, size_t elem) {
   return k;
 }
 
-hipError_t launch_synth_y(sp_plan* p, const double2* u, bool fp32) {
+hipError_t launch_synth_tab(sp_plan* p, const double2* u, int which, void* out, bool fp32) {
   const Dims& d = p->d;
-  dim3 grid((d.nx + 15) / 16, (d.ny + 15) / 16, d.nzm * 5);
+  FieldTab tab{};
+  if (which == 0) {  // forward: u, du/dy, v, w, dw/dy
+    tab.n = 5;
+    const int c[5] = {0, 0, 1, 2, 2}, m[5] = {0, 1, 0, 0, 1};
+    for (int i = 0; i < 5; ++i) {
+      tab.comp[i] = c[i];
+      tab.mat[i] = m[i];
+    }
+  } else {  // adjoint of the analysis: Tinv^T on each component
+    tab.n = 3;
+    for (int i = 0; i < 3; ++i) {
+      tab.comp[i] = i;
+      tab.mat[i] = 2;
+    }
+  }
+  dim3 grid((d.nx + 15) / 16, (d.ny + 15) / 16, d.nzm * tab.n);
   SP_PROF_BEGIN(p, KID_SYNTH_Y);
   if (fp32) {
     size_t sh = 16 * d.ny * (sizeof(float2) + sizeof(float));
-    hipLaunchKernelGGL(k_synth_y<float>, grid, dim3(256), sh, p->stream, u, p->f_T, p->f_TD,
-                       (float2*)p->yv, d.nx, d.ny, d.nzh, d.nzm);
+    hipLaunchKernelGGL(k_synth_y<float>, grid, dim3(256), sh, p->stream, u, tab, p->f_T, p->f_TD,
+                       p->f_TinvT, (float2*)out, d.nx, d.ny, d.nzh, d.nzm);
   } else {
     size_t sh = 16 * d.ny * (sizeof(double2) + sizeof(double));
-    hipLaunchKernelGGL(k_synth_y<double>, grid, dim3(256), sh, p->stream, u, p->d_T, p->d_TD,
-                       (double2*)p->yv, d.nx, d.ny, d.nzh, d.nzm);
+    hipLaunchKernelGGL(k_synth_y<double>, grid, dim3(256), sh, p->stream, u, tab, p->d_T, p->d_TD,
+                       p->d_TinvT, (double2*)out, d.nx, d.ny, d.nzh, d.nzm);
   }
   SP_PROF_END(p, KID_SYNTH_Y);
   return hipGetLastError();
 }
 
-hipError_t launch_fft_x_inv(sp_plan* p, bool fp32) {
+hipError_t launch_synth_y(sp_plan* p, const double2* u, bool fp32) {
+  return launch_synth_tab(p, u, 0, p->yv, fp32);
+}
+
+hipError_t launch_fft_x_inv_gen(sp_plan* p, const void* in, void* out, int nfields, int plain,
+                                bool fp32) {
   const Dims& d = p->d;
   const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
   const int kc = chunk_for(d.px, d.nzm, el);
-  dim3 grid(d.ny, 6, (d.nzm + kc - 1) / kc);
+  dim3 grid(d.ny, nfields, (d.nzm + kc - 1) / kc);
   const size_t sh = 2 * (size_t)kc * d.px * el;
   SP_PROF_BEGIN(p, KID_FFT_X_INV);
   if (fp32)
-    hipLaunchKernelGGL(k_fft_x_inv<float>, grid, dim3(256), sh, p->stream, (const float2*)p->yv,
-                       (float2*)p->xp, p->f_twx, p->fx, d.nx, d.ny, d.nzm, kc, (float)d.alpha,
-                       (float)d.gamma);
+    hipLaunchKernelGGL(k_fft_x_inv<float>, grid, dim3(256), sh, p->stream, (const float2*)in,
+                       (float2*)out, p->f_twx, p->fx, d.nx, d.ny, d.nzm, kc, (float)d.alpha,
+                       (float)d.gamma, plain);
   else
-    hipLaunchKernelGGL(k_fft_x_inv<double>, grid, dim3(256), sh, p->stream, (const double2*)p->yv,
-                       (double2*)p->xp, p->d_twx, p->fx, d.nx, d.ny, d.nzm, kc, d.alpha, d.gamma);
+    hipLaunchKernelGGL(k_fft_x_inv<double>, grid, dim3(256), sh, p->stream, (const double2*)in,
+                       (double2*)out, p->d_twx, p->fx, d.nx, d.ny, d.nzm, kc, d.alpha, d.gamma,
+                       plain);
   SP_PROF_END(p, KID_FFT_X_INV);
   return hipGetLastError();
+}
+
+hipError_t launch_fft_x_inv(sp_plan* p, bool fp32) {
+  return launch_fft_x_inv_gen(p, p->yv, p->xp, 6, 0, fp32);
 }
 
 hipError_t launch_z_product(sp_plan* p, int mode, bool fp32) {
@@ -744,21 +680,25 @@ hipError_t launch_z_product(sp_plan* p, int mode, bool fp32) {
   return hipGetLastError();
 }
 
-hipError_t launch_fft_x_fwd(sp_plan* p, bool fp32) {
+hipError_t launch_fft_x_fwd_gen(sp_plan* p, const void* in, void* out, int nfields, bool fp32) {
   const Dims& d = p->d;
   const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
   const int kc = chunk_for(d.px, d.nzm, el);
-  dim3 grid(d.ny, 3, (d.nzm + kc - 1) / kc);
+  dim3 grid(d.ny, nfields, (d.nzm + kc - 1) / kc);
   const size_t sh = 2 * (size_t)kc * d.px * el;
   SP_PROF_BEGIN(p, KID_FFT_X_FWD);
   if (fp32)
-    hipLaunchKernelGGL(k_fft_x_fwd<float>, grid, dim3(256), sh, p->stream, (const float2*)p->np,
-                       (float2*)p->nv, p->f_twx, p->fx, d.nx, d.ny, d.nzm, kc);
+    hipLaunchKernelGGL(k_fft_x_fwd<float>, grid, dim3(256), sh, p->stream, (const float2*)in,
+                       (float2*)out, p->f_twx, p->fx, d.nx, d.ny, d.nzm, kc);
   else
-    hipLaunchKernelGGL(k_fft_x_fwd<double>, grid, dim3(256), sh, p->stream, (const double2*)p->np,
-                       (double2*)p->nv, p->d_twx, p->fx, d.nx, d.ny, d.nzm, kc);
+    hipLaunchKernelGGL(k_fft_x_fwd<double>, grid, dim3(256), sh, p->stream, (const double2*)in,
+                       (double2*)out, p->d_twx, p->fx, d.nx, d.ny, d.nzm, kc);
   SP_PROF_END(p, KID_FFT_X_FWD);
   return hipGetLastError();
+}
+
+hipError_t launch_fft_x_fwd(sp_plan* p, bool fp32) {
+  return launch_fft_x_fwd_gen(p, p->np, p->nv, 3, fp32);
 }
 
 hipError_t launch_analysis_rhs(sp_plan* p, const double2* x, double a, double2* g, bool fp32) {

@@ -204,7 +204,8 @@ static std::vector<F> convert(const std::vector<D>& v) {
 
 static void free_plan(sp_plan* p) {
   void* ptrs[] = {p->d_T,   p->d_TD,  p->d_Tinv, p->d_G,    p->d_hw,   p->d_mode, p->d_twx,
-                  p->d_twz, p->f_twx, p->f_twz,  p->f_T,    p->f_TD,   p->f_Tinv, p->d_scratch};
+                  p->d_twz, p->f_twx, p->f_twz,  p->f_T,    p->f_TD,   p->f_Tinv, p->d_scratch,
+                  p->d_TinvT, p->f_TinvT};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (p->h_partial) (void)hipHostFree(p->h_partial);
@@ -275,12 +276,18 @@ extern "C" sp_status sp_plan_create(const sp_params* prm, void* hip_stream, sp_p
   if ((s = upload(p, (void**)&p->d_TD, TD.data(), mb, "upload TD"))) return fail(s);
   if ((s = upload(p, (void**)&p->d_Tinv, Tinv.data(), mb, "upload Tinv"))) return fail(s);
   if ((s = upload(p, (void**)&p->d_G, G.data(), mb, "upload G"))) return fail(s);
+  std::vector<double> TinvT(Tinv.size());
+  for (int a = 0; a < d.ny; ++a)
+    for (int b = 0; b < d.ny; ++b) TinvT[(size_t)a * d.ny + b] = Tinv[(size_t)b * d.ny + a];
+  if ((s = upload(p, (void**)&p->d_TinvT, TinvT.data(), mb, "upload TinvT"))) return fail(s);
   {
     auto fT = convert<float>(T), fTD = convert<float>(TD), fTi = convert<float>(Tinv);
+    auto fTiT = convert<float>(TinvT);
     const size_t fb = fT.size() * sizeof(float);
     if ((s = upload(p, (void**)&p->f_T, fT.data(), fb, "upload fT"))) return fail(s);
     if ((s = upload(p, (void**)&p->f_TD, fTD.data(), fb, "upload fTD"))) return fail(s);
     if ((s = upload(p, (void**)&p->f_Tinv, fTi.data(), fb, "upload fTinv"))) return fail(s);
+    if ((s = upload(p, (void**)&p->f_TinvT, fTiT.data(), fb, "upload fTinvT"))) return fail(s);
   }
   {
     auto tx = twiddles(d.px), tz = twiddles(d.pz);
@@ -305,7 +312,7 @@ extern "C" sp_status sp_plan_create(const sp_params* prm, void* hip_stream, sp_p
   };
   p->npartial = 1024;
   Piece pieces[] = {
-      {&p->yv, (size_t)5 * d.ny * d.nzm * d.nx * cz},
+      {&p->yv, (size_t)6 * d.ny * d.nzm * d.nx * cz},
       {&p->xp, (size_t)6 * d.ny * d.px * d.nzm * cz},
       {&p->np, (size_t)3 * d.ny * d.px * d.nzm * cz},
       {&p->nv, (size_t)3 * d.ny * d.nzm * d.nx * cz},

@@ -64,12 +64,14 @@ struct sp_plan {
   float* f_T = nullptr;
   float* f_TD = nullptr;
   float* f_Tinv = nullptr;
+  double* d_TinvT = nullptr;  // [ny][ny] Tinv^T (adjoint of the analysis)
+  float* f_TinvT = nullptr;
   sp::FFTPlan1D fx, fz;
 
   // scratch (device)
   void* d_scratch = nullptr;
   size_t scratch_bytes = 0;
-  void* yv = nullptr;         // [5][ny][nzm][nx] complex (real type of the path)
+  void* yv = nullptr;         // [6][ny][nzm][nx] complex (real type of the path)
   void* xp = nullptr;         // [6][ny][px][nzm] complex
   void* np = nullptr;         // [3][ny][px][nzm] complex
   void* nv = nullptr;         // [3][ny][nzm][nx] complex
@@ -106,6 +108,16 @@ hipError_t launch_fft_x_inv(sp_plan* p, bool fp32);
 // 2: store U, Omega into base (no product) ; 3: adjoint (see kernels.hip)
 hipError_t launch_z_product(sp_plan* p, int mode, bool fp32);
 hipError_t launch_fft_x_fwd(sp_plan* p, bool fp32);
+// which = 0: forward synthesis table into p->yv; 1: Tinv^T on 3 components into out
+hipError_t launch_synth_tab(sp_plan* p, const double2* u, int which, void* out, bool fp32);
+hipError_t launch_fft_x_inv_gen(sp_plan* p, const void* in, void* out, int nfields, int plain,
+                                bool fp32);
+hipError_t launch_fft_x_fwd_gen(sp_plan* p, const void* in, void* out, int nfields, bool fp32);
+// adjoint kernels (adjoint.hip)
+hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out);
+hipError_t launch_adj_z(sp_plan* p, bool fp32);
+hipError_t launch_adj_synth(sp_plan* p, const double2* x, double a, double2* out, bool fp32);
+hipError_t launch_mean_scale(sp_plan* p, double2* a, double s);
 hipError_t launch_analysis_rhs(sp_plan* p, const double2* x, double a, double2* g, bool fp32);
 hipError_t launch_stokes_solve(sp_plan* p, const double2* g, double2* out, int inhomogeneous);
 hipError_t launch_axpby(sp_plan* p, const double2* x, double a, const double2* y, double b,
