@@ -19,15 +19,26 @@
 
 #include "device_common.h"
 #include "solve_core.h"
+#include "solve_wave.h"
 #include "sp_internal.h"
 
 namespace sp {
 
 // ---------------------------------------------------------------------------
 // stokes_solve_adj: out = S_0^+ w per mode (conjugate transpose of the solve
-// with homogeneous walls). One 64-lane block per mode; lanes 0 and 1 run the
-// two parity classes, the other lanes help with the elementwise parts.
+// with homogeneous walls): the forward steps of k_stokes_solve transposed and
+// taken in reverse order. One 64-lane wave per mode, lanes 0-31 parity class 0,
+// lanes 32-63 class 1.
 // ---------------------------------------------------------------------------
+#define SP_FOR_PAR(par, body)                       \
+  _Pragma("unroll") for (int e_ = 0; e_ < E; ++e_) { \
+    const int n = (par) + 2 * (lane * E + e_);       \
+    if (n <= N) {                                    \
+      body                                           \
+    }                                                \
+  }
+
+template <int E>
 __global__ void __launch_bounds__(64)
     k_stokes_solve_adj(const double2* __restrict__ w, double2* __restrict__ out,
                        const double* __restrict__ modedata, const double* __restrict__ hw_g,
@@ -55,6 +66,8 @@ __global__ void __launch_bounds__(64)
   const int i = mode / nzh;
   const int j = mode - i * nzh;
   const int tid = threadIdx.x;
+  const int half = tid >> 5;
+  const int lane = tid & 31;
   const size_t cs = (size_t)nx * nzh * ny;
   const size_t mo = ((size_t)i * nzh + j) * ny;
   const bool nyq = (i == nx / 2) || (j == nzh - 1);
@@ -75,6 +88,7 @@ __global__ void __launch_bounds__(64)
   const double k2 = kx * kx + kz * kz;
   const bool mean = (i == 0 && j == 0);
   const double k = sqrt(k2);
+  const double ik = mean ? 0.0 : 1.0 / k;
   const double lam = k2 + re * inv_dt;
   for (int n = tid; n < n1; n += 64) {
     const double2 a = w[mo + n];
@@ -85,8 +99,8 @@ __global__ void __launch_bounds__(64)
       Upb[n] = ub;
       Ub[n] = wb;
     } else {
-      Upb[n] = (ub * kx + wb * kz) * (1.0 / k);
-      Ub[n] = (ub * kz - wb * kx) * (1.0 / k);
+      Upb[n] = (ub * kx + wb * kz) * ik;
+      Ub[n] = (ub * kz - wb * kx) * ik;
     }
     Vb[n] = vb;
     Pb[n] = cd(0.0);
@@ -98,49 +112,54 @@ __global__ void __launch_bounds__(64)
   const ModeLayout L{n1};
   SweepView helm(rec + L.helm(), n1);
   SweepView pois(rec + L.pois(), n1);
-  if (tid < 2) {
-    if (mean) {
-      const int p = tid;
-      sweep_solve_T<cd>(helm, hw, N, p, Upb, Rb, W);
-      for (int n = p; n <= N; n += 2) Fpb[n] = -Rb[n];
-      sweep_solve_T<cd>(helm, hw, N, p, Ub, Rb, W);
-      for (int n = p; n <= N; n += 2) Fpp[n] = -Rb[n];
-    } else {
-      const int pv = tid;
-      const int po = 1 - pv;
-      // u_perp = H(-F_perp)
-      sweep_solve_T<cd>(helm, hw, N, po, Ub, Rb, W);
-      for (int n = po; n <= N; n += 2) Fpp[n] = -Rb[n];
-      // u_par = i D v / k
-      for (int n = po; n <= N; n += 2) A[n] = mul_i(-Upb[n]) * (1.0 / k);
-      deriv_T_parity<cd>(N, po, A, Tm);
-      for (int n = pv; n <= N; n += 2) Vb[n] = Vb[n] + Tm[n];
-      // v = v_p + c_delta v_delta + c_b v_b, (c_delta, c_b) = -Minv (l_a, l_b)
-      const double* vdel = rec + L.vdel();
-      const double* vbs = rec + L.vb();
-      cd ca(0.0), cbb(0.0);
-      for (int n = pv; n <= N; n += 2) {
-        ca = ca + Vb[n] * vdel[n];
-        cbb = cbb + Vb[n] * vbs[n];
-      }
-      const double* Mi = rec + L.minv() + 4 * pv;
-      const cd la = -(ca * Mi[0] + cbb * Mi[2]);
-      const cd lb = -(ca * Mi[1] + cbb * Mi[3]);
-      for (int n = pv; n <= N; n += 2) Vb[n] = Vb[n] + la * ((double)n * n);
-      const int m = (N % 2 == pv) ? N : N - 1;
-      Vb[m] = Vb[m] + lb * lam;
-      if (m == N - 1) Pb[N] = Pb[N] + lb * (2.0 * N);
-      // v_p = H(D P - F_v)
-      sweep_solve_T<cd>(helm, hw, N, pv, Vb, Rb, W);
-      for (int n = pv; n <= N; n += 2) Fvb[n] = -Rb[n];
-      deriv_T_parity<cd>(N, pv, Rb, Tm);
-      for (int n = po; n <= N; n += 2) Pb[n] = Pb[n] + Tm[n];
-      // P = Pois(div F), div F = i k F_par + D F_v
-      sweep_solve_T<cd>(pois, hw, N, po, Pb, Db, W);
-      for (int n = po; n <= N; n += 2) Fpb[n] = mul_i(-Db[n]) * k;
-      deriv_T_parity<cd>(N, po, Db, Tm);
-      for (int n = pv; n <= N; n += 2) Fvb[n] = Fvb[n] + Tm[n];
-    }
+  if (mean) {
+    const int p = half;
+    wsweep_T<E>(helm, hw, N, p, Upb, Rb, W, lane);
+    SP_FOR_PAR(p, Fpb[n] = -Rb[n];)
+    __syncthreads();
+    wsweep_T<E>(helm, hw, N, p, Ub, Rb, W, lane);
+    SP_FOR_PAR(p, Fpp[n] = -Rb[n];)
+  } else {
+    const int pv = half;
+    const int po = 1 - pv;
+    // u_perp = H(-F_perp)
+    wsweep_T<E>(helm, hw, N, po, Ub, Rb, W, lane);
+    SP_FOR_PAR(po, Fpp[n] = -Rb[n]; A[n] = mul_i(-Upb[n]) * ik;)
+    __syncthreads();
+    // u_par = i D v / k
+    wderiv_T<E>(N, po, A, Tm, W, lane);
+    __syncthreads();
+    SP_FOR_PAR(pv, Vb[n] = Vb[n] + Tm[n];)
+    __syncthreads();
+    // v = v_p + c_delta v_delta + c_b v_b, (c_delta, c_b) = -Minv (l_a, l_b)
+    const double* vdel = rec + L.vdel();
+    const double* vbs = rec + L.vb();
+    cd ca(0.0), cbb(0.0);
+    SP_FOR_PAR(pv, ca = ca + Vb[n] * vdel[n]; cbb = cbb + Vb[n] * vbs[n];)
+    ca = sum32(ca);
+    cbb = sum32(cbb);
+    const double* Mi = rec + L.minv() + 4 * pv;
+    const cd la = -(ca * Mi[0] + cbb * Mi[2]);
+    const cd lb = -(ca * Mi[1] + cbb * Mi[3]);
+    const int m = (N % 2 == pv) ? N : N - 1;
+    SP_FOR_PAR(pv, Vb[n] = Vb[n] + la * ((double)n * n) + ((n == m) ? lb * lam : cd(0.0));)
+    SP_FOR_PAR(po, if (n == N && m == N - 1) Pb[n] = Pb[n] + lb * (2.0 * N);)
+    __syncthreads();
+    // v_p = H(D P - F_v)
+    wsweep_T<E>(helm, hw, N, pv, Vb, Rb, W, lane);
+    SP_FOR_PAR(pv, Fvb[n] = -Rb[n];)
+    __syncthreads();
+    wderiv_T<E>(N, pv, Rb, Tm, W, lane);
+    __syncthreads();
+    SP_FOR_PAR(po, Pb[n] = Pb[n] + Tm[n];)
+    __syncthreads();
+    // P = Pois(div F), div F = i k F_par + D F_v
+    wsweep_T<E>(pois, hw, N, po, Pb, Db, W, lane);
+    SP_FOR_PAR(po, Fpb[n] = mul_i(-Db[n]) * k;)
+    __syncthreads();
+    wderiv_T<E>(N, po, Db, Tm, W, lane);
+    __syncthreads();
+    SP_FOR_PAR(pv, Fvb[n] = Fvb[n] + Tm[n];)
   }
   __syncthreads();
   for (int n = tid; n < n1; n += 64) {
@@ -150,8 +169,8 @@ __global__ void __launch_bounds__(64)
         gu = Fpb[n] * re;
         gw = Fpp[n] * re;
       } else {
-        gu = (Fpb[n] * kx + Fpp[n] * kz) * (re / k);
-        gw = (Fpb[n] * kz - Fpp[n] * kx) * (re / k);
+        gu = (Fpb[n] * kx + Fpp[n] * kz) * (re * ik);
+        gw = (Fpb[n] * kz - Fpp[n] * kx) * (re * ik);
         gv = Fvb[n] * re;
       }
     }
@@ -170,7 +189,7 @@ __global__ void __launch_bounds__(64)
 // and returns the six fields to z spectral space (forward FFT of three packed
 // pairs, unpacked), scaled by `scale`.
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, int PT>
 __global__ void __launch_bounds__(256)
     k_adj_z(typename V2<R>::T* __restrict__ xp, const R* __restrict__ base,
             const typename V2<R>::T* __restrict__ tw, FFTPlan1D pl, int ny, int px, int nzm,
@@ -183,7 +202,9 @@ __global__ void __launch_bounds__(256)
   const int nxl = min(xc, px - x0);
   C* A = reinterpret_cast<C*>(smem_raw);
   C* B = A + xc * 3 * pz;
+  C* twl = B + xc * 3 * pz;
   const size_t fs = (size_t)ny * px * nzm;
+  for (int t = threadIdx.x; t < pz; t += blockDim.x) twl[t] = tw[t];
   for (int t = threadIdx.x; t < nxl * 2 * pz; t += blockDim.x) {
     const int m = t % pz;
     const int lj = t / pz;  // x_l * 2 + j
@@ -216,7 +237,7 @@ __global__ void __launch_bounds__(256)
     A[(xl * 3 + 2) * pz + z] = mk((R)0, (R)0);
   }
   __syncthreads();
-  C* res = lds_fft<R>(A, B, nxl * 3, pl, tw, (R)1);
+  C* res = fft_lines<R, PT>(A, B, nxl * 3, pl, twl, (R)1);
   C* oth = (res == A) ? B : A;
   const size_t bs = (size_t)ny * px * pz;
   for (int t = threadIdx.x; t < nxl * pz; t += blockDim.x) {
@@ -239,7 +260,7 @@ __global__ void __launch_bounds__(256)
     oth[(xl * 3 + 2) * pz + z] = mk(doy, doz);
   }
   __syncthreads();
-  C* fin = lds_fft<R>(oth, res, nxl * 3, pl, tw, (R)-1);
+  C* fin = fft_lines<R, PT>(oth, res, nxl * 3, pl, twl, (R)-1);
   for (int t = threadIdx.x; t < nxl * 3 * nzm; t += blockDim.x) {
     const int m = t % nzm;
     const int lj = t / nzm;
@@ -347,14 +368,23 @@ __global__ void k_mean_scale(double2* __restrict__ a, double s, int nx, int nzh,
 
 // ----------------------------------- launchers -----------------------------------
 
+int solve_lanes_per_chain(int ny);
+
 hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out) {
   const Dims& d = p->d;
   const size_t sh = (size_t)p->mode_stride * sizeof(double) + 3 * (size_t)d.ny * sizeof(double) +
                     12 * (size_t)d.ny * sizeof(cd);
   SP_PROF_BEGIN(p, KID_SOLVE_ADJ);
-  hipLaunchKernelGGL(k_stokes_solve_adj, dim3(d.nx * d.nzh), dim3(64), sh, p->stream, w, out,
-                     p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh, d.alpha, d.gamma, d.re,
-                     d.inv_dt);
+#define SP_SOLVE_ADJ_LAUNCH(EV)                                                                 \
+  hipLaunchKernelGGL(k_stokes_solve_adj<EV>, dim3(d.nx * d.nzh), dim3(64), sh, p->stream, w, out, \
+                     p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh, d.alpha, d.gamma,    \
+                     d.re, d.inv_dt)
+  switch (solve_lanes_per_chain(d.ny)) {
+    case 1: SP_SOLVE_ADJ_LAUNCH(1); break;
+    case 2: SP_SOLVE_ADJ_LAUNCH(2); break;
+    default: SP_SOLVE_ADJ_LAUNCH(3); break;
+  }
+#undef SP_SOLVE_ADJ_LAUNCH
   SP_PROF_END(p, KID_SOLVE_ADJ);
   return hipGetLastError();
 }
@@ -362,19 +392,32 @@ hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out) {
 hipError_t launch_adj_z(sp_plan* p, bool fp32) {
   const Dims& d = p->d;
   const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
-  int xc = (int)((64 * 1024) / (2 * 3 * d.pz * el));
+  int xc = (int)((48 * 1024 - d.pz * el) / (2 * 3 * d.pz * el));
   if (xc < 1) xc = 1;
   if (xc > d.px) xc = d.px;
   dim3 grid(d.ny, (d.px + xc - 1) / xc);
-  const size_t sh = 2 * (size_t)xc * 3 * d.pz * el;
+  const size_t sh = (2 * (size_t)xc * 3 + 1) * d.pz * el;
   const double scale = 1.0 / ((double)d.px * d.pz);
   SP_PROF_BEGIN(p, KID_ADJ_Z);
-  if (fp32)
-    hipLaunchKernelGGL(k_adj_z<float>, grid, dim3(256), sh, p->stream, (float2*)p->xp, p->base32,
-                       p->f_twz, p->fz, d.ny, d.px, d.nzm, xc, (float)scale);
-  else
-    hipLaunchKernelGGL(k_adj_z<double>, grid, dim3(256), sh, p->stream, (double2*)p->xp, p->base,
-                       p->d_twz, p->fz, d.ny, d.px, d.nzm, xc, scale);
+#define L32(PV)                                                                                   \
+  hipLaunchKernelGGL((k_adj_z<float, PV>), grid, dim3(256), sh, p->stream, (float2*)p->xp,        \
+                     p->base32, p->f_twz, p->fz, d.ny, d.px, d.nzm, xc, (float)scale)
+#define L64(PV)                                                                                   \
+  hipLaunchKernelGGL((k_adj_z<double, PV>), grid, dim3(256), sh, p->stream, (double2*)p->xp,      \
+                     p->base, p->d_twz, p->fz, d.ny, d.px, d.nzm, xc, scale)
+  switch (d.pz) {
+    case 12: if (fp32) L32(12); else L64(12); break;
+    case 24: if (fp32) L32(24); else L64(24); break;
+    case 36: if (fp32) L32(36); else L64(36); break;
+    case 48: if (fp32) L32(48); else L64(48); break;
+    case 72: if (fp32) L32(72); else L64(72); break;
+    case 96: if (fp32) L32(96); else L64(96); break;
+    case 144: if (fp32) L32(144); else L64(144); break;
+    case 192: if (fp32) L32(192); else L64(192); break;
+    default: if (fp32) L32(0); else L64(0); break;
+  }
+#undef L32
+#undef L64
   SP_PROF_END(p, KID_ADJ_Z);
   return hipGetLastError();
 }

@@ -111,4 +111,133 @@ __device__ typename V2<R>::T* lds_fft(typename V2<R>::T* a, typename V2<R>::T* b
   return a;
 }
 
+
+// ---------------------------------------------------------------------------
+// Compile-time-length variant: the radix sequence of P is fixed, so every
+// index computation folds to constants; twiddles come from a table tw[q] =
+// exp(-2 pi i q / P) (staged in LDS by the caller). Radix 2, 3, 4, 8.
+// ---------------------------------------------------------------------------
+template <typename C, typename R>
+__device__ inline void bfly4(C* v, R sign) {
+  const C s0 = cadd(v[0], v[2]);
+  const C s1 = csub(v[0], v[2]);
+  const C s2 = cadd(v[1], v[3]);
+  const C s3 = sidot(csub(v[1], v[3]), sign);
+  v[0] = cadd(s0, s2);
+  v[2] = csub(s0, s2);
+  v[1] = cadd(s1, s3);
+  v[3] = csub(s1, s3);
+}
+
+template <typename C, typename R>
+__device__ inline void bfly(C* v, int Rd, R sign) {
+  if (Rd == 2) {
+    const C a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if (Rd == 3) {
+    const R h = (R)0.86602540378443864676;  // sqrt(3)/2
+    const C t1 = cadd(v[1], v[2]);
+    const C d = csub(v[1], v[2]);
+    const C m = csub(v[0], cscale(t1, (R)0.5));
+    const C e = sidot(cscale(d, h), sign);
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd(m, e);
+    v[2] = csub(m, e);
+  } else if (Rd == 4) {
+    bfly4<C, R>(v, sign);
+  } else {  // 8: decimation in frequency, then two radix-4
+    const R c = (R)0.70710678118654752440;  // sqrt(1/2)
+    C s[4], d[4];
+    for (int k = 0; k < 4; ++k) {
+      s[k] = cadd(v[k], v[k + 4]);
+      d[k] = csub(v[k], v[k + 4]);
+    }
+    // d_k *= W8^k, W8 = exp(sign 2 pi i / 8)
+    d[1] = cmul(d[1], mk(c, sign * c));
+    d[2] = sidot(d[2], sign);
+    d[3] = cmul(d[3], mk(-c, sign * c));
+    bfly4<C, R>(s, sign);
+    bfly4<C, R>(d, sign);
+    for (int m = 0; m < 4; ++m) {
+      v[2 * m] = s[m];
+      v[2 * m + 1] = d[m];
+    }
+  }
+}
+
+template <int P, int RD, int NS, typename R>
+__device__ inline void fft_pass_c(const typename V2<R>::T* __restrict__ x,
+                                  typename V2<R>::T* __restrict__ y, int nl,
+                                  const typename V2<R>::T* __restrict__ tw, R sign) {
+  using C = typename V2<R>::T;
+  constexpr int NB = P / RD;
+  constexpr int TS = P / (NS * RD);
+  for (int t = threadIdx.x; t < nl * NB; t += blockDim.x) {
+    const int l = t / NB;
+    const int j = t - l * NB;
+    const int k = j % NS;
+    const C* xl = x + l * P;
+    C* yl = y + l * P;
+    C v[RD];
+#pragma unroll
+    for (int r = 0; r < RD; ++r) v[r] = xl[j + r * NB];
+    if (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < RD; ++r) {
+        C w = tw[k * r * TS];
+        if (sign > 0) w = conjc(w);
+        v[r] = cmul(v[r], w);
+      }
+    }
+    bfly<C, R>(v, RD, sign);
+    const int base = (j / NS) * NS * RD + k;
+#pragma unroll
+    for (int r = 0; r < RD; ++r) yl[base + r * NS] = v[r];
+  }
+  __syncthreads();
+}
+
+// Radix sequences of the supported compile-time lengths.
+template <int P>
+struct RadixSeq;
+template <> struct RadixSeq<12> { static constexpr int n = 2, r0 = 4, r1 = 3, r2 = 1, r3 = 1; };
+template <> struct RadixSeq<24> { static constexpr int n = 2, r0 = 8, r1 = 3, r2 = 1, r3 = 1; };
+template <> struct RadixSeq<36> { static constexpr int n = 3, r0 = 4, r1 = 3, r2 = 3, r3 = 1; };
+template <> struct RadixSeq<48> { static constexpr int n = 3, r0 = 4, r1 = 4, r2 = 3, r3 = 1; };
+template <> struct RadixSeq<72> { static constexpr int n = 3, r0 = 8, r1 = 3, r2 = 3, r3 = 1; };
+template <> struct RadixSeq<96> { static constexpr int n = 3, r0 = 8, r1 = 4, r2 = 3, r3 = 1; };
+template <> struct RadixSeq<144> { static constexpr int n = 4, r0 = 4, r1 = 4, r2 = 3, r3 = 3; };
+template <> struct RadixSeq<192> { static constexpr int n = 3, r0 = 8, r1 = 8, r2 = 3, r3 = 1; };
+
+// Batched FFT of nl lines of length P (line l at a[l*P]); returns the buffer
+// holding the result. P == 0 selects the runtime-length lds_fft.
+template <typename R, int P>
+__device__ typename V2<R>::T* fft_lines(typename V2<R>::T* a, typename V2<R>::T* b, int nl,
+                                        const FFTPlan1D& pl, const typename V2<R>::T* tw,
+                                        R sign) {
+  if constexpr (P == 0) {
+    return lds_fft<R>(a, b, nl, pl, tw, sign);
+  } else {
+    using S = RadixSeq<P>;
+    fft_pass_c<P, S::r0, 1, R>(a, b, nl, tw, sign);
+    fft_pass_c<P, S::r1, S::r0, R>(b, a, nl, tw, sign);
+    if constexpr (S::n == 2) {
+      return a;
+    } else if constexpr (S::n == 3) {
+      fft_pass_c<P, S::r2, S::r0 * S::r1, R>(a, b, nl, tw, sign);
+      return b;
+    } else {
+      fft_pass_c<P, S::r2, S::r0 * S::r1, R>(a, b, nl, tw, sign);
+      fft_pass_c<P, S::r3, S::r0 * S::r1 * S::r2, R>(b, a, nl, tw, sign);
+      return a;
+    }
+  }
+}
+
+// Supported compile-time lengths (others use the runtime path).
+inline bool fft_length_specialised(int P) {
+  return P == 12 || P == 24 || P == 36 || P == 48 || P == 72 || P == 96 || P == 144 || P == 192;
+}
+
 }  // namespace sp

@@ -19,6 +19,7 @@
 
 #include "device_common.h"
 #include "solve_core.h"
+#include "solve_wave.h"
 #include "sp_internal.h"
 
 namespace sp {
@@ -87,7 +88,7 @@ __global__ void __launch_bounds__(256)
 // plain != 0: output field f is input field f.
 // Block: (y, output field f, chunk of kc z-modes).
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, int PT>
 __global__ void __launch_bounds__(256)
     k_fft_x_inv(const typename V2<R>::T* __restrict__ yv, typename V2<R>::T* __restrict__ xp,
                 const typename V2<R>::T* __restrict__ tw, FFTPlan1D pl, int nx, int ny, int nzm,
@@ -97,10 +98,12 @@ __global__ void __launch_bounds__(256)
   const int px = pl.P;
   C* A = reinterpret_cast<C*>(smem_raw);
   C* B = A + kc * px;
+  C* twl = B + kc * px;
   const int y = blockIdx.x;
   const int f = blockIdx.y;
   const int kz0 = blockIdx.z * kc;
   const int nl = min(kc, nzm - kz0);
+  for (int t = threadIdx.x; t < px; t += blockDim.x) twl[t] = tw[t];
   for (int t = threadIdx.x; t < nl * px; t += blockDim.x) A[t] = mk((R)0, (R)0);
   __syncthreads();
   const size_t fs = (size_t)ny * nzm * nx;  // field stride in yv
@@ -133,7 +136,7 @@ __global__ void __launch_bounds__(256)
     A[l * px + pos] = val;
   }
   __syncthreads();
-  C* res = lds_fft<R>(A, B, nl, pl, tw, (R)1);
+  C* res = fft_lines<R, PT>(A, B, nl, pl, twl, (R)1);
   for (int t = threadIdx.x; t < nl * px; t += blockDim.x) {
     const int x = t / nl;
     const int l = t - x * nl;
@@ -149,7 +152,7 @@ __global__ void __launch_bounds__(256)
 // fields into `base`. The product is packed as (nx + i ny, nz), forward FFT,
 // unpacked and scaled by 1/(px pz).
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, int PT>
 __global__ void __launch_bounds__(256)
     k_z_product(const typename V2<R>::T* __restrict__ xp, typename V2<R>::T* __restrict__ np,
                 R* __restrict__ base, const typename V2<R>::T* __restrict__ tw, FFTPlan1D pl,
@@ -162,7 +165,9 @@ __global__ void __launch_bounds__(256)
   const int nxl = min(xc, px - x0);
   C* A = reinterpret_cast<C*>(smem_raw);
   C* B = A + xc * 3 * pz;
+  C* twl = B + xc * 3 * pz;
   const size_t fs = (size_t)ny * px * nzm;
+  for (int t = threadIdx.x; t < pz; t += blockDim.x) twl[t] = tw[t];
   for (int t = threadIdx.x; t < nxl * 3 * pz; t += blockDim.x) {
     const int m = t % pz;
     const int lj = t / pz;  // x_l * 3 + j
@@ -187,7 +192,7 @@ __global__ void __launch_bounds__(256)
     A[t] = val;
   }
   __syncthreads();
-  C* res = lds_fft<R>(A, B, nxl * 3, pl, tw, (R)1);
+  C* res = fft_lines<R, PT>(A, B, nxl * 3, pl, twl, (R)1);
   C* oth = (res == A) ? B : A;
   const size_t bs = (size_t)ny * px * pz;  // base field stride
   for (int t = threadIdx.x; t < nxl * pz; t += blockDim.x) {
@@ -223,7 +228,7 @@ __global__ void __launch_bounds__(256)
   }
   if (mode == 2) return;  // uniform across the block
   __syncthreads();
-  C* fin = lds_fft<R>(oth, res, nxl * 2, pl, tw, (R)-1);
+  C* fin = fft_lines<R, PT>(oth, res, nxl * 2, pl, twl, (R)-1);
   const size_t ns = (size_t)ny * px * nzm;
   for (int t = threadIdx.x; t < nxl * nzm; t += blockDim.x) {
     const int xl = t / nzm;
@@ -245,7 +250,7 @@ __global__ void __launch_bounds__(256)
 // fft_x_fwd: forward FFT along x of the three product fields, truncation to
 // the kept m_x (Nyquist zero). Block: (y, component, chunk of kc z-modes).
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, int PT>
 __global__ void __launch_bounds__(256)
     k_fft_x_fwd(const typename V2<R>::T* __restrict__ np, typename V2<R>::T* __restrict__ nv,
                 const typename V2<R>::T* __restrict__ tw, FFTPlan1D pl, int nx, int ny, int nzm,
@@ -255,17 +260,19 @@ __global__ void __launch_bounds__(256)
   const int px = pl.P;
   C* A = reinterpret_cast<C*>(smem_raw);
   C* B = A + kc * px;
+  C* twl = B + kc * px;
   const int y = blockIdx.x;
   const int c = blockIdx.y;
   const int kz0 = blockIdx.z * kc;
   const int nl = min(kc, nzm - kz0);
+  for (int t = threadIdx.x; t < px; t += blockDim.x) twl[t] = tw[t];
   for (int t = threadIdx.x; t < nl * px; t += blockDim.x) {
     const int x = t / nl;
     const int l = t - x * nl;
     A[l * px + x] = np[(((size_t)c * ny + y) * px + x) * nzm + kz0 + l];
   }
   __syncthreads();
-  C* res = lds_fft<R>(A, B, nl, pl, tw, (R)-1);
+  C* res = fft_lines<R, PT>(A, B, nl, pl, twl, (R)-1);
   for (int t = threadIdx.x; t < nl * nx; t += blockDim.x) {
     const int l = t / nx;
     const int i = t - l * nx;
@@ -338,10 +345,21 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------
-// stokes_solve: per-mode implicit solve (FP64). One 64-lane block per mode.
+// stokes_solve: per-mode implicit solve (FP64). One 64-lane wave per mode:
+// lanes 0-31 run parity class 0 (v even), lanes 32-63 class 1, each chain as
+// 32-lane scans (solve_wave.h).
 // out = S(g): velocity of (1/Re) Lap phi - phi/dt - grad p = -g, div phi = 0,
 // walls (wall_upper, wall_lower) for the (0,0) mode when inhomogeneous, else 0.
 // ---------------------------------------------------------------------------
+#define SP_FOR_PAR(par, body)                       \
+  _Pragma("unroll") for (int e_ = 0; e_ < E; ++e_) { \
+    const int n = (par) + 2 * (lane * E + e_);       \
+    if (n <= N) {                                    \
+      body                                           \
+    }                                                \
+  }
+
+template <int E>
 __global__ void __launch_bounds__(64)
     k_stokes_solve(const double2* __restrict__ g, double2* __restrict__ out,
                    const double* __restrict__ modedata, const double* __restrict__ hw_g,
@@ -358,8 +376,7 @@ __global__ void __launch_bounds__(64)
   cd* A = Fperp + n1;
   cd* divF = A + n1;
   cd* P = divF + n1;
-  cd* W = P + n1;
-  cd* Rv = W + n1;
+  cd* Rv = P + n1;
   cd* V = Rv + n1;
   cd* Rp = V + n1;
   cd* U = Rp + n1;
@@ -368,6 +385,8 @@ __global__ void __launch_bounds__(64)
   const int i = mode / nzh;
   const int j = mode - i * nzh;
   const int tid = threadIdx.x;
+  const int half = tid >> 5;
+  const int lane = tid & 31;
   const size_t cs = (size_t)nx * nzh * ny;  // component stride
   const size_t mo = ((size_t)i * nzh + j) * ny;
   const bool nyq = (i == nx / 2) || (j == nzh - 1);
@@ -388,6 +407,7 @@ __global__ void __launch_bounds__(64)
   const double k2 = kx * kx + kz * kz;
   const bool mean = (i == 0 && j == 0);
   const double k = sqrt(k2);
+  const double ik = mean ? 0.0 : 1.0 / k;
   const double lam = k2 + re * inv_dt;
   for (int n = tid; n < n1; n += 64) {
     cd fu, fv, fw;
@@ -400,57 +420,58 @@ __global__ void __launch_bounds__(64)
       fw = cd(re * c.x, re * c.y);
     }
     if (mean) {
-      Fpar[n] = fu;
-      Fperp[n] = fw;
-      Fv[n] = cd(0.0);
+      Rv[n] = -fu;  // (0,0): u and w solve Dirichlet Helmholtz problems
+      Rp[n] = -fw;
     } else {
-      Fpar[n] = (fu * kx + fw * kz) * (1.0 / k);
-      Fperp[n] = (fu * kz - fw * kx) * (1.0 / k);
+      Fpar[n] = (fu * kx + fw * kz) * ik;
+      Fperp[n] = (fu * kz - fw * kx) * ik;
       Fv[n] = fv;
     }
-    A[n] = cd(0.0);
-    W[n] = cd(0.0);
   }
   __syncthreads();
-  const int n1r = n1;
-  const ModeLayout L{n1r};
+  const ModeLayout L{n1};
   SweepView helm(rec + L.helm(), n1);
   SweepView pois(rec + L.pois(), n1);
-  if (tid < 2) {
-    if (mean) {
-      const int p = tid;
-      cd bu(0.0);
-      if (inhomogeneous) bu = cd(p == 0 ? 0.5 * (wu + wl) : 0.5 * (wu - wl));
-      for (int n = p; n <= N; n += 2) {
-        Rv[n] = -Fpar[n];
-        Rp[n] = -Fperp[n];
-      }
-      sweep_solve<cd>(helm, hw, N, p, Rv, bu, P, W);
-      sweep_solve<cd>(helm, hw, N, p, Rp, cd(0.0), U, W);
-    } else {
-      const int pv = tid;
-      const int po = 1 - pv;
-      deriv_parity<cd>(N, pv, Fv, A);
-      for (int n = po; n <= N; n += 2) divF[n] = mul_i(Fpar[n] * k) + A[n];
-      sweep_solve<cd>(pois, hw, N, po, divF, cd(0.0), P, W);
-      deriv_parity<cd>(N, po, P, A);
-      for (int n = pv; n <= N; n += 2) Rv[n] = A[n] - Fv[n];
-      sweep_solve<cd>(helm, hw, N, pv, Rv, cd(0.0), V, W);
-      cd la(0.0);
-      for (int n = pv; n <= N; n += 2) la = la + V[n] * ((double)n * n);
-      const int m = (N % 2 == pv) ? N : N - 1;
-      cd lb = V[m] * lam;
-      if (m == N - 1) lb = lb + P[N] * (2.0 * N);
-      const double* Mi = rec + L.minv() + 4 * pv;
-      const cd ca = -(la * Mi[0] + lb * Mi[1]);
-      const cd cb = -(la * Mi[2] + lb * Mi[3]);
-      const double* vdel = rec + L.vdel();
-      const double* vb = rec + L.vb();
-      for (int n = pv; n <= N; n += 2) V[n] = V[n] + ca * vdel[n] + cb * vb[n];
-      deriv_parity<cd>(N, pv, V, A);
-      for (int n = po; n <= N; n += 2) Rp[n] = -Fperp[n];
-      sweep_solve<cd>(helm, hw, N, po, Rp, cd(0.0), U, W);
-    }
+  if (mean) {
+    const int p = half;
+    cd bu(0.0);
+    if (inhomogeneous) bu = cd(p == 0 ? 0.5 * (wu + wl) : 0.5 * (wu - wl));
+    wsweep<E>(helm, hw, N, p, Rv, bu, P, lane);
+    wsweep<E>(helm, hw, N, p, Rp, cd(0.0), U, lane);
+  } else {
+    const int pv = half;
+    const int po = 1 - pv;
+    wderiv<E>(N, pv, Fv, A, lane);
+    __syncthreads();
+    SP_FOR_PAR(po, divF[n] = mul_i(Fpar[n] * k) + A[n];)
+    __syncthreads();
+    wsweep<E>(pois, hw, N, po, divF, cd(0.0), P, lane);
+    __syncthreads();
+    wderiv<E>(N, po, P, A, lane);
+    __syncthreads();
+    SP_FOR_PAR(pv, Rv[n] = A[n] - Fv[n];)
+    __syncthreads();
+    wsweep<E>(helm, hw, N, pv, Rv, cd(0.0), V, lane);
+    __syncthreads();
+    // influence correction: (c_delta, c_b) = -Minv (D v(1), tau definition)
+    cd la(0.0);
+    SP_FOR_PAR(pv, la = la + V[n] * ((double)n * n);)
+    la = sum32(la);
+    const int m = (N % 2 == pv) ? N : N - 1;
+    cd lb = V[m] * lam;
+    if (m == N - 1) lb = lb + P[N] * (2.0 * N);
+    const double* Mi = rec + L.minv() + 4 * pv;
+    const cd ca = -(la * Mi[0] + lb * Mi[1]);
+    const cd cb = -(la * Mi[2] + lb * Mi[3]);
+    const double* vdel = rec + L.vdel();
+    const double* vb = rec + L.vb();
+    __syncthreads();
+    SP_FOR_PAR(pv, V[n] = V[n] + ca * vdel[n] + cb * vb[n];)
+    __syncthreads();
+    wderiv<E>(N, pv, V, A, lane);
+    SP_FOR_PAR(po, Rp[n] = -Fperp[n];)
+    __syncthreads();
+    wsweep<E>(helm, hw, N, po, Rp, cd(0.0), U, lane);
   }
   __syncthreads();
   for (int n = tid; n < n1; n += 64) {
@@ -459,9 +480,9 @@ __global__ void __launch_bounds__(64)
       uo = P[n];
       wo = U[n];
     } else {
-      const cd upar = mul_i(A[n]) * (1.0 / k);
-      uo = (upar * kx + U[n] * kz) * (1.0 / k);
-      wo = (upar * kz - U[n] * kx) * (1.0 / k);
+      const cd upar = mul_i(A[n]) * ik;
+      uo = (upar * kx + U[n] * kz) * ik;
+      wo = (upar * kz - U[n] * kx) * ik;
       vo = V[n];
     }
     out[mo + n] = make_double2(uo.re, uo.im);
@@ -590,9 +611,23 @@ __global__ void k_unpack(const double* __restrict__ packed, double2* __restrict_
 
 // ----------------------------------- launchers -----------------------------------
 
+// Calls LAUNCH(P) with P a supported compile-time FFT length, or 0.
+#define SP_FFT_DISPATCH(PV, LAUNCH) \
+  switch (PV) {                     \
+    case 12: LAUNCH(12); break;     \
+    case 24: LAUNCH(24); break;     \
+    case 36: LAUNCH(36); break;     \
+    case 48: LAUNCH(48); break;     \
+    case 72: LAUNCH(72); break;     \
+    case 96: LAUNCH(96); break;     \
+    case 144: LAUNCH(144); break;   \
+    case 192: LAUNCH(192); break;   \
+    default: LAUNCH(0); break;      \
+  }
+
 static int chunk_for(int P, int total, size_t elem) {
-  // largest chunk whose two ping-pong buffers fit in 64 KiB of LDS
-  int k = (int)((64 * 1024) / (2 * P * elem));
+  // largest chunk whose two ping-pong buffers (plus twiddles) fit in 48 KiB of LDS
+  int k = (int)((48 * 1024 - P * elem) / (2 * P * elem));
   if (k < 1) k = 1;
   if (k > total) k = total;
   return k;
@@ -640,16 +675,23 @@ hipError_t launch_fft_x_inv_gen(sp_plan* p, const void* in, void* out, int nfiel
   const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
   const int kc = chunk_for(d.px, d.nzm, el);
   dim3 grid(d.ny, nfields, (d.nzm + kc - 1) / kc);
-  const size_t sh = 2 * (size_t)kc * d.px * el;
+  const size_t sh = (2 * (size_t)kc + 1) * d.px * el;
   SP_PROF_BEGIN(p, KID_FFT_X_INV);
-  if (fp32)
-    hipLaunchKernelGGL(k_fft_x_inv<float>, grid, dim3(256), sh, p->stream, (const float2*)in,
-                       (float2*)out, p->f_twx, p->fx, d.nx, d.ny, d.nzm, kc, (float)d.alpha,
-                       (float)d.gamma, plain);
-  else
-    hipLaunchKernelGGL(k_fft_x_inv<double>, grid, dim3(256), sh, p->stream, (const double2*)in,
-                       (double2*)out, p->d_twx, p->fx, d.nx, d.ny, d.nzm, kc, d.alpha, d.gamma,
-                       plain);
+#define L32(PV)                                                                                 \
+  hipLaunchKernelGGL((k_fft_x_inv<float, PV>), grid, dim3(256), sh, p->stream, (const float2*)in, \
+                     (float2*)out, p->f_twx, p->fx, d.nx, d.ny, d.nzm, kc, (float)d.alpha,      \
+                     (float)d.gamma, plain)
+#define L64(PV)                                                                          \
+  hipLaunchKernelGGL((k_fft_x_inv<double, PV>), grid, dim3(256), sh, p->stream,          \
+                     (const double2*)in, (double2*)out, p->d_twx, p->fx, d.nx, d.ny, d.nzm, kc, \
+                     d.alpha, d.gamma, plain)
+  if (fp32) {
+    SP_FFT_DISPATCH(d.px, L32)
+  } else {
+    SP_FFT_DISPATCH(d.px, L64)
+  }
+#undef L32
+#undef L64
   SP_PROF_END(p, KID_FFT_X_INV);
   return hipGetLastError();
 }
@@ -661,21 +703,28 @@ hipError_t launch_fft_x_inv(sp_plan* p, bool fp32) {
 hipError_t launch_z_product(sp_plan* p, int mode, bool fp32) {
   const Dims& d = p->d;
   const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
-  int xc = (int)((64 * 1024) / (2 * 3 * d.pz * el));
+  int xc = (int)((48 * 1024 - d.pz * el) / (2 * 3 * d.pz * el));
   if (xc < 1) xc = 1;
   if (xc > d.px) xc = d.px;
   dim3 grid(d.ny, (d.px + xc - 1) / xc);
-  const size_t sh = 2 * (size_t)xc * 3 * d.pz * el;
+  const size_t sh = (2 * (size_t)xc * 3 + 1) * d.pz * el;
   const double scale = 1.0 / ((double)d.px * d.pz);
   SP_PROF_BEGIN(p, KID_Z_PRODUCT);
-  if (fp32)
-    hipLaunchKernelGGL(k_z_product<float>, grid, dim3(256), sh, p->stream, (const float2*)p->xp,
-                       (float2*)p->np, p->base32, p->f_twz, p->fz, d.ny, d.px, d.nzm, xc, mode,
-                       (float)scale);
-  else
-    hipLaunchKernelGGL(k_z_product<double>, grid, dim3(256), sh, p->stream, (const double2*)p->xp,
-                       (double2*)p->np, p->base, p->d_twz, p->fz, d.ny, d.px, d.nzm, xc, mode,
-                       scale);
+#define L32(PV)                                                                                  \
+  hipLaunchKernelGGL((k_z_product<float, PV>), grid, dim3(256), sh, p->stream,                   \
+                     (const float2*)p->xp, (float2*)p->np, p->base32, p->f_twz, p->fz, d.ny, d.px, \
+                     d.nzm, xc, mode, (float)scale)
+#define L64(PV)                                                                                   \
+  hipLaunchKernelGGL((k_z_product<double, PV>), grid, dim3(256), sh, p->stream,                   \
+                     (const double2*)p->xp, (double2*)p->np, p->base, p->d_twz, p->fz, d.ny, d.px, \
+                     d.nzm, xc, mode, scale)
+  if (fp32) {
+    SP_FFT_DISPATCH(d.pz, L32)
+  } else {
+    SP_FFT_DISPATCH(d.pz, L64)
+  }
+#undef L32
+#undef L64
   SP_PROF_END(p, KID_Z_PRODUCT);
   return hipGetLastError();
 }
@@ -685,14 +734,21 @@ hipError_t launch_fft_x_fwd_gen(sp_plan* p, const void* in, void* out, int nfiel
   const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
   const int kc = chunk_for(d.px, d.nzm, el);
   dim3 grid(d.ny, nfields, (d.nzm + kc - 1) / kc);
-  const size_t sh = 2 * (size_t)kc * d.px * el;
+  const size_t sh = (2 * (size_t)kc + 1) * d.px * el;
   SP_PROF_BEGIN(p, KID_FFT_X_FWD);
-  if (fp32)
-    hipLaunchKernelGGL(k_fft_x_fwd<float>, grid, dim3(256), sh, p->stream, (const float2*)in,
-                       (float2*)out, p->f_twx, p->fx, d.nx, d.ny, d.nzm, kc);
-  else
-    hipLaunchKernelGGL(k_fft_x_fwd<double>, grid, dim3(256), sh, p->stream, (const double2*)in,
-                       (double2*)out, p->d_twx, p->fx, d.nx, d.ny, d.nzm, kc);
+#define L32(PV)                                                                                 \
+  hipLaunchKernelGGL((k_fft_x_fwd<float, PV>), grid, dim3(256), sh, p->stream, (const float2*)in, \
+                     (float2*)out, p->f_twx, p->fx, d.nx, d.ny, d.nzm, kc)
+#define L64(PV)                                                                       \
+  hipLaunchKernelGGL((k_fft_x_fwd<double, PV>), grid, dim3(256), sh, p->stream,       \
+                     (const double2*)in, (double2*)out, p->d_twx, p->fx, d.nx, d.ny, d.nzm, kc)
+  if (fp32) {
+    SP_FFT_DISPATCH(d.px, L32)
+  } else {
+    SP_FFT_DISPATCH(d.px, L64)
+  }
+#undef L32
+#undef L64
   SP_PROF_END(p, KID_FFT_X_FWD);
   return hipGetLastError();
 }
@@ -718,14 +774,23 @@ hipError_t launch_analysis_rhs(sp_plan* p, const double2* x, double a, double2* 
   return hipGetLastError();
 }
 
+int solve_lanes_per_chain(int ny) { return ((ny - 1) / 2 + 1 + 31) / 32; }
+
 hipError_t launch_stokes_solve(sp_plan* p, const double2* g, double2* out, int inhomogeneous) {
   const Dims& d = p->d;
   const size_t sh = (size_t)p->mode_stride * sizeof(double) + 3 * (size_t)d.ny * sizeof(double) +
-                    11 * (size_t)d.ny * sizeof(cd);
+                    10 * (size_t)d.ny * sizeof(cd);
   SP_PROF_BEGIN(p, KID_SOLVE);
-  hipLaunchKernelGGL(k_stokes_solve, dim3(d.nx * d.nzh), dim3(64), sh, p->stream, g, out,
-                     p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh, d.alpha, d.gamma, d.re,
-                     d.inv_dt, d.wall_upper, d.wall_lower, inhomogeneous);
+#define SP_SOLVE_LAUNCH(EV)                                                                    \
+  hipLaunchKernelGGL(k_stokes_solve<EV>, dim3(d.nx * d.nzh), dim3(64), sh, p->stream, g, out, \
+                     p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh, d.alpha, d.gamma,  \
+                     d.re, d.inv_dt, d.wall_upper, d.wall_lower, inhomogeneous)
+  switch (solve_lanes_per_chain(d.ny)) {
+    case 1: SP_SOLVE_LAUNCH(1); break;
+    case 2: SP_SOLVE_LAUNCH(2); break;
+    default: SP_SOLVE_LAUNCH(3); break;
+  }
+#undef SP_SOLVE_LAUNCH
   SP_PROF_END(p, KID_SOLVE);
   return hipGetLastError();
 }

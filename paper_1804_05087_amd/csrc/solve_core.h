@@ -50,9 +50,6 @@ __host__ __device__ inline cd operator*(cd a, double s) { return cd(a.re * s, a.
 __host__ __device__ inline cd operator*(double s, cd a) { return cd(a.re * s, a.im * s); }
 __host__ __device__ inline cd mul_i(cd a) { return cd(-a.im, a.re); }  // i * a
 
-// Scalar helpers so the templates work for double and cd.
-__host__ __device__ inline double fma_s(double a, double s, double b) { return a * s + b; }
-
 // Offsets inside a sweep block of n1 = N + 1: inv_den, cc, q, Q, inv_sum_q[2].
 struct SweepView {
   const double* inv_den;
@@ -111,60 +108,6 @@ __host__ __device__ inline void deriv_parity(int N, int pa, const T* a, T* b) {
   }
   if (pa == 1) b[0] = b[0] * 0.5;
   if (nmax + 1 <= N) b[nmax + 1] = T(0.0);
-}
-
-// Transpose of sweep_solve (with beta = 0) for the parity-p chain: given gbar
-// (parity-p entries), writes rbar = H^T gbar into the parity-p entries of rbar
-// with index <= N-2 (other entries of that parity are set to zero).
-// work: scratch of length n1.
-template <typename T>
-__host__ __device__ inline void sweep_solve_T(SweepView sw, const double* hw, int N, int p,
-                                              const T* gbar, T* rbar, T* work) {
-  const int n1 = N + 1;
-  const double* w1 = hw;
-  const double* w2 = hw + n1;
-  const double* w3 = hw + 2 * n1;
-  const int nmax = top_index(N, p);
-  // g_n = P_n + Q_n g0, g_p = g0, g0 = -inv_sum * sum_n P_n
-  T g0b = gbar[p];
-  for (int n = p + 2; n <= nmax; n += 2) g0b = g0b + gbar[n] * sw.Q[n];
-  const T corr = g0b * (-sw.inv_sum[p]);
-  // Pbar_n = gbar_n + corr ; P_n = p_n + q_n P_{n-2}  =>  pbar_n = Pbar_n + q_{n+2} pbar_{n+2}
-  T pb_next = T(0.0);
-  for (int n = nmax; n >= p + 2; n -= 2) {
-    T pb = gbar[n] + corr;
-    if (n + 2 <= nmax) pb = pb + pb_next * sw.q[n + 2];
-    work[n] = pb;
-    pb_next = pb;
-  }
-  // p_n = inv_den_n (d_n - cc_n p_{n+2})  (descending)  =>  ascending transpose
-  T y_prev = T(0.0);
-  for (int n = p + 2; n <= nmax; n += 2) {
-    T y = work[n];
-    if (n - 2 >= p + 2) y = y - y_prev * (sw.inv_den[n - 2] * sw.cc[n - 2]);
-    work[n] = y * sw.inv_den[n];  // dbar_n
-    y_prev = y;
-  }
-  for (int n = p; n <= N; n += 2) rbar[n] = T(0.0);
-  // d_n = w1_n r_{n-2} + w2_n r_n + w3_n r_{n+2}
-  for (int n = p + 2; n <= nmax; n += 2) {
-    const T db = work[n];
-    rbar[n - 2] = rbar[n - 2] + db * w1[n];
-    if (n <= N - 2) rbar[n] = rbar[n] + db * w2[n];
-    if (n + 2 <= N - 2) rbar[n + 2] = rbar[n + 2] + db * w3[n];
-  }
-}
-
-// abar = D^T bbar where bbar holds parity-pb entries (n <= N-1 used); abar gets
-// the parity 1-pb entries: (D^T b)_m = m * sum_{n < m, n = pb mod 2} (2/c_n) b_n.
-template <typename T>
-__host__ __device__ inline void deriv_T_parity(int N, int pb, const T* bbar, T* abar) {
-  const int pa = 1 - pb;
-  T S = T(0.0);
-  for (int m = pa; m <= N; m += 2) {
-    if (m >= 1) S = S + bbar[m - 1] * ((m - 1 == 0) ? 1.0 : 2.0);
-    abar[m] = S * (double)m;
-  }
 }
 
 // Precomputes the sweep block of the operator (D^2 - lam) for both parities.
