@@ -38,18 +38,23 @@ namespace sp {
     }                                                \
   }
 
-template <int E>
+// When FUSED, the adjoint of the Chebyshev analysis is applied as well:
+// nvout[c][j][kz][mx] = sum_n Tinv[n][j] out_c[n] (a DCT-I with a 2N-entry
+// cosine table), the input of the adjoint transform chain.
+template <int E, bool FUSED>
 __global__ void __launch_bounds__(64)
     k_stokes_solve_adj(const double2* __restrict__ w, double2* __restrict__ out,
                        const double* __restrict__ modedata, const double* __restrict__ hw_g,
                        int stride, int nx, int ny, int nzh, double alpha, double gamma, double re,
-                       double inv_dt) {
+                       double inv_dt, double2* __restrict__ nvout,
+                       const double* __restrict__ ctab_g) {
   extern __shared__ unsigned char smem_raw[];
   const int N = ny - 1;
   const int n1 = ny;
   double* rec = reinterpret_cast<double*>(smem_raw);
   double* hw = rec + stride;
-  cd* Upb = reinterpret_cast<cd*>(hw + 3 * n1);  // adjoint of u_par
+  double* ctab = hw + 3 * n1;
+  cd* Upb = reinterpret_cast<cd*>(ctab + 2 * N);  // adjoint of u_par
   cd* Ub = Upb + n1;                              // adjoint of u_perp
   cd* Vb = Ub + n1;                               // adjoint of v
   cd* A = Vb + n1;
@@ -82,6 +87,8 @@ __global__ void __launch_bounds__(64)
   const double* src = modedata + (size_t)mode * stride;
   for (int t = tid; t < stride; t += 64) rec[t] = src[t];
   for (int t = tid; t < 3 * n1; t += 64) hw[t] = hw_g[t];
+  if constexpr (FUSED)
+    for (int t = tid; t < 2 * N; t += 64) ctab[t] = ctab_g[t];
   const int mxv = (i < nx / 2) ? i : i - nx;
   const double kx = alpha * mxv;
   const double kz = gamma * j;
@@ -177,6 +184,31 @@ __global__ void __launch_bounds__(64)
     out[mo + n] = make_double2(gu.re, gu.im);
     out[cs + mo + n] = make_double2(gv.re, gv.im);
     out[2 * cs + mo + n] = make_double2(gw.re, gw.im);
+    if constexpr (FUSED) {
+      A[n] = gu;
+      Tm[n] = gv;
+      W[n] = gw;
+    }
+  }
+  if constexpr (FUSED) {
+    __syncthreads();
+    const int nzm = nzh - 1;
+    for (int jj = tid; jj < n1; jj += 64) {
+      cd s0(0.0), s1(0.0), s2(0.0);
+      int q = 0;
+      for (int n = 0; n <= N - 2; ++n) {
+        const double cw = ctab[q] * ((n == 0) ? 0.5 : 1.0);
+        s0 = s0 + A[n] * cw;
+        s1 = s1 + Tm[n] * cw;
+        s2 = s2 + W[n] * cw;
+        q += jj;
+        if (q >= 2 * N) q -= 2 * N;
+      }
+      const double sc = ((jj == 0 || jj == N) ? 1.0 : 2.0) / N;
+      nvout[((size_t)(0 * ny + jj) * nzm + j) * nx + i] = make_double2(s0.re * sc, s0.im * sc);
+      nvout[((size_t)(1 * ny + jj) * nzm + j) * nx + i] = make_double2(s1.re * sc, s1.im * sc);
+      nvout[((size_t)(2 * ny + jj) * nzm + j) * nx + i] = make_double2(s2.re * sc, s2.im * sc);
+    }
   }
 }
 
@@ -370,19 +402,24 @@ __global__ void k_mean_scale(double2* __restrict__ a, double s, int nx, int nzh,
 
 int solve_lanes_per_chain(int ny);
 
-hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out) {
+hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out, void* nvout) {
   const Dims& d = p->d;
   const size_t sh = (size_t)p->mode_stride * sizeof(double) + 3 * (size_t)d.ny * sizeof(double) +
-                    12 * (size_t)d.ny * sizeof(cd);
+                    2 * (size_t)d.N * sizeof(double) + 12 * (size_t)d.ny * sizeof(cd);
   SP_PROF_BEGIN(p, KID_SOLVE_ADJ);
-#define SP_SOLVE_ADJ_LAUNCH(EV)                                                                 \
-  hipLaunchKernelGGL(k_stokes_solve_adj<EV>, dim3(d.nx * d.nzh), dim3(64), sh, p->stream, w, out, \
-                     p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh, d.alpha, d.gamma,    \
-                     d.re, d.inv_dt)
-  switch (solve_lanes_per_chain(d.ny)) {
-    case 1: SP_SOLVE_ADJ_LAUNCH(1); break;
-    case 2: SP_SOLVE_ADJ_LAUNCH(2); break;
-    default: SP_SOLVE_ADJ_LAUNCH(3); break;
+#define SP_SOLVE_ADJ_LAUNCH(EV, FU)                                                           \
+  hipLaunchKernelGGL((k_stokes_solve_adj<EV, FU>), dim3(d.nx * d.nzh), dim3(64), sh, p->stream, \
+                     w, out, p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh, d.alpha,     \
+                     d.gamma, d.re, d.inv_dt, (double2*)nvout, p->d_ctab)
+  const int ev = solve_lanes_per_chain(d.ny);
+  if (nvout) {
+    if (ev == 1) SP_SOLVE_ADJ_LAUNCH(1, true);
+    else if (ev == 2) SP_SOLVE_ADJ_LAUNCH(2, true);
+    else SP_SOLVE_ADJ_LAUNCH(3, true);
+  } else {
+    if (ev == 1) SP_SOLVE_ADJ_LAUNCH(1, false);
+    else if (ev == 2) SP_SOLVE_ADJ_LAUNCH(2, false);
+    else SP_SOLVE_ADJ_LAUNCH(3, false);
   }
 #undef SP_SOLVE_ADJ_LAUNCH
   SP_PROF_END(p, KID_SOLVE_ADJ);
@@ -464,8 +501,12 @@ sp_status vjp_lin(sp_plan* p, int op, const double2* w, double2* out) {
   SP_TRY_HIP(hipMemcpyAsync(p->t1, w, n * sizeof(double2), hipMemcpyDeviceToDevice, p->stream),
              "copy w");
   SP_TRY_HIP(launch_mean_scale(p, p->t1, 2.0), "mean_scale");
-  SP_TRY_HIP(launch_stokes_solve_adj(p, p->t1, p->t2), "stokes_solve_adj");
-  SP_TRY_HIP(launch_synth_tab(p, p->t2, 1, p->nv, fp32), "analysis^T");
+  if (fp32) {
+    SP_TRY_HIP(launch_stokes_solve_adj(p, p->t1, p->t2, nullptr), "stokes_solve_adj");
+    SP_TRY_HIP(launch_synth_tab(p, p->t2, 1, p->nv, fp32), "analysis^T");
+  } else {
+    SP_TRY_HIP(launch_stokes_solve_adj(p, p->t1, p->t2, p->nv), "stokes_solve_adj+analysis^T");
+  }
   SP_TRY_HIP(launch_fft_x_inv_gen(p, p->nv, p->xp, 3, 1, fp32), "pad+ifft_x");
   SP_TRY_HIP(launch_adj_z(p, fp32), "adj_z");
   SP_TRY_HIP(launch_fft_x_fwd_gen(p, p->xp, p->yv, 6, fp32), "fft_x+truncate");

@@ -85,6 +85,35 @@ __global__ void k_scale(const double2* __restrict__ y, double s, double2* __rest
     x[t] = make_double2(s * y[t].x, s * y[t].y);
 }
 
+// Makes the m_z = 0 plane exactly Hermitian (entry at -m_x := conjugate of the
+// one at +m_x, (0,0) real) and zeroes Nyquist entries, so that Krylov vectors
+// stay in the real vector space the packed product is defined on.
+__global__ void k_hermitian(double2* __restrict__ a, int nx, int ny, int nzh) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = 3 * nx * ny;  // (component, i, n) in the m_z = 0 plane
+  if (t < total) {
+    const int n = t % ny;
+    const int i = (t / ny) % nx;
+    const int c = t / (ny * nx);
+    const size_t o = (((size_t)c * nx + i) * nzh + 0) * ny + n;
+    if (i == 0) {
+      a[o].y = 0.0;
+    } else if (i == nx / 2) {
+      a[o] = make_double2(0.0, 0.0);
+    } else if (i < nx / 2) {
+      const size_t om = (((size_t)c * nx + (nx - i)) * nzh + 0) * ny + n;
+      a[om] = make_double2(a[o].x, -a[o].y);
+    }
+  }
+  // Nyquist m_z column
+  if (t < 3 * nx * ny) {
+    const int n = t % ny;
+    const int i = (t / ny) % nx;
+    const int c = t / (ny * nx);
+    a[(((size_t)c * nx + i) * nzh + (nzh - 1)) * ny + n] = make_double2(0.0, 0.0);
+  }
+}
+
 static int nblocks_for(size_t n) {
   size_t b = (n + 255) / 256;
   if (b > 1024) b = 1024;
@@ -114,6 +143,15 @@ hipError_t launch_multiaxpy(sp_plan* p, const double2* V, int nvec, const double
   hipLaunchKernelGGL(k_multiaxpy, dim3(nblocks_for(n)), dim3(256), 0, p->stream, V, nvec, h, alpha,
                      beta, w, n);
   SP_PROF_END(p, KID_MULTIAXPY);
+  return hipGetLastError();
+}
+
+hipError_t launch_hermitian(sp_plan* p, double2* a) {
+  const int total = 3 * p->d.nx * p->d.ny;
+  SP_PROF_BEGIN(p, KID_SCALE);
+  hipLaunchKernelGGL(k_hermitian, dim3((total + 255) / 256), dim3(256), 0, p->stream, a, p->d.nx,
+                     p->d.ny, p->d.nzh);
+  SP_PROF_END(p, KID_SCALE);
   return hipGetLastError();
 }
 

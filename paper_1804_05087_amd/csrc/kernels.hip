@@ -359,18 +359,25 @@ __global__ void __launch_bounds__(256)
     }                                                \
   }
 
-template <int E>
+// When FUSED, the right-hand side is formed here from the y-valued product
+// fields nv ([3][ny][nz/2][nx]): g = Tinv nv + xa * x (the Chebyshev analysis,
+// a DCT-I evaluated with a 2N-entry cosine table), so the per-mode column of
+// the nonlinear term never makes a round trip through a canonical buffer.
+template <int E, bool FUSED>
 __global__ void __launch_bounds__(64)
     k_stokes_solve(const double2* __restrict__ g, double2* __restrict__ out,
                    const double* __restrict__ modedata, const double* __restrict__ hw_g,
                    int stride, int nx, int ny, int nzh, double alpha, double gamma, double re,
-                   double inv_dt, double wu, double wl, int inhomogeneous) {
+                   double inv_dt, double wu, double wl, int inhomogeneous,
+                   const double2* __restrict__ nv, const double2* __restrict__ x, double xa,
+                   const double* __restrict__ ctab_g) {
   extern __shared__ unsigned char smem_raw[];
   const int N = ny - 1;
   const int n1 = ny;
   double* rec = reinterpret_cast<double*>(smem_raw);
   double* hw = rec + stride;
-  cd* Fpar = reinterpret_cast<cd*>(hw + 3 * n1);
+  double* ctab = hw + 3 * n1;                        // cos(pi q / N), q < 2N (FUSED only)
+  cd* Fpar = reinterpret_cast<cd*>(ctab + 2 * N);
   cd* Fv = Fpar + n1;
   cd* Fperp = Fv + n1;
   cd* A = Fperp + n1;
@@ -380,6 +387,7 @@ __global__ void __launch_bounds__(64)
   cd* V = Rv + n1;
   cd* Rp = V + n1;
   cd* U = Rp + n1;
+  cd* col = U + n1;  // [3][n1] staged y-values of the mode (FUSED only)
 
   const int mode = blockIdx.x;
   const int i = mode / nzh;
@@ -409,15 +417,46 @@ __global__ void __launch_bounds__(64)
   const double k = sqrt(k2);
   const double ik = mean ? 0.0 : 1.0 / k;
   const double lam = k2 + re * inv_dt;
+  if constexpr (FUSED) {
+    // stage the three y-valued columns of this mode (in the Fpar/Fv/Fperp slots)
+    const int nzm = nzh - 1;
+    for (int t = tid; t < 2 * N; t += 64) ctab[t] = ctab_g[t];
+    for (int t = tid; t < 3 * n1; t += 64) {
+      const int c = t / n1;
+      const int jj = t - c * n1;
+      const double2 v = nv[(((size_t)c * ny + jj) * nzm + j) * nx + i];
+      col[t] = cd(v.x, v.y);
+    }
+    __syncthreads();
+  }
   for (int n = tid; n < n1; n += 64) {
     cd fu, fv, fw;
     if (n <= N - 2) {
-      const double2 a = g[mo + n];
-      const double2 b = g[cs + mo + n];
-      const double2 c = g[2 * cs + mo + n];
-      fu = cd(re * a.x, re * a.y);
-      fv = cd(re * b.x, re * b.y);
-      fw = cd(re * c.x, re * c.y);
+      if constexpr (FUSED) {
+        // a_n = 2/(N cb_n) sum_j f_j cos(pi n j / N) / cb_j, cb_0 = cb_N = 2
+        cd s0(0.0), s1(0.0), s2(0.0);
+        int q = 0;
+        for (int jj = 0; jj <= N; ++jj) {
+          const double cw = ctab[q] * ((jj == 0 || jj == N) ? 0.5 : 1.0);
+          s0 = s0 + col[jj] * cw;
+          s1 = s1 + col[n1 + jj] * cw;
+          s2 = s2 + col[2 * n1 + jj] * cw;
+          q += n;
+          if (q >= 2 * N) q -= 2 * N;
+        }
+        const double sc = ((n == 0) ? 1.0 : 2.0) / N;
+        const double2 xa0 = x[mo + n], xa1 = x[cs + mo + n], xa2 = x[2 * cs + mo + n];
+        fu = (s0 * sc + cd(xa * xa0.x, xa * xa0.y)) * re;
+        fv = (s1 * sc + cd(xa * xa1.x, xa * xa1.y)) * re;
+        fw = (s2 * sc + cd(xa * xa2.x, xa * xa2.y)) * re;
+      } else {
+        const double2 a = g[mo + n];
+        const double2 b = g[cs + mo + n];
+        const double2 c = g[2 * cs + mo + n];
+        fu = cd(re * a.x, re * a.y);
+        fv = cd(re * b.x, re * b.y);
+        fw = cd(re * c.x, re * c.y);
+      }
     }
     if (mean) {
       Rv[n] = -fu;  // (0,0): u and w solve Dirichlet Helmholtz problems
@@ -779,12 +818,35 @@ int solve_lanes_per_chain(int ny) { return ((ny - 1) / 2 + 1 + 31) / 32; }
 hipError_t launch_stokes_solve(sp_plan* p, const double2* g, double2* out, int inhomogeneous) {
   const Dims& d = p->d;
   const size_t sh = (size_t)p->mode_stride * sizeof(double) + 3 * (size_t)d.ny * sizeof(double) +
-                    10 * (size_t)d.ny * sizeof(cd);
+                    2 * (size_t)d.N * sizeof(double) + 10 * (size_t)d.ny * sizeof(cd);
   SP_PROF_BEGIN(p, KID_SOLVE);
-#define SP_SOLVE_LAUNCH(EV)                                                                    \
-  hipLaunchKernelGGL(k_stokes_solve<EV>, dim3(d.nx * d.nzh), dim3(64), sh, p->stream, g, out, \
-                     p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh, d.alpha, d.gamma,  \
-                     d.re, d.inv_dt, d.wall_upper, d.wall_lower, inhomogeneous)
+#define SP_SOLVE_LAUNCH(EV)                                                                      \
+  hipLaunchKernelGGL((k_stokes_solve<EV, false>), dim3(d.nx * d.nzh), dim3(64), sh, p->stream, g, \
+                     out, p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh, d.alpha,         \
+                     d.gamma, d.re, d.inv_dt, d.wall_upper, d.wall_lower, inhomogeneous, nullptr,  \
+                     nullptr, 0.0, nullptr)
+  switch (solve_lanes_per_chain(d.ny)) {
+    case 1: SP_SOLVE_LAUNCH(1); break;
+    case 2: SP_SOLVE_LAUNCH(2); break;
+    default: SP_SOLVE_LAUNCH(3); break;
+  }
+#undef SP_SOLVE_LAUNCH
+  SP_PROF_END(p, KID_SOLVE);
+  return hipGetLastError();
+}
+
+// Chebyshev analysis of p->nv fused into the solve: out = S(Tinv nv + xa * x).
+hipError_t launch_analysis_solve(sp_plan* p, const double2* x, double xa, double2* out,
+                                 int inhomogeneous) {
+  const Dims& d = p->d;
+  const size_t sh = (size_t)p->mode_stride * sizeof(double) + 3 * (size_t)d.ny * sizeof(double) +
+                    2 * (size_t)d.N * sizeof(double) + 13 * (size_t)d.ny * sizeof(cd);
+  SP_PROF_BEGIN(p, KID_SOLVE);
+#define SP_SOLVE_LAUNCH(EV)                                                                     \
+  hipLaunchKernelGGL((k_stokes_solve<EV, true>), dim3(d.nx * d.nzh), dim3(64), sh, p->stream,   \
+                     nullptr, out, p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh,        \
+                     d.alpha, d.gamma, d.re, d.inv_dt, d.wall_upper, d.wall_lower, inhomogeneous, \
+                     (const double2*)p->nv, x, xa, p->d_ctab)
   switch (solve_lanes_per_chain(d.ny)) {
     case 1: SP_SOLVE_LAUNCH(1); break;
     case 2: SP_SOLVE_LAUNCH(2); break;

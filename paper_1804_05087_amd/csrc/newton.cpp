@@ -179,6 +179,7 @@ extern "C" sp_status sp_newton_gmres(sp_plan* p, double* u_inout, const sp_newto
     const double beta = std::sqrt(b2);
     if (!std::isfinite(beta)) return set_error(p, SP_ERR_NONFINITE, "residual is not finite");
     SP_TRY_HIP(launch_scale(p, r, 1.0 / beta, W.V), "scale");
+    SP_TRY_HIP(launch_hermitian(p, W.V), "hermitian");
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(gv.begin(), gv.end(), 0.0);
     gv[0] = beta;
@@ -196,6 +197,7 @@ extern "C" sp_status sp_newton_gmres(sp_plan* p, double* u_inout, const sp_newto
                    "axpby");
       }
       rep->total_actions += 1;
+      SP_TRY_HIP(launch_hermitian(p, W.w), "hermitian");
       // CGS2
       SP_TRY_HIP(launch_multidot(p, W.V, k + 1, W.w, W.partial, W.h1, nullptr), "multidot");
       SP_TRY_HIP(launch_multiaxpy(p, W.V, k + 1, W.h1, -1.0, 1.0, W.w), "multiaxpy");

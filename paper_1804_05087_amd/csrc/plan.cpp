@@ -205,7 +205,7 @@ static std::vector<F> convert(const std::vector<D>& v) {
 static void free_plan(sp_plan* p) {
   void* ptrs[] = {p->d_T,   p->d_TD,  p->d_Tinv, p->d_G,    p->d_hw,   p->d_mode, p->d_twx,
                   p->d_twz, p->f_twx, p->f_twz,  p->f_T,    p->f_TD,   p->f_Tinv, p->d_scratch,
-                  p->d_TinvT, p->f_TinvT};
+                  p->d_TinvT, p->f_TinvT, p->d_ctab};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (p->h_partial) (void)hipHostFree(p->h_partial);
@@ -302,6 +302,13 @@ extern "C" sp_status sp_plan_create(const sp_params* prm, void* hip_stream, sp_p
       return fail(s);
   }
   if ((s = build_mode_data(p))) return fail(s);
+  {
+    std::vector<double> ctab(2 * d.N);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int q = 0; q < 2 * d.N; ++q) ctab[q] = (double)cosl(pi * (long double)q / (long double)d.N);
+    if ((s = upload(p, (void**)&p->d_ctab, ctab.data(), ctab.size() * sizeof(double), "ctab")))
+      return fail(s);
+  }
 
   // scratch: one allocation carved into 256-byte aligned pieces
   const size_t cz = sizeof(double2);

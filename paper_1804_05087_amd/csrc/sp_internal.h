@@ -55,6 +55,7 @@ struct sp_plan {
   double* d_Tinv = nullptr;   // [ny][ny] analysis
   double* d_G = nullptr;      // [ny][ny] Gram matrix int T_n T_m
   double* d_hw = nullptr;     // [3][ny] Helmholtz right-hand-side weights
+  double* d_ctab = nullptr;   // [2N] cos(pi q / N) for the fused Chebyshev analysis
   double* d_mode = nullptr;   // per-mode solve records
   int mode_stride = 0;
   double2* d_twx = nullptr;   // [px] exp(-2 pi i k / px)
@@ -114,12 +115,16 @@ hipError_t launch_fft_x_inv_gen(sp_plan* p, const void* in, void* out, int nfiel
                                 bool fp32);
 hipError_t launch_fft_x_fwd_gen(sp_plan* p, const void* in, void* out, int nfields, bool fp32);
 // adjoint kernels (adjoint.hip)
-hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out);
+// nvout != NULL: also write Tinv^T out in the nv layout (FP64 path)
+hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out, void* nvout);
 hipError_t launch_adj_z(sp_plan* p, bool fp32);
 hipError_t launch_adj_synth(sp_plan* p, const double2* x, double a, double2* out, bool fp32);
 hipError_t launch_mean_scale(sp_plan* p, double2* a, double s);
 hipError_t launch_analysis_rhs(sp_plan* p, const double2* x, double a, double2* g, bool fp32);
 hipError_t launch_stokes_solve(sp_plan* p, const double2* g, double2* out, int inhomogeneous);
+// FP64 nv (y-valued product fields) -> Chebyshev analysis + xa * x -> solve, one kernel
+hipError_t launch_analysis_solve(sp_plan* p, const double2* x, double xa, double2* out,
+                                 int inhomogeneous);
 hipError_t launch_axpby(sp_plan* p, const double2* x, double a, const double2* y, double b,
                         double2* out, size_t n);
 hipError_t launch_norm_partial(sp_plan* p, const double2* a, double* partial, int* nblocks);
@@ -132,6 +137,7 @@ hipError_t launch_multidot(sp_plan* p, const double2* V, int nvec, const double2
 hipError_t launch_multiaxpy(sp_plan* p, const double2* V, int nvec, const double* h, double alpha,
                             double beta, double2* w);
 hipError_t launch_scale(sp_plan* p, const double2* y, double s, double2* x);
+hipError_t launch_hermitian(sp_plan* p, double2* a);
 constexpr int kMultidotBlocks = 256;
 
 // compositions (api.cpp)
