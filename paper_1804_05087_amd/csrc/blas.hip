@@ -17,28 +17,48 @@ __device__ inline double packed_weight(size_t t, int nx, int ny, int nzh) {
 }
 
 // partial[v * nb + block] = block's share of <V_v, w>, v = 0..nvec-1.
-// V is nvec contiguous canonical vectors of n complex entries.
+// V is nvec contiguous canonical vectors of n complex entries. Vectors are
+// taken eight at a time: each thread streams its grid-strided entries of w
+// once per group, then the eight sums are reduced with wave shuffles.
+constexpr int kDotGroup = 8;
+
 __global__ void __launch_bounds__(256)
     k_multidot(const double2* __restrict__ V, int nvec, const double2* __restrict__ w,
                double* __restrict__ partial, size_t n, int nx, int ny, int nzh) {
-  __shared__ double red[256];
-  const size_t chunk = (n + gridDim.x - 1) / gridDim.x;
-  const size_t lo = blockIdx.x * chunk;
-  const size_t hi = (lo + chunk < n) ? lo + chunk : n;
-  for (int v = 0; v < nvec; ++v) {
-    const double2* a = V + (size_t)v * n;
-    double acc = 0.0;
-    for (size_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+  __shared__ double red[4][kDotGroup];
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (int v0 = 0; v0 < nvec; v0 += kDotGroup) {
+    const int nv = (nvec - v0 < kDotGroup) ? nvec - v0 : kDotGroup;
+    double acc[kDotGroup];
+#pragma unroll
+    for (int q = 0; q < kDotGroup; ++q) acc[q] = 0.0;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
       const double wt = packed_weight(t, nx, ny, nzh);
-      acc += wt * (a[t].x * w[t].x + a[t].y * w[t].y);
+      const double2 x = w[t];
+      const double wr = wt * x.x, wi = wt * x.y;
+#pragma unroll
+      for (int q = 0; q < kDotGroup; ++q) {
+        if (q < nv) {
+          const double2 a = V[(size_t)(v0 + q) * n + t];
+          acc[q] += a.x * wr + a.y * wi;
+        }
+      }
     }
-    red[threadIdx.x] = acc;
+#pragma unroll
+    for (int q = 0; q < kDotGroup; ++q) {
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) acc[q] += __shfl_xor(acc[q], d);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < kDotGroup; ++q) red[wid][q] = acc[q];
+    }
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[(size_t)v * gridDim.x + blockIdx.x] = red[0];
+    if (threadIdx.x < nv)
+      partial[(size_t)(v0 + threadIdx.x) * gridDim.x + blockIdx.x] =
+          red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
     __syncthreads();
   }
 }
