@@ -85,6 +85,7 @@ __global__ void __launch_bounds__(64)
     return;
   }
   const double* src = modedata + (size_t)mode * stride;
+  #pragma unroll 8
   for (int t = tid; t < stride; t += 64) rec[t] = src[t];
   for (int t = tid; t < 3 * n1; t += 64) hw[t] = hw_g[t];
   if constexpr (FUSED)
@@ -232,11 +233,13 @@ __global__ void __launch_bounds__(256)
   const int y = blockIdx.x;
   const int x0 = blockIdx.y * xc;
   const int nxl = min(xc, px - x0);
+  const int LS = (PT == 0) ? pz : line_stride(PT);
   C* A = reinterpret_cast<C*>(smem_raw);
-  C* B = A + xc * 3 * pz;
-  C* twl = B + xc * 3 * pz;
+  C* B = A + xc * 3 * LS;
+  C* twl = B + xc * 3 * LS;
   const size_t fs = (size_t)ny * px * nzm;
   for (int t = threadIdx.x; t < pz; t += blockDim.x) twl[t] = tw[t];
+  #pragma unroll 8
   for (int t = threadIdx.x; t < nxl * 2 * pz; t += blockDim.x) {
     const int m = t % pz;
     const int lj = t / pz;  // x_l * 2 + j
@@ -259,24 +262,26 @@ __global__ void __launch_bounds__(256)
       C b = (jj == 0) ? conjc(xp[1 * fs + off + mm]) : mk((R)0, (R)0);
       val = mk(a.x - b.y, a.y + b.x);
     }
-    A[(xl * 3 + jj) * pz + m] = val;
+    A[lidx<PT>(xl * 3 + jj, m, pz)] = val;
   }
   __syncthreads();
   // inverse FFT of the two used lines of every x (line 2 of each x is idle)
+  #pragma unroll 8
   for (int t = threadIdx.x; t < nxl * pz; t += blockDim.x) {
     const int xl = t / pz;
     const int z = t - xl * pz;
-    A[(xl * 3 + 2) * pz + z] = mk((R)0, (R)0);
+    A[lidx<PT>(xl * 3 + 2, z, pz)] = mk((R)0, (R)0);
   }
   __syncthreads();
   C* res = fft_lines<R, PT>(A, B, nxl * 3, pl, twl, (R)1);
   C* oth = (res == A) ? B : A;
   const size_t bs = (size_t)ny * px * pz;
+  #pragma unroll 8
   for (int t = threadIdx.x; t < nxl * pz; t += blockDim.x) {
     const int xl = t / pz;
     const int z = t - xl * pz;
-    const C p0 = res[(xl * 3 + 0) * pz + z];
-    const C p1 = res[(xl * 3 + 1) * pz + z];
+    const C p0 = res[lidx<PT>(xl * 3 + 0, z, pz)];
+    const C p1 = res[lidx<PT>(xl * 3 + 1, z, pz)];
     const R lx = p0.x, ly = p0.y, lz = p1.x;
     const size_t bo = ((size_t)y * px + (x0 + xl)) * pz + z;
     const R U = base[0 * bs + bo], V = base[1 * bs + bo], W = base[2 * bs + bo];
@@ -287,19 +292,20 @@ __global__ void __launch_bounds__(256)
     const R dox = ly * W - lz * V;
     const R doy = lz * U - lx * W;
     const R doz = lx * V - ly * U;
-    oth[(xl * 3 + 0) * pz + z] = mk(dux, duy);
-    oth[(xl * 3 + 1) * pz + z] = mk(duz, dox);
-    oth[(xl * 3 + 2) * pz + z] = mk(doy, doz);
+    oth[lidx<PT>(xl * 3 + 0, z, pz)] = mk(dux, duy);
+    oth[lidx<PT>(xl * 3 + 1, z, pz)] = mk(duz, dox);
+    oth[lidx<PT>(xl * 3 + 2, z, pz)] = mk(doy, doz);
   }
   __syncthreads();
   C* fin = fft_lines<R, PT>(oth, res, nxl * 3, pl, twl, (R)-1);
+  #pragma unroll 8
   for (int t = threadIdx.x; t < nxl * 3 * nzm; t += blockDim.x) {
     const int m = t % nzm;
     const int lj = t / nzm;
     const int jj = lj % 3;
     const int xl = lj / 3;
-    const C a = fin[(xl * 3 + jj) * pz + m];
-    const C am = conjc(fin[(xl * 3 + jj) * pz + (pz - m) % pz]);
+    const C a = fin[lidx<PT>(xl * 3 + jj, m, pz)];
+    const C am = conjc(fin[lidx<PT>(xl * 3 + jj, (pz - m) % pz, pz)]);
     const C s1 = cscale(cadd(a, am), (R)0.5 * scale);
     const C d = csub(a, am);
     const C s2 = mk(d.y * (R)0.5 * scale, -d.x * (R)0.5 * scale);
@@ -333,6 +339,7 @@ __global__ void __launch_bounds__(256)
   const bool nyq = (kz >= nzm);
   const size_t fs = (size_t)ny * nzm * nx;
   if (!nyq) {
+    #pragma unroll 8
     for (int idx = threadIdx.x; idx < 8 * ny; idx += 256) {
       const int ml = idx % 8;
       const int jj = idx / 8;
@@ -429,11 +436,12 @@ hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out, v
 hipError_t launch_adj_z(sp_plan* p, bool fp32) {
   const Dims& d = p->d;
   const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
-  int xc = (int)((48 * 1024 - d.pz * el) / (2 * 3 * d.pz * el));
+  const int LL = fft_length_specialised(d.pz) ? line_stride(d.pz) : d.pz;
+  int xc = (int)((48 * 1024 - d.pz * el) / (2 * 3 * LL * el));
   if (xc < 1) xc = 1;
   if (xc > d.px) xc = d.px;
   dim3 grid(d.ny, (d.px + xc - 1) / xc);
-  const size_t sh = (2 * (size_t)xc * 3 + 1) * d.pz * el;
+  const size_t sh = (2 * (size_t)xc * 3 * LL + d.pz) * el;
   const double scale = 1.0 / ((double)d.px * d.pz);
   SP_PROF_BEGIN(p, KID_ADJ_Z);
 #define L32(PV)                                                                                   \

@@ -112,6 +112,28 @@ __device__ typename V2<R>::T* lds_fft(typename V2<R>::T* a, typename V2<R>::T* b
 }
 
 
+// Block-cooperative copy into LDS with the global loads of up to MAXE elements
+// per thread issued before any LDS store (LDS pointers are generic here, so
+// the compiler would otherwise keep each load/store pair in order).
+// load(t) -> value, store(t, value); t = 0 .. total-1.
+template <int MAXE, typename T, typename LoadF, typename StoreF>
+__device__ inline void staged_copy(int total, LoadF load, StoreF store) {
+  const int nt = blockDim.x;
+  for (int base = 0; base < total; base += MAXE * nt) {
+    T v[MAXE];
+#pragma unroll
+    for (int q = 0; q < MAXE; ++q) {
+      const int t = base + q * nt + (int)threadIdx.x;
+      if (t < total) v[q] = load(t);
+    }
+#pragma unroll
+    for (int q = 0; q < MAXE; ++q) {
+      const int t = base + q * nt + (int)threadIdx.x;
+      if (t < total) store(t, v[q]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Compile-time-length variant: the radix sequence of P is fixed, so every
 // index computation folds to constants; twiddles come from a table tw[q] =
@@ -166,6 +188,20 @@ __device__ inline void bfly(C* v, int Rd, R sign) {
   }
 }
 
+// LDS line layout of the compile-time-length FFTs: element i of line l sits at
+// l * line_stride(P) + pad(i), with one padding slot after every 8 elements and
+// an odd line stride, so that the stride-R writes of the first Stockham pass
+// and the line-transposing loads/stores of the x kernels avoid bank conflicts.
+// P == 0 (runtime length) keeps the dense layout l * P + i.
+__host__ __device__ constexpr int line_stride(int P) { return P == 0 ? 0 : ((P + P / 8) | 1); }
+template <int PT>
+__device__ inline int lidx(int l, int i, int P) {
+  if constexpr (PT == 0)
+    return l * P + i;
+  else
+    return l * line_stride(PT) + i + (i >> 3);
+}
+
 template <int P, int RD, int NS, typename R>
 __device__ inline void fft_pass_c(const typename V2<R>::T* __restrict__ x,
                                   typename V2<R>::T* __restrict__ y, int nl,
@@ -173,15 +209,19 @@ __device__ inline void fft_pass_c(const typename V2<R>::T* __restrict__ x,
   using C = typename V2<R>::T;
   constexpr int NB = P / RD;
   constexpr int TS = P / (NS * RD);
+  constexpr int LS = line_stride(P);
   for (int t = threadIdx.x; t < nl * NB; t += blockDim.x) {
     const int l = t / NB;
     const int j = t - l * NB;
     const int k = j % NS;
-    const C* xl = x + l * P;
-    C* yl = y + l * P;
+    const C* xl = x + l * LS;
+    C* yl = y + l * LS;
     C v[RD];
 #pragma unroll
-    for (int r = 0; r < RD; ++r) v[r] = xl[j + r * NB];
+    for (int r = 0; r < RD; ++r) {
+      const int e = j + r * NB;
+      v[r] = xl[e + (e >> 3)];
+    }
     if (NS > 1) {
 #pragma unroll
       for (int r = 1; r < RD; ++r) {
@@ -193,7 +233,10 @@ __device__ inline void fft_pass_c(const typename V2<R>::T* __restrict__ x,
     bfly<C, R>(v, RD, sign);
     const int base = (j / NS) * NS * RD + k;
 #pragma unroll
-    for (int r = 0; r < RD; ++r) yl[base + r * NS] = v[r];
+    for (int r = 0; r < RD; ++r) {
+      const int e = base + r * NS;
+      yl[e + (e >> 3)] = v[r];
+    }
   }
   __syncthreads();
 }

@@ -53,16 +53,25 @@ __global__ void __launch_bounds__(256)
   const R* M = (tab.mat[f] == 0) ? M0 : (tab.mat[f] == 1 ? M1 : M2);
   const int mx0 = blockIdx.x * 16;
   const int y0 = blockIdx.y * 16;
-  for (int idx = threadIdx.x; idx < 16 * ny; idx += 256) {
-    const int ml = idx / ny;
-    const int n = idx - ml * ny;
-    const int mx = mx0 + ml;
-    C val = mk((R)0, (R)0);
-    if (mx < nx) val = to_r2<R>(u[(((size_t)comp * nx + mx) * nzh + kz) * ny + n]);
-    Us[idx] = val;
-    const int yy = y0 + ml;
-    Ms[idx] = (yy < ny) ? M[(size_t)yy * ny + n] : (R)0;
-  }
+    staged_copy<4, C>(
+      16 * ny,
+      [&](int idx) {
+        const int ml = idx / ny;
+        const int n = idx - ml * ny;
+        const int mx = mx0 + ml;
+        return (mx < nx) ? to_r2<R>(u[(((size_t)comp * nx + mx) * nzh + kz) * ny + n])
+                         : mk((R)0, (R)0);
+      },
+      [&](int idx, C v) { Us[idx] = v; });
+  staged_copy<4, R>(
+      16 * ny,
+      [&](int idx) {
+        const int yl = idx / ny;
+        const int n = idx - yl * ny;
+        const int yy = y0 + yl;
+        return (yy < ny) ? M[(size_t)yy * ny + n] : (R)0;
+      },
+      [&](int idx, R v) { Ms[idx] = v; });
   __syncthreads();
   const int ty = threadIdx.x / 16;
   const int tm = threadIdx.x % 16;
@@ -96,51 +105,61 @@ __global__ void __launch_bounds__(256)
   using C = typename V2<R>::T;
   extern __shared__ unsigned char smem_raw[];
   const int px = pl.P;
+  const int LS = (PT == 0) ? px : line_stride(PT);
   C* A = reinterpret_cast<C*>(smem_raw);
-  C* B = A + kc * px;
-  C* twl = B + kc * px;
+  C* B = A + kc * LS;
+  C* twl = B + kc * LS;
   const int y = blockIdx.x;
   const int f = blockIdx.y;
   const int kz0 = blockIdx.z * kc;
   const int nl = min(kc, nzm - kz0);
   for (int t = threadIdx.x; t < px; t += blockDim.x) twl[t] = tw[t];
-  for (int t = threadIdx.x; t < nl * px; t += blockDim.x) A[t] = mk((R)0, (R)0);
+  for (int t = threadIdx.x; t < nl * LS; t += blockDim.x) A[t] = mk((R)0, (R)0);
   __syncthreads();
   const size_t fs = (size_t)ny * nzm * nx;  // field stride in yv
-  for (int t = threadIdx.x; t < nl * nx; t += blockDim.x) {
-    const int l = t / nx;
-    const int i = t - l * nx;
-    if (i == nx / 2) continue;
-    const int kz = kz0 + l;
-    const int mxv = (i < nx / 2) ? i : i - nx;
-    const int pos = (i < nx / 2) ? i : i - nx + px;
-    const size_t off = ((size_t)y * nzm + kz) * nx + i;
-    const R kxv = alpha * (R)mxv;
-    const R kzv = gamma * (R)kz;
-    C val;
-    if (plain) {
-      val = yv[f * fs + off];
-    } else if (f == 0) {
-      val = yv[0 * fs + off];
-    } else if (f == 1) {
-      val = yv[2 * fs + off];
-    } else if (f == 2) {
-      val = yv[3 * fs + off];
-    } else if (f == 3) {  // dw/dy - i kz v
-      val = csub(yv[4 * fs + off], sidot(cscale(yv[2 * fs + off], kzv), (R)1));
-    } else if (f == 4) {  // i kz u - i kx w
-      val = sidot(csub(cscale(yv[0 * fs + off], kzv), cscale(yv[3 * fs + off], kxv)), (R)1);
-    } else {  // i kx v - du/dy
-      val = csub(sidot(cscale(yv[2 * fs + off], kxv), (R)1), yv[1 * fs + off]);
-    }
-    A[l * px + pos] = val;
-  }
+    staged_copy<4, C>(
+      nl * nx,
+      [&](int t) {
+        const int l = t / nx;
+        const int i = t - l * nx;
+        C val = mk((R)0, (R)0);
+        if (i == nx / 2) return val;
+        const int kz = kz0 + l;
+        const int mxv = (i < nx / 2) ? i : i - nx;
+        const size_t off = ((size_t)y * nzm + kz) * nx + i;
+        const R kxv = alpha * (R)mxv;
+        const R kzv = gamma * (R)kz;
+        if (plain) {
+          val = yv[f * fs + off];
+        } else if (f == 0) {
+          val = yv[0 * fs + off];
+        } else if (f == 1) {
+          val = yv[2 * fs + off];
+        } else if (f == 2) {
+          val = yv[3 * fs + off];
+        } else if (f == 3) {  // dw/dy - i kz v
+          val = csub(yv[4 * fs + off], sidot(cscale(yv[2 * fs + off], kzv), (R)1));
+        } else if (f == 4) {  // i kz u - i kx w
+          val = sidot(csub(cscale(yv[0 * fs + off], kzv), cscale(yv[3 * fs + off], kxv)), (R)1);
+        } else {  // i kx v - du/dy
+          val = csub(sidot(cscale(yv[2 * fs + off], kxv), (R)1), yv[1 * fs + off]);
+        }
+        return val;
+      },
+      [&](int t, C v) {
+        const int l = t / nx;
+        const int i = t - l * nx;
+        if (i == nx / 2) return;
+        const int pos = (i < nx / 2) ? i : i - nx + px;
+        A[lidx<PT>(l, pos, px)] = v;
+      });
   __syncthreads();
   C* res = fft_lines<R, PT>(A, B, nl, pl, twl, (R)1);
+  #pragma unroll 8
   for (int t = threadIdx.x; t < nl * px; t += blockDim.x) {
     const int x = t / nl;
     const int l = t - x * nl;
-    xp[(((size_t)f * ny + y) * px + x) * nzm + kz0 + l] = res[l * px + x];
+    xp[(((size_t)f * ny + y) * px + x) * nzm + kz0 + l] = res[lidx<PT>(l, x, px)];
   }
 }
 
@@ -163,44 +182,49 @@ __global__ void __launch_bounds__(256)
   const int y = blockIdx.x;
   const int x0 = blockIdx.y * xc;
   const int nxl = min(xc, px - x0);
+  const int LS = (PT == 0) ? pz : line_stride(PT);
   C* A = reinterpret_cast<C*>(smem_raw);
-  C* B = A + xc * 3 * pz;
-  C* twl = B + xc * 3 * pz;
+  C* B = A + xc * 3 * LS;
+  C* twl = B + xc * 3 * LS;
   const size_t fs = (size_t)ny * px * nzm;
   for (int t = threadIdx.x; t < pz; t += blockDim.x) twl[t] = tw[t];
-  for (int t = threadIdx.x; t < nxl * 3 * pz; t += blockDim.x) {
-    const int m = t % pz;
-    const int lj = t / pz;  // x_l * 3 + j
-    const int j = lj % 3;
-    const int xl = lj / 3;
-    const size_t off = ((size_t)y * px + (x0 + xl)) * nzm;
-    C val = mk((R)0, (R)0);
-    if (m < nzm) {
-      C a = xp[(2 * j) * fs + off + m];
-      C b = xp[(2 * j + 1) * fs + off + m];
-      if (m == 0) {
-        a.y = 0;
-        b.y = 0;
-      }
-      val = mk(a.x - b.y, a.y + b.x);
-    } else if (m > pz - nzm) {
-      const int mm = pz - m;
-      C a = conjc(xp[(2 * j) * fs + off + mm]);
-      C b = conjc(xp[(2 * j + 1) * fs + off + mm]);
-      val = mk(a.x - b.y, a.y + b.x);
-    }
-    A[t] = val;
-  }
+    staged_copy<6, C>(
+      nxl * 3 * pz,
+      [&](int t) {
+        const int m = t % pz;
+        const int lj = t / pz;  // x_l * 3 + j
+        const int j = lj % 3;
+        const int xl = lj / 3;
+        const size_t off = ((size_t)y * px + (x0 + xl)) * nzm;
+        C val = mk((R)0, (R)0);
+        if (m < nzm) {
+          C a = xp[(2 * j) * fs + off + m];
+          C b = xp[(2 * j + 1) * fs + off + m];
+          if (m == 0) {
+            a.y = 0;
+            b.y = 0;
+          }
+          val = mk(a.x - b.y, a.y + b.x);
+        } else if (m > pz - nzm) {
+          const int mm = pz - m;
+          C a = conjc(xp[(2 * j) * fs + off + mm]);
+          C b = conjc(xp[(2 * j + 1) * fs + off + mm]);
+          val = mk(a.x - b.y, a.y + b.x);
+        }
+        return val;
+      },
+      [&](int t, C v) { A[lidx<PT>(t / pz, t % pz, pz)] = v; });
   __syncthreads();
   C* res = fft_lines<R, PT>(A, B, nxl * 3, pl, twl, (R)1);
   C* oth = (res == A) ? B : A;
   const size_t bs = (size_t)ny * px * pz;  // base field stride
+  #pragma unroll 8
   for (int t = threadIdx.x; t < nxl * pz; t += blockDim.x) {
     const int xl = t / pz;
     const int z = t - xl * pz;
-    const C p0 = res[(xl * 3 + 0) * pz + z];
-    const C p1 = res[(xl * 3 + 1) * pz + z];
-    const C p2 = res[(xl * 3 + 2) * pz + z];
+    const C p0 = res[lidx<PT>(xl * 3 + 0, z, pz)];
+    const C p1 = res[lidx<PT>(xl * 3 + 1, z, pz)];
+    const C p2 = res[lidx<PT>(xl * 3 + 2, z, pz)];
     const R u = p0.x, v = p0.y, w = p1.x, ox = p1.y, oy = p2.x, oz = p2.y;
     const size_t bo = ((size_t)y * px + (x0 + xl)) * pz + z;
     R nxv, nyv, nzv;
@@ -223,19 +247,20 @@ __global__ void __launch_bounds__(256)
       base[5 * bs + bo] = oz;
       continue;
     }
-    oth[(xl * 2 + 0) * pz + z] = mk(nxv, nyv);
-    oth[(xl * 2 + 1) * pz + z] = mk(nzv, (R)0);
+    oth[lidx<PT>(xl * 2 + 0, z, pz)] = mk(nxv, nyv);
+    oth[lidx<PT>(xl * 2 + 1, z, pz)] = mk(nzv, (R)0);
   }
   if (mode == 2) return;  // uniform across the block
   __syncthreads();
   C* fin = fft_lines<R, PT>(oth, res, nxl * 2, pl, twl, (R)-1);
   const size_t ns = (size_t)ny * px * nzm;
+  #pragma unroll 8
   for (int t = threadIdx.x; t < nxl * nzm; t += blockDim.x) {
     const int xl = t / nzm;
     const int m = t - xl * nzm;
-    const C a = fin[(xl * 2 + 0) * pz + m];
-    const C am = conjc(fin[(xl * 2 + 0) * pz + (pz - m) % pz]);
-    const C cz = fin[(xl * 2 + 1) * pz + m];
+    const C a = fin[lidx<PT>(xl * 2 + 0, m, pz)];
+    const C am = conjc(fin[lidx<PT>(xl * 2 + 0, (pz - m) % pz, pz)]);
+    const C cz = fin[lidx<PT>(xl * 2 + 1, m, pz)];
     const C sx = cscale(cadd(a, am), (R)0.5 * scale);
     const C d = csub(a, am);  // 2 i Ny
     const C sy = mk(d.y * (R)0.5 * scale, -d.x * (R)0.5 * scale);
@@ -258,28 +283,37 @@ __global__ void __launch_bounds__(256)
   using C = typename V2<R>::T;
   extern __shared__ unsigned char smem_raw[];
   const int px = pl.P;
+  const int LS = (PT == 0) ? px : line_stride(PT);
   C* A = reinterpret_cast<C*>(smem_raw);
-  C* B = A + kc * px;
-  C* twl = B + kc * px;
+  C* B = A + kc * LS;
+  C* twl = B + kc * LS;
   const int y = blockIdx.x;
   const int c = blockIdx.y;
   const int kz0 = blockIdx.z * kc;
   const int nl = min(kc, nzm - kz0);
   for (int t = threadIdx.x; t < px; t += blockDim.x) twl[t] = tw[t];
-  for (int t = threadIdx.x; t < nl * px; t += blockDim.x) {
-    const int x = t / nl;
-    const int l = t - x * nl;
-    A[l * px + x] = np[(((size_t)c * ny + y) * px + x) * nzm + kz0 + l];
-  }
+    staged_copy<6, C>(
+      nl * px,
+      [&](int t) {
+        const int x = t / nl;
+        const int l = t - x * nl;
+        return np[(((size_t)c * ny + y) * px + x) * nzm + kz0 + l];
+      },
+      [&](int t, C v) {
+        const int x = t / nl;
+        const int l = t - x * nl;
+        A[lidx<PT>(l, x, px)] = v;
+      });
   __syncthreads();
   C* res = fft_lines<R, PT>(A, B, nl, pl, twl, (R)-1);
+  #pragma unroll 8
   for (int t = threadIdx.x; t < nl * nx; t += blockDim.x) {
     const int l = t / nx;
     const int i = t - l * nx;
     C val = mk((R)0, (R)0);
     if (i != nx / 2) {
       const int pos = (i < nx / 2) ? i : i - nx + px;
-      val = res[l * px + pos];
+      val = res[lidx<PT>(l, pos, px)];
     }
     nv[(((size_t)c * ny + y) * nzm + kz0 + l) * nx + i] = val;
   }
@@ -305,7 +339,8 @@ __global__ void __launch_bounds__(256)
   const int n0 = blockIdx.y * 16;
   const bool nyq = (kz >= nzm);
   if (!nyq) {
-    for (int idx = threadIdx.x; idx < 16 * ny; idx += 256) {
+    #pragma unroll 8
+  for (int idx = threadIdx.x; idx < 16 * ny; idx += 256) {
       const int j = idx / 16;
       const int ml = idx % 16;
       const int mx = mx0 + ml;
@@ -407,6 +442,7 @@ __global__ void __launch_bounds__(64)
     return;
   }
   const double* src = modedata + (size_t)mode * stride;
+  #pragma unroll 8
   for (int t = tid; t < stride; t += 64) rec[t] = src[t];
   for (int t = tid; t < 3 * n1; t += 64) hw[t] = hw_g[t];
   const int mxv = (i < nx / 2) ? i : i - nx;
@@ -421,6 +457,7 @@ __global__ void __launch_bounds__(64)
     // stage the three y-valued columns of this mode (in the Fpar/Fv/Fperp slots)
     const int nzm = nzh - 1;
     for (int t = tid; t < 2 * N; t += 64) ctab[t] = ctab_g[t];
+    #pragma unroll 8
     for (int t = tid; t < 3 * n1; t += 64) {
       const int c = t / n1;
       const int jj = t - c * n1;
@@ -664,9 +701,13 @@ __global__ void k_unpack(const double* __restrict__ packed, double2* __restrict_
     default: LAUNCH(0); break;      \
   }
 
+// LDS elements per FFT line (padded layout for the specialised lengths).
+static int lds_line(int P) { return fft_length_specialised(P) ? line_stride(P) : P; }
+
 static int chunk_for(int P, int total, size_t elem) {
   // largest chunk whose two ping-pong buffers (plus twiddles) fit in 48 KiB of LDS
-  int k = (int)((48 * 1024 - P * elem) / (2 * P * elem));
+  const int L = lds_line(P);
+  int k = (int)((48 * 1024 - P * elem) / (2 * L * elem));
   if (k < 1) k = 1;
   if (k > total) k = total;
   return k;
@@ -714,7 +755,7 @@ hipError_t launch_fft_x_inv_gen(sp_plan* p, const void* in, void* out, int nfiel
   const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
   const int kc = chunk_for(d.px, d.nzm, el);
   dim3 grid(d.ny, nfields, (d.nzm + kc - 1) / kc);
-  const size_t sh = (2 * (size_t)kc + 1) * d.px * el;
+  const size_t sh = (2 * (size_t)kc * lds_line(d.px) + d.px) * el;
   SP_PROF_BEGIN(p, KID_FFT_X_INV);
 #define L32(PV)                                                                                 \
   hipLaunchKernelGGL((k_fft_x_inv<float, PV>), grid, dim3(256), sh, p->stream, (const float2*)in, \
@@ -742,11 +783,11 @@ hipError_t launch_fft_x_inv(sp_plan* p, bool fp32) {
 hipError_t launch_z_product(sp_plan* p, int mode, bool fp32) {
   const Dims& d = p->d;
   const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
-  int xc = (int)((48 * 1024 - d.pz * el) / (2 * 3 * d.pz * el));
+  int xc = (int)((48 * 1024 - d.pz * el) / (2 * 3 * lds_line(d.pz) * el));
   if (xc < 1) xc = 1;
   if (xc > d.px) xc = d.px;
   dim3 grid(d.ny, (d.px + xc - 1) / xc);
-  const size_t sh = (2 * (size_t)xc * 3 + 1) * d.pz * el;
+  const size_t sh = (2 * (size_t)xc * 3 * lds_line(d.pz) + d.pz) * el;
   const double scale = 1.0 / ((double)d.px * d.pz);
   SP_PROF_BEGIN(p, KID_Z_PRODUCT);
 #define L32(PV)                                                                                  \
@@ -773,7 +814,7 @@ hipError_t launch_fft_x_fwd_gen(sp_plan* p, const void* in, void* out, int nfiel
   const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
   const int kc = chunk_for(d.px, d.nzm, el);
   dim3 grid(d.ny, nfields, (d.nzm + kc - 1) / kc);
-  const size_t sh = (2 * (size_t)kc + 1) * d.px * el;
+  const size_t sh = (2 * (size_t)kc * lds_line(d.px) + d.px) * el;
   SP_PROF_BEGIN(p, KID_FFT_X_FWD);
 #define L32(PV)                                                                                 \
   hipLaunchKernelGGL((k_fft_x_fwd<float, PV>), grid, dim3(256), sh, p->stream, (const float2*)in, \
