@@ -38,23 +38,18 @@ namespace sp {
     }                                                \
   }
 
-// When FUSED, the adjoint of the Chebyshev analysis is applied as well:
-// nvout[c][j][kz][mx] = sum_n Tinv[n][j] out_c[n] (a DCT-I with a 2N-entry
-// cosine table), the input of the adjoint transform chain.
-template <int E, bool FUSED>
+template <int E>
 __global__ void __launch_bounds__(64)
     k_stokes_solve_adj(const double2* __restrict__ w, double2* __restrict__ out,
                        const double* __restrict__ modedata, const double* __restrict__ hw_g,
                        int stride, int nx, int ny, int nzh, double alpha, double gamma, double re,
-                       double inv_dt, double2* __restrict__ nvout,
-                       const double* __restrict__ ctab_g) {
+                       double inv_dt) {
   extern __shared__ unsigned char smem_raw[];
   const int N = ny - 1;
   const int n1 = ny;
   double* rec = reinterpret_cast<double*>(smem_raw);
   double* hw = rec + stride;
-  double* ctab = hw + 3 * n1;
-  cd* Upb = reinterpret_cast<cd*>(ctab + 2 * N);  // adjoint of u_par
+  cd* Upb = reinterpret_cast<cd*>(hw + 3 * n1);  // adjoint of u_par
   cd* Ub = Upb + n1;                              // adjoint of u_perp
   cd* Vb = Ub + n1;                               // adjoint of v
   cd* A = Vb + n1;
@@ -88,8 +83,6 @@ __global__ void __launch_bounds__(64)
   #pragma unroll 8
   for (int t = tid; t < stride; t += 64) rec[t] = src[t];
   for (int t = tid; t < 3 * n1; t += 64) hw[t] = hw_g[t];
-  if constexpr (FUSED)
-    for (int t = tid; t < 2 * N; t += 64) ctab[t] = ctab_g[t];
   const int mxv = (i < nx / 2) ? i : i - nx;
   const double kx = alpha * mxv;
   const double kz = gamma * j;
@@ -185,31 +178,6 @@ __global__ void __launch_bounds__(64)
     out[mo + n] = make_double2(gu.re, gu.im);
     out[cs + mo + n] = make_double2(gv.re, gv.im);
     out[2 * cs + mo + n] = make_double2(gw.re, gw.im);
-    if constexpr (FUSED) {
-      A[n] = gu;
-      Tm[n] = gv;
-      W[n] = gw;
-    }
-  }
-  if constexpr (FUSED) {
-    __syncthreads();
-    const int nzm = nzh - 1;
-    for (int jj = tid; jj < n1; jj += 64) {
-      cd s0(0.0), s1(0.0), s2(0.0);
-      int q = 0;
-      for (int n = 0; n <= N - 2; ++n) {
-        const double cw = ctab[q] * ((n == 0) ? 0.5 : 1.0);
-        s0 = s0 + A[n] * cw;
-        s1 = s1 + Tm[n] * cw;
-        s2 = s2 + W[n] * cw;
-        q += jj;
-        if (q >= 2 * N) q -= 2 * N;
-      }
-      const double sc = ((jj == 0 || jj == N) ? 1.0 : 2.0) / N;
-      nvout[((size_t)(0 * ny + jj) * nzm + j) * nx + i] = make_double2(s0.re * sc, s0.im * sc);
-      nvout[((size_t)(1 * ny + jj) * nzm + j) * nx + i] = make_double2(s1.re * sc, s1.im * sc);
-      nvout[((size_t)(2 * ny + jj) * nzm + j) * nx + i] = make_double2(s2.re * sc, s2.im * sc);
-    }
   }
 }
 
@@ -315,86 +283,6 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// ---------------------------------------------------------------------------
-// adj_synth: adjoint of (synthesis + curl combination), plus a * x:
-//   u_bar = T^T (F0 - i kz F4) - (T.D)^T F5
-//   v_bar = T^T (F1 + i kz F3 - i kx F5)
-//   w_bar = T^T (F2 + i kx F4) + (T.D)^T F3
-// F: six truncated y-valued fields [6][ny][nzm][nx] (u, v, w, omega adjoints).
-// Block: 8 mx x 32 n tile of one (component, kz).
-// ---------------------------------------------------------------------------
-template <typename R>
-__global__ void __launch_bounds__(256)
-    k_adj_synth(const typename V2<R>::T* __restrict__ F, const R* __restrict__ T,
-                const R* __restrict__ TD, const double2* __restrict__ x, double a,
-                double2* __restrict__ out, int nx, int ny, int nzh, int nzm, R alpha, R gamma) {
-  using C = typename V2<R>::T;
-  extern __shared__ unsigned char smem_raw[];
-  C* G1 = reinterpret_cast<C*>(smem_raw);  // [8][ny]
-  C* G2 = G1 + 8 * ny;                      // [8][ny]
-  const int c = blockIdx.z % 3;
-  const int kz = blockIdx.z / 3;
-  const int mx0 = blockIdx.x * 8;
-  const int n0 = blockIdx.y * 32;
-  const bool nyq = (kz >= nzm);
-  const size_t fs = (size_t)ny * nzm * nx;
-  if (!nyq) {
-    #pragma unroll 8
-    for (int idx = threadIdx.x; idx < 8 * ny; idx += 256) {
-      const int ml = idx % 8;
-      const int jj = idx / 8;
-      const int mx = mx0 + ml;
-      C g1 = mk((R)0, (R)0), g2 = mk((R)0, (R)0);
-      if (mx < nx && mx != nx / 2) {
-        const int mxv = (mx < nx / 2) ? mx : mx - nx;
-        const R kxv = alpha * (R)mxv;
-        const R kzv = gamma * (R)kz;
-        const size_t off = ((size_t)jj * nzm + kz) * nx + mx;
-        if (c == 0) {
-          g1 = csub(F[0 * fs + off], sidot(cscale(F[4 * fs + off], kzv), (R)1));
-          g2 = cscale(F[5 * fs + off], (R)-1);
-        } else if (c == 1) {
-          g1 = cadd(F[1 * fs + off], sidot(csub(cscale(F[3 * fs + off], kzv),
-                                                cscale(F[5 * fs + off], kxv)),
-                                           (R)1));
-        } else {
-          g1 = cadd(F[2 * fs + off], sidot(cscale(F[4 * fs + off], kxv), (R)1));
-          g2 = F[3 * fs + off];
-        }
-      }
-      G1[ml * ny + jj] = g1;
-      G2[ml * ny + jj] = g2;
-    }
-  }
-  __syncthreads();
-  const int tm = threadIdx.x / 32;
-  const int tn = threadIdx.x % 32;
-  const int mx = mx0 + tm;
-  const int n = n0 + tn;
-  if (mx < nx && n < ny) {
-    double rr = 0.0, ri = 0.0;
-    if (!nyq) {
-      R ar = 0, ai = 0;
-      const C* g1 = G1 + tm * ny;
-      const C* g2 = G2 + tm * ny;
-      for (int jj = 0; jj < ny; ++jj) {
-        const R t = T[(size_t)jj * ny + n];
-        const R td = TD[(size_t)jj * ny + n];
-        ar += t * g1[jj].x + td * g2[jj].x;
-        ai += t * g1[jj].y + td * g2[jj].y;
-      }
-      rr = (double)ar;
-      ri = (double)ai;
-    }
-    const size_t o = (((size_t)c * nx + mx) * nzh + kz) * ny + n;
-    if (x != nullptr) {
-      rr += a * x[o].x;
-      ri += a * x[o].y;
-    }
-    out[o] = make_double2(rr, ri);
-  }
-}
-
 // Scale the (0,0) mode of a canonical field in place.
 __global__ void k_mean_scale(double2* __restrict__ a, double s, int nx, int nzh, int ny) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -409,31 +297,27 @@ __global__ void k_mean_scale(double2* __restrict__ a, double s, int nx, int nzh,
 
 int solve_lanes_per_chain(int ny);
 
-hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out, void* nvout) {
+hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out) {
   const Dims& d = p->d;
   const size_t sh = (size_t)p->mode_stride * sizeof(double) + 3 * (size_t)d.ny * sizeof(double) +
-                    2 * (size_t)d.N * sizeof(double) + 12 * (size_t)d.ny * sizeof(cd);
+                    12 * (size_t)d.ny * sizeof(cd);
   SP_PROF_BEGIN(p, KID_SOLVE_ADJ);
-#define SP_SOLVE_ADJ_LAUNCH(EV, FU)                                                           \
-  hipLaunchKernelGGL((k_stokes_solve_adj<EV, FU>), dim3(d.nx * d.nzh), dim3(64), sh, p->stream, \
-                     w, out, p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh, d.alpha,     \
-                     d.gamma, d.re, d.inv_dt, (double2*)nvout, p->d_ctab)
-  const int ev = solve_lanes_per_chain(d.ny);
-  if (nvout) {
-    if (ev == 1) SP_SOLVE_ADJ_LAUNCH(1, true);
-    else if (ev == 2) SP_SOLVE_ADJ_LAUNCH(2, true);
-    else SP_SOLVE_ADJ_LAUNCH(3, true);
-  } else {
-    if (ev == 1) SP_SOLVE_ADJ_LAUNCH(1, false);
-    else if (ev == 2) SP_SOLVE_ADJ_LAUNCH(2, false);
-    else SP_SOLVE_ADJ_LAUNCH(3, false);
+#define SP_SOLVE_ADJ_LAUNCH(EV)                                                                \
+  hipLaunchKernelGGL((k_stokes_solve_adj<EV>), dim3(d.nx * d.nzh), dim3(64), sh, p->stream, w, \
+                     out, p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh, d.alpha,       \
+                     d.gamma, d.re, d.inv_dt)
+  switch (solve_lanes_per_chain(d.ny)) {
+    case 1: SP_SOLVE_ADJ_LAUNCH(1); break;
+    case 2: SP_SOLVE_ADJ_LAUNCH(2); break;
+    default: SP_SOLVE_ADJ_LAUNCH(3); break;
   }
 #undef SP_SOLVE_ADJ_LAUNCH
   SP_PROF_END(p, KID_SOLVE_ADJ);
   return hipGetLastError();
 }
 
-hipError_t launch_adj_z(sp_plan* p, bool fp32) {
+// LDS Stockham fallback for z lengths without a register kernel (zline.hip)
+hipError_t launch_adj_z_lds(sp_plan* p, bool fp32) {
   const Dims& d = p->d;
   const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
   const int LL = fft_length_specialised(d.pz) ? line_stride(d.pz) : d.pz;
@@ -467,24 +351,6 @@ hipError_t launch_adj_z(sp_plan* p, bool fp32) {
   return hipGetLastError();
 }
 
-hipError_t launch_adj_synth(sp_plan* p, const double2* x, double a, double2* out, bool fp32) {
-  const Dims& d = p->d;
-  dim3 grid((d.nx + 7) / 8, (d.ny + 31) / 32, d.nzh * 3);
-  SP_PROF_BEGIN(p, KID_ADJ_SYNTH);
-  if (fp32) {
-    size_t sh = 2 * 8 * (size_t)d.ny * sizeof(float2);
-    hipLaunchKernelGGL(k_adj_synth<float>, grid, dim3(256), sh, p->stream, (const float2*)p->yv,
-                       p->f_T, p->f_TD, x, a, out, d.nx, d.ny, d.nzh, d.nzm, (float)d.alpha,
-                       (float)d.gamma);
-  } else {
-    size_t sh = 2 * 8 * (size_t)d.ny * sizeof(double2);
-    hipLaunchKernelGGL(k_adj_synth<double>, grid, dim3(256), sh, p->stream, (const double2*)p->yv,
-                       p->d_T, p->d_TD, x, a, out, d.nx, d.ny, d.nzh, d.nzm, d.alpha, d.gamma);
-  }
-  SP_PROF_END(p, KID_ADJ_SYNTH);
-  return hipGetLastError();
-}
-
 hipError_t launch_mean_scale(sp_plan* p, double2* a, double s) {
   const Dims& d = p->d;
   SP_PROF_BEGIN(p, KID_MEAN_SCALE);
@@ -509,12 +375,8 @@ sp_status vjp_lin(sp_plan* p, int op, const double2* w, double2* out) {
   SP_TRY_HIP(hipMemcpyAsync(p->t1, w, n * sizeof(double2), hipMemcpyDeviceToDevice, p->stream),
              "copy w");
   SP_TRY_HIP(launch_mean_scale(p, p->t1, 2.0), "mean_scale");
-  if (fp32) {
-    SP_TRY_HIP(launch_stokes_solve_adj(p, p->t1, p->t2, nullptr), "stokes_solve_adj");
-    SP_TRY_HIP(launch_synth_tab(p, p->t2, 1, p->nv, fp32), "analysis^T");
-  } else {
-    SP_TRY_HIP(launch_stokes_solve_adj(p, p->t1, p->t2, p->nv), "stokes_solve_adj+analysis^T");
-  }
+  SP_TRY_HIP(launch_stokes_solve_adj(p, p->t1, p->t2), "stokes_solve_adj");
+  SP_TRY_HIP(launch_synth_tab(p, p->t2, 1, p->nv, fp32), "analysis^T");
   SP_TRY_HIP(launch_fft_x_inv_gen(p, p->nv, p->xp, 3, 1, fp32), "pad+ifft_x");
   SP_TRY_HIP(launch_adj_z(p, fp32), "adj_z");
   SP_TRY_HIP(launch_fft_x_fwd_gen(p, p->xp, p->yv, 6, fp32), "fft_x+truncate");

@@ -25,72 +25,6 @@
 namespace sp {
 
 // ---------------------------------------------------------------------------
-// synth_y: y-contractions of canonical coefficient fields.
-// out[f][y][kz][mx] = sum_n M_f[y][n] u[c_f][mx][kz][n] for the fields of `tab`
-// (component c_f, matrix M_f in {M0, M1, M2}). Forward use: values at the
-// Gauss-Lobatto points of u, du/dy, v, w, dw/dy (M = T, T.D); adjoint use:
-// Tinv^T applied to the three components.
-// Block: 16 mx x 16 y tile of one (field, kz).
-// ---------------------------------------------------------------------------
-struct FieldTab {
-  int n;
-  int comp[8];
-  int mat[8];
-};
-
-template <typename R>
-__global__ void __launch_bounds__(256)
-    k_synth_y(const double2* __restrict__ u, FieldTab tab, const R* __restrict__ M0,
-              const R* __restrict__ M1, const R* __restrict__ M2,
-              typename V2<R>::T* __restrict__ yv, int nx, int ny, int nzh, int nzm) {
-  using C = typename V2<R>::T;
-  extern __shared__ unsigned char smem_raw[];
-  C* Us = reinterpret_cast<C*>(smem_raw);            // [16][ny]
-  R* Ms = reinterpret_cast<R*>(Us + 16 * ny);         // [16][ny]
-  const int f = blockIdx.z % tab.n;
-  const int kz = blockIdx.z / tab.n;
-  const int comp = tab.comp[f];
-  const R* M = (tab.mat[f] == 0) ? M0 : (tab.mat[f] == 1 ? M1 : M2);
-  const int mx0 = blockIdx.x * 16;
-  const int y0 = blockIdx.y * 16;
-    staged_copy<4, C>(
-      16 * ny,
-      [&](int idx) {
-        const int ml = idx / ny;
-        const int n = idx - ml * ny;
-        const int mx = mx0 + ml;
-        return (mx < nx) ? to_r2<R>(u[(((size_t)comp * nx + mx) * nzh + kz) * ny + n])
-                         : mk((R)0, (R)0);
-      },
-      [&](int idx, C v) { Us[idx] = v; });
-  staged_copy<4, R>(
-      16 * ny,
-      [&](int idx) {
-        const int yl = idx / ny;
-        const int n = idx - yl * ny;
-        const int yy = y0 + yl;
-        return (yy < ny) ? M[(size_t)yy * ny + n] : (R)0;
-      },
-      [&](int idx, R v) { Ms[idx] = v; });
-  __syncthreads();
-  const int ty = threadIdx.x / 16;
-  const int tm = threadIdx.x % 16;
-  const int yy = y0 + ty;
-  const int mx = mx0 + tm;
-  if (yy < ny && mx < nx) {
-    R ar = 0, ai = 0;
-    const C* us = Us + tm * ny;
-    const R* ms = Ms + ty * ny;
-    for (int n = 0; n < ny; ++n) {
-      const R m = ms[n];
-      ar += m * us[n].x;
-      ai += m * us[n].y;
-    }
-    yv[(((size_t)f * ny + yy) * nzm + kz) * nx + mx] = mk(ar, ai);
-  }
-}
-
-// ---------------------------------------------------------------------------
 // fft_x_inv: zero-pad lines along x to px and inverse FFT.
 // plain == 0: the six output fields u, v, w, omega_x, omega_y, omega_z are
 // built from the five y-valued fields (u, du/dy, v, w, dw/dy) with i k_x, i k_z;
@@ -320,66 +254,6 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------
-// analysis_rhs: g[c][mx][kz][n] = sum_j Tinv[n][j] nv[c][j][kz][mx] + a x[c][mx][kz][n].
-// x may be NULL (a ignored). kz = nz/2 (Nyquist) rows get a x only.
-// Block: 16 mx x 16 n tile of one (component, kz).
-// ---------------------------------------------------------------------------
-template <typename R>
-__global__ void __launch_bounds__(256)
-    k_analysis_rhs(const typename V2<R>::T* __restrict__ nv, const R* __restrict__ Tinv,
-                   const double2* __restrict__ x, double a, double2* __restrict__ g, int nx, int ny,
-                   int nzh, int nzm) {
-  using C = typename V2<R>::T;
-  extern __shared__ unsigned char smem_raw[];
-  C* Ns = reinterpret_cast<C*>(smem_raw);   // [16 mx][ny]
-  R* Ts = reinterpret_cast<R*>(Ns + 16 * ny);  // [16 n][ny]
-  const int c = blockIdx.z % 3;
-  const int kz = blockIdx.z / 3;
-  const int mx0 = blockIdx.x * 16;
-  const int n0 = blockIdx.y * 16;
-  const bool nyq = (kz >= nzm);
-  if (!nyq) {
-    #pragma unroll 8
-  for (int idx = threadIdx.x; idx < 16 * ny; idx += 256) {
-      const int j = idx / 16;
-      const int ml = idx % 16;
-      const int mx = mx0 + ml;
-      Ns[ml * ny + j] =
-          (mx < nx) ? nv[(((size_t)c * ny + j) * nzm + kz) * nx + mx] : mk((R)0, (R)0);
-      const int nl = idx / ny;
-      const int jj = idx - nl * ny;
-      const int n = n0 + nl;
-      Ts[idx] = (n < ny) ? Tinv[(size_t)n * ny + jj] : (R)0;
-    }
-  }
-  __syncthreads();
-  const int tm = threadIdx.x / 16;
-  const int tn = threadIdx.x % 16;
-  const int mx = mx0 + tm;
-  const int n = n0 + tn;
-  if (mx < nx && n < ny) {
-    double rr = 0.0, ri = 0.0;
-    if (!nyq) {
-      R ar = 0, ai = 0;
-      const C* ns = Ns + tm * ny;
-      const R* ts = Ts + tn * ny;
-      for (int j = 0; j < ny; ++j) {
-        ar += ts[j] * ns[j].x;
-        ai += ts[j] * ns[j].y;
-      }
-      rr = (double)ar;
-      ri = (double)ai;
-    }
-    const size_t o = (((size_t)c * nx + mx) * nzh + kz) * ny + n;
-    if (x != nullptr) {
-      rr += a * x[o].x;
-      ri += a * x[o].y;
-    }
-    g[o] = make_double2(rr, ri);
-  }
-}
-
-// ---------------------------------------------------------------------------
 // stokes_solve: per-mode implicit solve (FP64). One 64-lane wave per mode:
 // lanes 0-31 run parity class 0 (v even), lanes 32-63 class 1, each chain as
 // 32-lane scans (solve_wave.h).
@@ -394,25 +268,18 @@ __global__ void __launch_bounds__(256)
     }                                                \
   }
 
-// When FUSED, the right-hand side is formed here from the y-valued product
-// fields nv ([3][ny][nz/2][nx]): g = Tinv nv + xa * x (the Chebyshev analysis,
-// a DCT-I evaluated with a 2N-entry cosine table), so the per-mode column of
-// the nonlinear term never makes a round trip through a canonical buffer.
-template <int E, bool FUSED>
+template <int E>
 __global__ void __launch_bounds__(64)
     k_stokes_solve(const double2* __restrict__ g, double2* __restrict__ out,
                    const double* __restrict__ modedata, const double* __restrict__ hw_g,
                    int stride, int nx, int ny, int nzh, double alpha, double gamma, double re,
-                   double inv_dt, double wu, double wl, int inhomogeneous,
-                   const double2* __restrict__ nv, const double2* __restrict__ x, double xa,
-                   const double* __restrict__ ctab_g) {
+                   double inv_dt, double wu, double wl, int inhomogeneous) {
   extern __shared__ unsigned char smem_raw[];
   const int N = ny - 1;
   const int n1 = ny;
   double* rec = reinterpret_cast<double*>(smem_raw);
   double* hw = rec + stride;
-  double* ctab = hw + 3 * n1;                        // cos(pi q / N), q < 2N (FUSED only)
-  cd* Fpar = reinterpret_cast<cd*>(ctab + 2 * N);
+  cd* Fpar = reinterpret_cast<cd*>(hw + 3 * n1);
   cd* Fv = Fpar + n1;
   cd* Fperp = Fv + n1;
   cd* A = Fperp + n1;
@@ -422,7 +289,6 @@ __global__ void __launch_bounds__(64)
   cd* V = Rv + n1;
   cd* Rp = V + n1;
   cd* U = Rp + n1;
-  cd* col = U + n1;  // [3][n1] staged y-values of the mode (FUSED only)
 
   const int mode = blockIdx.x;
   const int i = mode / nzh;
@@ -453,47 +319,15 @@ __global__ void __launch_bounds__(64)
   const double k = sqrt(k2);
   const double ik = mean ? 0.0 : 1.0 / k;
   const double lam = k2 + re * inv_dt;
-  if constexpr (FUSED) {
-    // stage the three y-valued columns of this mode (in the Fpar/Fv/Fperp slots)
-    const int nzm = nzh - 1;
-    for (int t = tid; t < 2 * N; t += 64) ctab[t] = ctab_g[t];
-    #pragma unroll 8
-    for (int t = tid; t < 3 * n1; t += 64) {
-      const int c = t / n1;
-      const int jj = t - c * n1;
-      const double2 v = nv[(((size_t)c * ny + jj) * nzm + j) * nx + i];
-      col[t] = cd(v.x, v.y);
-    }
-    __syncthreads();
-  }
   for (int n = tid; n < n1; n += 64) {
     cd fu, fv, fw;
     if (n <= N - 2) {
-      if constexpr (FUSED) {
-        // a_n = 2/(N cb_n) sum_j f_j cos(pi n j / N) / cb_j, cb_0 = cb_N = 2
-        cd s0(0.0), s1(0.0), s2(0.0);
-        int q = 0;
-        for (int jj = 0; jj <= N; ++jj) {
-          const double cw = ctab[q] * ((jj == 0 || jj == N) ? 0.5 : 1.0);
-          s0 = s0 + col[jj] * cw;
-          s1 = s1 + col[n1 + jj] * cw;
-          s2 = s2 + col[2 * n1 + jj] * cw;
-          q += n;
-          if (q >= 2 * N) q -= 2 * N;
-        }
-        const double sc = ((n == 0) ? 1.0 : 2.0) / N;
-        const double2 xa0 = x[mo + n], xa1 = x[cs + mo + n], xa2 = x[2 * cs + mo + n];
-        fu = (s0 * sc + cd(xa * xa0.x, xa * xa0.y)) * re;
-        fv = (s1 * sc + cd(xa * xa1.x, xa * xa1.y)) * re;
-        fw = (s2 * sc + cd(xa * xa2.x, xa * xa2.y)) * re;
-      } else {
-        const double2 a = g[mo + n];
-        const double2 b = g[cs + mo + n];
-        const double2 c = g[2 * cs + mo + n];
-        fu = cd(re * a.x, re * a.y);
-        fv = cd(re * b.x, re * b.y);
-        fw = cd(re * c.x, re * c.y);
-      }
+      const double2 a = g[mo + n];
+      const double2 b = g[cs + mo + n];
+      const double2 c = g[2 * cs + mo + n];
+      fu = cd(re * a.x, re * a.y);
+      fv = cd(re * b.x, re * b.y);
+      fw = cd(re * c.x, re * c.y);
     }
     if (mean) {
       Rv[n] = -fu;  // (0,0): u and w solve Dirichlet Helmholtz problems
@@ -713,42 +547,6 @@ static int chunk_for(int P, int total, size_t elem) {
   return k;
 }
 
-hipError_t launch_synth_tab(sp_plan* p, const double2* u, int which, void* out, bool fp32) {
-  const Dims& d = p->d;
-  FieldTab tab{};
-  if (which == 0) {  // forward: u, du/dy, v, w, dw/dy
-    tab.n = 5;
-    const int c[5] = {0, 0, 1, 2, 2}, m[5] = {0, 1, 0, 0, 1};
-    for (int i = 0; i < 5; ++i) {
-      tab.comp[i] = c[i];
-      tab.mat[i] = m[i];
-    }
-  } else {  // adjoint of the analysis: Tinv^T on each component
-    tab.n = 3;
-    for (int i = 0; i < 3; ++i) {
-      tab.comp[i] = i;
-      tab.mat[i] = 2;
-    }
-  }
-  dim3 grid((d.nx + 15) / 16, (d.ny + 15) / 16, d.nzm * tab.n);
-  SP_PROF_BEGIN(p, KID_SYNTH_Y);
-  if (fp32) {
-    size_t sh = 16 * d.ny * (sizeof(float2) + sizeof(float));
-    hipLaunchKernelGGL(k_synth_y<float>, grid, dim3(256), sh, p->stream, u, tab, p->f_T, p->f_TD,
-                       p->f_TinvT, (float2*)out, d.nx, d.ny, d.nzh, d.nzm);
-  } else {
-    size_t sh = 16 * d.ny * (sizeof(double2) + sizeof(double));
-    hipLaunchKernelGGL(k_synth_y<double>, grid, dim3(256), sh, p->stream, u, tab, p->d_T, p->d_TD,
-                       p->d_TinvT, (double2*)out, d.nx, d.ny, d.nzh, d.nzm);
-  }
-  SP_PROF_END(p, KID_SYNTH_Y);
-  return hipGetLastError();
-}
-
-hipError_t launch_synth_y(sp_plan* p, const double2* u, bool fp32) {
-  return launch_synth_tab(p, u, 0, p->yv, fp32);
-}
-
 hipError_t launch_fft_x_inv_gen(sp_plan* p, const void* in, void* out, int nfields, int plain,
                                 bool fp32) {
   const Dims& d = p->d;
@@ -780,7 +578,8 @@ hipError_t launch_fft_x_inv(sp_plan* p, bool fp32) {
   return launch_fft_x_inv_gen(p, p->yv, p->xp, 6, 0, fp32);
 }
 
-hipError_t launch_z_product(sp_plan* p, int mode, bool fp32) {
+// LDS Stockham fallback for z lengths without a register kernel (zline.hip)
+hipError_t launch_z_product_lds(sp_plan* p, int mode, bool fp32) {
   const Dims& d = p->d;
   const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
   int xc = (int)((48 * 1024 - d.pz * el) / (2 * 3 * lds_line(d.pz) * el));
@@ -837,57 +636,17 @@ hipError_t launch_fft_x_fwd(sp_plan* p, bool fp32) {
   return launch_fft_x_fwd_gen(p, p->np, p->nv, 3, fp32);
 }
 
-hipError_t launch_analysis_rhs(sp_plan* p, const double2* x, double a, double2* g, bool fp32) {
-  const Dims& d = p->d;
-  dim3 grid((d.nx + 15) / 16, (d.ny + 15) / 16, d.nzh * 3);
-  SP_PROF_BEGIN(p, KID_ANALYSIS);
-  if (fp32) {
-    size_t sh = 16 * d.ny * (sizeof(float2) + sizeof(float));
-    hipLaunchKernelGGL(k_analysis_rhs<float>, grid, dim3(256), sh, p->stream,
-                       (const float2*)p->nv, p->f_Tinv, x, a, g, d.nx, d.ny, d.nzh, d.nzm);
-  } else {
-    size_t sh = 16 * d.ny * (sizeof(double2) + sizeof(double));
-    hipLaunchKernelGGL(k_analysis_rhs<double>, grid, dim3(256), sh, p->stream,
-                       (const double2*)p->nv, p->d_Tinv, x, a, g, d.nx, d.ny, d.nzh, d.nzm);
-  }
-  SP_PROF_END(p, KID_ANALYSIS);
-  return hipGetLastError();
-}
-
 int solve_lanes_per_chain(int ny) { return ((ny - 1) / 2 + 1 + 31) / 32; }
 
 hipError_t launch_stokes_solve(sp_plan* p, const double2* g, double2* out, int inhomogeneous) {
   const Dims& d = p->d;
   const size_t sh = (size_t)p->mode_stride * sizeof(double) + 3 * (size_t)d.ny * sizeof(double) +
-                    2 * (size_t)d.N * sizeof(double) + 10 * (size_t)d.ny * sizeof(cd);
+                    10 * (size_t)d.ny * sizeof(cd);
   SP_PROF_BEGIN(p, KID_SOLVE);
-#define SP_SOLVE_LAUNCH(EV)                                                                      \
-  hipLaunchKernelGGL((k_stokes_solve<EV, false>), dim3(d.nx * d.nzh), dim3(64), sh, p->stream, g, \
-                     out, p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh, d.alpha,         \
-                     d.gamma, d.re, d.inv_dt, d.wall_upper, d.wall_lower, inhomogeneous, nullptr,  \
-                     nullptr, 0.0, nullptr)
-  switch (solve_lanes_per_chain(d.ny)) {
-    case 1: SP_SOLVE_LAUNCH(1); break;
-    case 2: SP_SOLVE_LAUNCH(2); break;
-    default: SP_SOLVE_LAUNCH(3); break;
-  }
-#undef SP_SOLVE_LAUNCH
-  SP_PROF_END(p, KID_SOLVE);
-  return hipGetLastError();
-}
-
-// Chebyshev analysis of p->nv fused into the solve: out = S(Tinv nv + xa * x).
-hipError_t launch_analysis_solve(sp_plan* p, const double2* x, double xa, double2* out,
-                                 int inhomogeneous) {
-  const Dims& d = p->d;
-  const size_t sh = (size_t)p->mode_stride * sizeof(double) + 3 * (size_t)d.ny * sizeof(double) +
-                    2 * (size_t)d.N * sizeof(double) + 13 * (size_t)d.ny * sizeof(cd);
-  SP_PROF_BEGIN(p, KID_SOLVE);
-#define SP_SOLVE_LAUNCH(EV)                                                                     \
-  hipLaunchKernelGGL((k_stokes_solve<EV, true>), dim3(d.nx * d.nzh), dim3(64), sh, p->stream,   \
-                     nullptr, out, p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh,        \
-                     d.alpha, d.gamma, d.re, d.inv_dt, d.wall_upper, d.wall_lower, inhomogeneous, \
-                     (const double2*)p->nv, x, xa, p->d_ctab)
+#define SP_SOLVE_LAUNCH(EV)                                                                  \
+  hipLaunchKernelGGL((k_stokes_solve<EV>), dim3(d.nx * d.nzh), dim3(64), sh, p->stream, g, out, \
+                     p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh, d.alpha, d.gamma,  \
+                     d.re, d.inv_dt, d.wall_upper, d.wall_lower, inhomogeneous)
   switch (solve_lanes_per_chain(d.ny)) {
     case 1: SP_SOLVE_LAUNCH(1); break;
     case 2: SP_SOLVE_LAUNCH(2); break;

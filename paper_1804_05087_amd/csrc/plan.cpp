@@ -3,6 +3,7 @@
 // influence matrices) and device allocation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -205,7 +206,7 @@ static std::vector<F> convert(const std::vector<D>& v) {
 static void free_plan(sp_plan* p) {
   void* ptrs[] = {p->d_T,   p->d_TD,  p->d_Tinv, p->d_G,    p->d_hw,   p->d_mode, p->d_twx,
                   p->d_twz, p->f_twx, p->f_twz,  p->f_T,    p->f_TD,   p->f_Tinv, p->d_scratch,
-                  p->d_TinvT, p->f_TinvT, p->d_ctab};
+                  p->d_yfrag, p->f_yfrag};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (p->h_partial) (void)hipHostFree(p->h_partial);
@@ -276,18 +277,41 @@ extern "C" sp_status sp_plan_create(const sp_params* prm, void* hip_stream, sp_p
   if ((s = upload(p, (void**)&p->d_TD, TD.data(), mb, "upload TD"))) return fail(s);
   if ((s = upload(p, (void**)&p->d_Tinv, Tinv.data(), mb, "upload Tinv"))) return fail(s);
   if ((s = upload(p, (void**)&p->d_G, G.data(), mb, "upload G"))) return fail(s);
-  std::vector<double> TinvT(Tinv.size());
-  for (int a = 0; a < d.ny; ++a)
-    for (int b = 0; b < d.ny; ++b) TinvT[(size_t)a * d.ny + b] = Tinv[(size_t)b * d.ny + a];
-  if ((s = upload(p, (void**)&p->d_TinvT, TinvT.data(), mb, "upload TinvT"))) return fail(s);
   {
     auto fT = convert<float>(T), fTD = convert<float>(TD), fTi = convert<float>(Tinv);
-    auto fTiT = convert<float>(TinvT);
     const size_t fb = fT.size() * sizeof(float);
     if ((s = upload(p, (void**)&p->f_T, fT.data(), fb, "upload fT"))) return fail(s);
     if ((s = upload(p, (void**)&p->f_TD, fTD.data(), fb, "upload fTD"))) return fail(s);
     if ((s = upload(p, (void**)&p->f_Tinv, fTi.data(), fb, "upload fTinv"))) return fail(s);
-    if ((s = upload(p, (void**)&p->f_TinvT, fTiT.data(), fb, "upload fTinvT"))) return fail(s);
+  }
+  {
+    // MFMA fragment tables of the six y-contraction matrices
+    const int ny = d.ny, nt = ny / 16, ks = ycontract_ks(ny);
+    const size_t per = std::max<size_t>((size_t)nt * ks * 64, 64);
+    std::vector<double> fr((size_t)YM_COUNT * per, 0.0);
+    auto elem = [&](int m, int r, int c) -> double {
+      switch (m) {
+        case YM_T: return T[(size_t)r * ny + c];
+        case YM_TD: return TD[(size_t)r * ny + c];
+        case YM_TINV_T: return Tinv[(size_t)c * ny + r];
+        case YM_TINV: return Tinv[(size_t)r * ny + c];
+        case YM_T_T: return T[(size_t)c * ny + r];
+        default: return TD[(size_t)c * ny + r];
+      }
+    };
+    for (int m = 0; m < YM_COUNT; ++m)
+      for (int t = 0; t < nt; ++t)
+        for (int st = 0; st < ks; ++st)
+          for (int l = 0; l < 64; ++l) {
+            const int r = 16 * t + l % 16, c = 4 * st + l / 16;
+            if (c < ny) fr[m * per + ((size_t)t * ks + st) * 64 + l] = elem(m, r, c);
+          }
+    p->yfrag_stride = per;
+    if ((s = upload(p, (void**)&p->d_yfrag, fr.data(), fr.size() * sizeof(double), "yfrag")))
+      return fail(s);
+    auto ff = convert<float>(fr);
+    if ((s = upload(p, (void**)&p->f_yfrag, ff.data(), ff.size() * sizeof(float), "fyfrag")))
+      return fail(s);
   }
   {
     auto tx = twiddles(d.px), tz = twiddles(d.pz);
@@ -302,14 +326,6 @@ extern "C" sp_status sp_plan_create(const sp_params* prm, void* hip_stream, sp_p
       return fail(s);
   }
   if ((s = build_mode_data(p))) return fail(s);
-  {
-    std::vector<double> ctab(2 * d.N);
-    const long double pi = 3.141592653589793238462643383279502884L;
-    for (int q = 0; q < 2 * d.N; ++q) ctab[q] = (double)cosl(pi * (long double)q / (long double)d.N);
-    if ((s = upload(p, (void**)&p->d_ctab, ctab.data(), ctab.size() * sizeof(double), "ctab")))
-      return fail(s);
-  }
-
   // scratch: one allocation carved into 256-byte aligned pieces
   const size_t cz = sizeof(double2);
   const size_t canon = (size_t)3 * d.nx * d.nzh * d.ny * cz;

@@ -35,6 +35,15 @@ struct FFTPlan1D {
   int rad[12] = {0};
 };
 
+// The y-contractions (Chebyshev synthesis/analysis and their adjoints) run as
+// 16x16x4 MFMAs: ny rows split into ny/16 full tiles (the rest on the vector
+// unit) and the ny-long sums into ycontract_ks(ny) steps of 4.
+enum YMatId { YM_T = 0, YM_TD, YM_TINV_T, YM_TINV, YM_T_T, YM_TD_T, YM_COUNT };
+inline int ycontract_ks(int ny) {
+  const int k = (ny + 3) / 4;
+  return k <= 5 ? 5 : k <= 9 ? 9 : k <= 17 ? 17 : k <= 25 ? 25 : 33;
+}
+
 struct Dims {
   int nx, ny, nz, N, nzh, nzm, px, pz;
   double alpha, gamma, re, dt, inv_dt, wall_upper, wall_lower;
@@ -55,7 +64,6 @@ struct sp_plan {
   double* d_Tinv = nullptr;   // [ny][ny] analysis
   double* d_G = nullptr;      // [ny][ny] Gram matrix int T_n T_m
   double* d_hw = nullptr;     // [3][ny] Helmholtz right-hand-side weights
-  double* d_ctab = nullptr;   // [2N] cos(pi q / N) for the fused Chebyshev analysis
   double* d_mode = nullptr;   // per-mode solve records
   int mode_stride = 0;
   double2* d_twx = nullptr;   // [px] exp(-2 pi i k / px)
@@ -65,8 +73,11 @@ struct sp_plan {
   float* f_T = nullptr;
   float* f_TD = nullptr;
   float* f_Tinv = nullptr;
-  double* d_TinvT = nullptr;  // [ny][ny] Tinv^T (adjoint of the analysis)
-  float* f_TinvT = nullptr;
+  // y-contraction matrices in MFMA fragment order (sp::YMatId), zero padded:
+  // frag[m][t][s][l] = M_m(16 t + l % 16, 4 s + l / 16), t < ny / 16, s < ycontract_ks(ny)
+  double* d_yfrag = nullptr;
+  float* f_yfrag = nullptr;
+  size_t yfrag_stride = 0;    // elements per matrix
   sp::FFTPlan1D fx, fz;
 
   // scratch (device)
@@ -115,16 +126,12 @@ hipError_t launch_fft_x_inv_gen(sp_plan* p, const void* in, void* out, int nfiel
                                 bool fp32);
 hipError_t launch_fft_x_fwd_gen(sp_plan* p, const void* in, void* out, int nfields, bool fp32);
 // adjoint kernels (adjoint.hip)
-// nvout != NULL: also write Tinv^T out in the nv layout (FP64 path)
-hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out, void* nvout);
+hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out);
 hipError_t launch_adj_z(sp_plan* p, bool fp32);
 hipError_t launch_adj_synth(sp_plan* p, const double2* x, double a, double2* out, bool fp32);
 hipError_t launch_mean_scale(sp_plan* p, double2* a, double s);
 hipError_t launch_analysis_rhs(sp_plan* p, const double2* x, double a, double2* g, bool fp32);
 hipError_t launch_stokes_solve(sp_plan* p, const double2* g, double2* out, int inhomogeneous);
-// FP64 nv (y-valued product fields) -> Chebyshev analysis + xa * x -> solve, one kernel
-hipError_t launch_analysis_solve(sp_plan* p, const double2* x, double xa, double2* out,
-                                 int inhomogeneous);
 hipError_t launch_axpby(sp_plan* p, const double2* x, double a, const double2* y, double b,
                         double2* out, size_t n);
 hipError_t launch_norm_partial(sp_plan* p, const double2* a, double* partial, int* nblocks);
