@@ -283,4 +283,80 @@ inline bool fft_length_specialised(int P) {
   return P == 12 || P == 24 || P == 36 || P == 48 || P == 72 || P == 96 || P == 144 || P == 192;
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident DFTs for the four-step line kernels (zline.hip, xline.hip).
+// ---------------------------------------------------------------------------
+// W_N^a = exp(sign 2 pi i a / N) from the table tw[q] = exp(-2 pi i q / P).
+template <int N, int P, typename C, typename R>
+__device__ inline C wpow(int a, R sign, const C* tw) {
+  const C w = tw[((a % N) * (P / N)) % P];
+  return (sign > 0) ? conjc(w) : w;
+}
+
+// In-register DFT of length N (natural order in and out):
+// X_k = sum_n v_n exp(sign 2 pi i n k / N).
+template <int N, int P, typename C, typename R>
+__device__ inline void dft_reg(C (&v)[N], R sign, const C* tw) {
+  if constexpr (N == 1) {
+    return;
+  } else if constexpr (N == 2 || N == 3 || N == 4 || N == 8) {
+    bfly<C, R>(v, N, sign);
+  } else {
+    constexpr int A = (N % 4 == 0 && N != 12) ? 4 : ((N % 3 == 0) ? 3 : 2);
+    constexpr int B = N / A;
+    C y[N];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+      C t[A];
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) t[n1] = v[B * n1 + n2];
+      dft_reg<A, P, C, R>(t, sign, tw);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1)
+        y[n2 * A + k1] = (n2 * k1 == 0) ? t[k1] : cmul(t[k1], wpow<N, P, C, R>(n2 * k1, sign, tw));
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      C t[B];
+#pragma unroll
+      for (int n2 = 0; n2 < B; ++n2) t[n2] = y[n2 * A + k1];
+      dft_reg<B, P, C, R>(t, sign, tw);
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = t[k2];
+    }
+  }
+}
+
+// Lengths P = P1 * P2 with a register line kernel: returns P1 (0 if none).
+inline int reg_fft_split(int P) {
+  switch (P) {
+    case 12: return 4;
+    case 18: return 6;
+    case 24: return 8;
+    case 36: return 6;
+    case 48: return 8;
+    case 54: return 6;
+    case 72: return 8;
+    case 96: return 12;
+    case 108: return 12;
+    case 144: return 16;
+    default: return 0;
+  }
+}
+
+// Expands LAUNCH(P1, P2) for the supported lengths (P must pass reg_fft_split).
+#define SP_REG_FFT_DISPATCH(P, LAUNCH) \
+  switch (P) {                         \
+    case 12: LAUNCH(4, 3); break;      \
+    case 18: LAUNCH(6, 3); break;      \
+    case 24: LAUNCH(8, 3); break;      \
+    case 36: LAUNCH(6, 6); break;      \
+    case 48: LAUNCH(8, 6); break;      \
+    case 54: LAUNCH(6, 9); break;      \
+    case 72: LAUNCH(8, 9); break;      \
+    case 96: LAUNCH(12, 8); break;     \
+    case 108: LAUNCH(12, 9); break;    \
+    default: LAUNCH(16, 9); break;     \
+  }
+
 }  // namespace sp

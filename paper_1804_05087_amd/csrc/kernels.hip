@@ -547,7 +547,8 @@ static int chunk_for(int P, int total, size_t elem) {
   return k;
 }
 
-hipError_t launch_fft_x_inv_gen(sp_plan* p, const void* in, void* out, int nfields, int plain,
+// LDS Stockham fallbacks for x lengths without a register kernel (xline.hip)
+hipError_t launch_fft_x_inv_lds(sp_plan* p, const void* in, void* out, int nfields, int plain,
                                 bool fp32) {
   const Dims& d = p->d;
   const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
@@ -572,10 +573,6 @@ hipError_t launch_fft_x_inv_gen(sp_plan* p, const void* in, void* out, int nfiel
 #undef L64
   SP_PROF_END(p, KID_FFT_X_INV);
   return hipGetLastError();
-}
-
-hipError_t launch_fft_x_inv(sp_plan* p, bool fp32) {
-  return launch_fft_x_inv_gen(p, p->yv, p->xp, 6, 0, fp32);
 }
 
 // LDS Stockham fallback for z lengths without a register kernel (zline.hip)
@@ -608,7 +605,7 @@ hipError_t launch_z_product_lds(sp_plan* p, int mode, bool fp32) {
   return hipGetLastError();
 }
 
-hipError_t launch_fft_x_fwd_gen(sp_plan* p, const void* in, void* out, int nfields, bool fp32) {
+hipError_t launch_fft_x_fwd_lds(sp_plan* p, const void* in, void* out, int nfields, bool fp32) {
   const Dims& d = p->d;
   const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
   const int kc = chunk_for(d.px, d.nzm, el);
@@ -630,10 +627,6 @@ hipError_t launch_fft_x_fwd_gen(sp_plan* p, const void* in, void* out, int nfiel
 #undef L64
   SP_PROF_END(p, KID_FFT_X_FWD);
   return hipGetLastError();
-}
-
-hipError_t launch_fft_x_fwd(sp_plan* p, bool fp32) {
-  return launch_fft_x_fwd_gen(p, p->np, p->nv, 3, fp32);
 }
 
 int solve_lanes_per_chain(int ny) { return ((ny - 1) / 2 + 1 + 31) / 32; }

@@ -22,47 +22,6 @@
 
 namespace sp {
 
-// W_N^a = exp(sign 2 pi i a / N) from the table tw[q] = exp(-2 pi i q / P).
-template <int N, int P, typename C, typename R>
-__device__ inline C wpow(int a, R sign, const C* tw) {
-  const C w = tw[((a % N) * (P / N)) % P];
-  return (sign > 0) ? conjc(w) : w;
-}
-
-// In-register DFT of length N (natural order in and out):
-// X_k = sum_n v_n exp(sign 2 pi i n k / N).
-template <int N, int P, typename C, typename R>
-__device__ inline void dft_reg(C (&v)[N], R sign, const C* tw) {
-  if constexpr (N == 1) {
-    return;
-  } else if constexpr (N == 2 || N == 3 || N == 4 || N == 8) {
-    bfly<C, R>(v, N, sign);
-  } else {
-    constexpr int A = (N % 4 == 0 && N != 12) ? 4 : ((N % 3 == 0) ? 3 : 2);
-    constexpr int B = N / A;
-    C y[N];
-#pragma unroll
-    for (int n2 = 0; n2 < B; ++n2) {
-      C t[A];
-#pragma unroll
-      for (int n1 = 0; n1 < A; ++n1) t[n1] = v[B * n1 + n2];
-      dft_reg<A, P, C, R>(t, sign, tw);
-#pragma unroll
-      for (int k1 = 0; k1 < A; ++k1)
-        y[n2 * A + k1] = (n2 * k1 == 0) ? t[k1] : cmul(t[k1], wpow<N, P, C, R>(n2 * k1, sign, tw));
-    }
-#pragma unroll
-    for (int k1 = 0; k1 < A; ++k1) {
-      C t[B];
-#pragma unroll
-      for (int n2 = 0; n2 < B; ++n2) t[n2] = y[n2 * A + k1];
-      dft_reg<B, P, C, R>(t, sign, tw);
-#pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = t[k2];
-    }
-  }
-}
-
 // ------------------------------- pointwise stages -------------------------------
 // in[i]: packed physical values of input line i at one point; out[f]: packed
 // values of forward line f. bo: offset of the point in a base field.
@@ -279,23 +238,6 @@ __global__ void __launch_bounds__(256)
 hipError_t launch_z_product_lds(sp_plan* p, int mode, bool fp32);
 hipError_t launch_adj_z_lds(sp_plan* p, bool fp32);
 
-// (P1, P2) splits of the z lengths with a register kernel; 0 if none.
-static int zsplit(int P) {
-  switch (P) {
-    case 12: return 4;
-    case 18: return 6;
-    case 24: return 8;
-    case 36: return 6;
-    case 48: return 8;
-    case 54: return 6;
-    case 72: return 8;
-    case 96: return 12;
-    case 108: return 12;
-    case 144: return 16;
-    default: return 0;
-  }
-}
-
 constexpr int kZXL = 8;
 
 template <typename R, class Op>
@@ -310,24 +252,13 @@ static void zline_launch(sp_plan* p, const void* in, void* out, R* base, const v
 #define ZL(A, B)                                                                              \
   hipLaunchKernelGGL((k_zline<R, A, B, kZXL, Op>), grid, dim3(256), 0, p->stream, ci, co, base, \
                      ct, map, d.ny, d.px, d.nzm, (R)scale)
-  switch (d.pz) {
-    case 12: ZL(4, 3); break;
-    case 18: ZL(6, 3); break;
-    case 24: ZL(8, 3); break;
-    case 36: ZL(6, 6); break;
-    case 48: ZL(8, 6); break;
-    case 54: ZL(6, 9); break;
-    case 72: ZL(8, 9); break;
-    case 96: ZL(12, 8); break;
-    case 108: ZL(12, 9); break;
-    default: ZL(16, 9); break;  // 144
-  }
+  SP_REG_FFT_DISPATCH(d.pz, ZL)
 #undef ZL
 }
 
 hipError_t launch_z_product(sp_plan* p, int mode, bool fp32) {
   const Dims& d = p->d;
-  if (zsplit(d.pz) == 0) return launch_z_product_lds(p, mode, fp32);
+  if (reg_fft_split(d.pz) == 0) return launch_z_product_lds(p, mode, fp32);
   const double scale = 1.0 / ((double)d.px * d.pz);
   const ZLineMap map{{0, 2, 4}, {1, 3, 5}, {0, 2, -1}, {1, -1, -1}};
   SP_PROF_BEGIN(p, KID_Z_PRODUCT);
@@ -352,7 +283,7 @@ hipError_t launch_z_product(sp_plan* p, int mode, bool fp32) {
 
 hipError_t launch_adj_z(sp_plan* p, bool fp32) {
   const Dims& d = p->d;
-  if (zsplit(d.pz) == 0) return launch_adj_z_lds(p, fp32);
+  if (reg_fft_split(d.pz) == 0) return launch_adj_z_lds(p, fp32);
   const double scale = 1.0 / ((double)d.px * d.pz);
   const ZLineMap map{{0, 2, -1}, {1, -1, -1}, {0, 2, 4}, {1, 3, 5}};
   SP_PROF_BEGIN(p, KID_ADJ_Z);
