@@ -19,7 +19,7 @@
 
 #include "device_common.h"
 #include "solve_core.h"
-#include "solve_wave.h"
+#include "solve_row.h"
 #include "sp_internal.h"
 
 namespace sp {
@@ -27,12 +27,14 @@ namespace sp {
 // ---------------------------------------------------------------------------
 // stokes_solve_adj: out = S_0^+ w per mode (conjugate transpose of the solve
 // with homogeneous walls): the forward steps of k_stokes_solve transposed and
-// taken in reverse order. One 64-lane wave per mode, lanes 0-31 parity class 0,
-// lanes 32-63 class 1.
+// taken in reverse order. One 64-lane wave per mode, four 16-lane rows:
+// rows 0, 1 run the (v, p) chain with v of parity r, rows 2, 3 the u_perp
+// chain of parity r - 2, whose transposed Helmholtz sweep shares a step with
+// the v sweep of rows 0, 1. (0,0) mode: rows 0, 1 u, rows 2, 3 w.
 // ---------------------------------------------------------------------------
-#define SP_FOR_PAR(par, body)                       \
+#define SP_ROW_PAR(par, body)                       \
   _Pragma("unroll") for (int e_ = 0; e_ < E; ++e_) { \
-    const int n = (par) + 2 * (lane * E + e_);       \
+    const int n = (par) + 2 * (l * E + e_);          \
     if (n <= N) {                                    \
       body                                           \
     }                                                \
@@ -54,20 +56,23 @@ __global__ void __launch_bounds__(64)
   cd* Vb = Ub + n1;                               // adjoint of v
   cd* A = Vb + n1;
   cd* Tm = A + n1;
-  cd* W = Tm + n1;
-  cd* Rb = W + n1;
-  cd* Pb = Rb + n1;
+  cd* W = Tm + n1;    // scratch of rows 0, 1
+  cd* W2 = W + n1;    // scratch of rows 2, 3
+  cd* Rb = W2 + n1;
+  cd* Rb2 = Rb + n1;
+  cd* Pb = Rb2 + n1;
   cd* Db = Pb + n1;
   cd* Fpb = Db + n1;
   cd* Fpp = Fpb + n1;
   cd* Fvb = Fpp + n1;
+  cd* Dm = Fvb + n1;  // output of the idle rows
 
   const int mode = blockIdx.x;
   const int i = mode / nzh;
   const int j = mode - i * nzh;
   const int tid = threadIdx.x;
-  const int half = tid >> 5;
-  const int lane = tid & 31;
+  const int row = tid >> 4;
+  const int l = tid & 15;
   const size_t cs = (size_t)nx * nzh * ny;
   const size_t mo = ((size_t)i * nzh + j) * ny;
   const bool nyq = (i == nx / 2) || (j == nzh - 1);
@@ -79,10 +84,6 @@ __global__ void __launch_bounds__(64)
     }
     return;
   }
-  const double* src = modedata + (size_t)mode * stride;
-  #pragma unroll 8
-  for (int t = tid; t < stride; t += 64) rec[t] = src[t];
-  for (int t = tid; t < 3 * n1; t += 64) hw[t] = hw_g[t];
   const int mxv = (i < nx / 2) ? i : i - nx;
   const double kx = alpha * mxv;
   const double kz = gamma * j;
@@ -91,76 +92,114 @@ __global__ void __launch_bounds__(64)
   const double k = sqrt(k2);
   const double ik = mean ? 0.0 : 1.0 / k;
   const double lam = k2 + re * inv_dt;
-  for (int n = tid; n < n1; n += 64) {
-    const double2 a = w[mo + n];
-    const double2 b = w[cs + mo + n];
-    const double2 c = w[2 * cs + mo + n];
-    const cd ub(a.x, a.y), vb(b.x, b.y), wb(c.x, c.y);
-    if (mean) {
-      Upb[n] = ub;
-      Ub[n] = wb;
-    } else {
-      Upb[n] = (ub * kx + wb * kz) * ik;
-      Ub[n] = (ub * kz - wb * kx) * ik;
+  double2 wa[3], wb[3], wc[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {  // clamped loads, masked after (no per-load branches)
+    const int n = tid + 64 * t;
+    const int nc = n < n1 ? n : N;
+    const double keep = n < n1 ? 1.0 : 0.0;
+    wa[t] = w[mo + nc];
+    wb[t] = w[cs + mo + nc];
+    wc[t] = w[2 * cs + mo + nc];
+    wa[t] = make_double2(wa[t].x * keep, wa[t].y * keep);
+    wb[t] = make_double2(wb[t].x * keep, wb[t].y * keep);
+    wc[t] = make_double2(wc[t].x * keep, wc[t].y * keep);
+  }
+  // mode record and weights (contiguous in LDS: hw = rec + stride) in one round
+  // trip: all loads are issued before the first LDS store
+  {
+    constexpr int RPL = (416 * E + 63) / 64;  // (13 ny + 12) / 64 for ny <= 32 E - 1
+    const double* src = modedata + (size_t)mode * stride;
+    const int tot = stride + 3 * n1;
+    double rv[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int t = tid + 64 * q;
+      const int tc = t < tot ? t : tot - 1;
+      rv[q] = (tc < stride) ? src[tc] : hw_g[tc - stride];
     }
-    Vb[n] = vb;
-    Pb[n] = cd(0.0);
-    Fvb[n] = cd(0.0);
-    Fpb[n] = cd(0.0);
-    Fpp[n] = cd(0.0);
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int t = tid + 64 * q;
+      if (t < tot) rec[t] = rv[q];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const int n = tid + 64 * t;
+    if (n < n1) {
+      const cd ub(wa[t].x, wa[t].y), vb(wb[t].x, wb[t].y), wbv(wc[t].x, wc[t].y);
+      if (mean) {
+        Upb[n] = ub;
+        Ub[n] = wbv;
+      } else {
+        Upb[n] = (ub * kx + wbv * kz) * ik;
+        Ub[n] = (ub * kz - wbv * kx) * ik;
+      }
+      Vb[n] = vb;
+      Pb[n] = cd(0.0);
+      Fvb[n] = cd(0.0);
+      Fpb[n] = cd(0.0);
+      Fpp[n] = cd(0.0);
+    }
   }
   __syncthreads();
   const ModeLayout L{n1};
-  SweepView helm(rec + L.helm(), n1);
-  SweepView pois(rec + L.pois(), n1);
+  const SweepView helm(rec + L.helm(), n1);
+  const SweepView pois(rec + L.pois(), n1);
+  const bool vrow = row < 2;
+  const int pv = row & 1;  // v parity (rows 0, 1), u_perp / w parity (rows 2, 3)
+  const int po = 1 - pv;
   if (mean) {
-    const int p = half;
-    wsweep_T<E>(helm, hw, N, p, Upb, Rb, W, lane);
-    SP_FOR_PAR(p, Fpb[n] = -Rb[n];)
-    __syncthreads();
-    wsweep_T<E>(helm, hw, N, p, Ub, Rb, W, lane);
-    SP_FOR_PAR(p, Fpp[n] = -Rb[n];)
+    wsweep_T<E>(helm, hw, N, pv, vrow ? Upb : Ub, vrow ? Rb : Rb2, vrow ? W : W2, l);
+    if (vrow)
+      SP_ROW_PAR(pv, Fpb[n] = -Rb[n];)
+    else
+      SP_ROW_PAR(pv, Fpp[n] = -Rb2[n];)
   } else {
-    const int pv = half;
-    const int po = 1 - pv;
-    // u_perp = H(-F_perp)
-    wsweep_T<E>(helm, hw, N, po, Ub, Rb, W, lane);
-    SP_FOR_PAR(po, Fpp[n] = -Rb[n]; A[n] = mul_i(-Upb[n]) * ik;)
+    // u_par = i D v / k (transposed): A = conj(i) u_par_bar / k on parity po
+    if (vrow) SP_ROW_PAR(po, A[n] = mul_i(-Upb[n]) * ik;)
     __syncthreads();
-    // u_par = i D v / k
-    wderiv_T<E>(N, po, A, Tm, W, lane);
+    wderiv_T<E>(N, po, vrow ? A : Ub, vrow ? Tm : Dm, vrow ? W : W2, l);
     __syncthreads();
-    SP_FOR_PAR(pv, Vb[n] = Vb[n] + Tm[n];)
+    if (vrow) SP_ROW_PAR(pv, Vb[n] = Vb[n] + Tm[n];)
     __syncthreads();
     // v = v_p + c_delta v_delta + c_b v_b, (c_delta, c_b) = -Minv (l_a, l_b)
     const double* vdel = rec + L.vdel();
     const double* vbs = rec + L.vb();
     cd ca(0.0), cbb(0.0);
-    SP_FOR_PAR(pv, ca = ca + Vb[n] * vdel[n]; cbb = cbb + Vb[n] * vbs[n];)
-    ca = sum32(ca);
-    cbb = sum32(cbb);
+    SP_ROW_PAR(pv, ca = ca + Vb[n] * vdel[n]; cbb = cbb + Vb[n] * vbs[n];)
+    ca = row_sum(ca);
+    cbb = row_sum(cbb);
     const double* Mi = rec + L.minv() + 4 * pv;
     const cd la = -(ca * Mi[0] + cbb * Mi[2]);
     const cd lb = -(ca * Mi[1] + cbb * Mi[3]);
     const int m = (N % 2 == pv) ? N : N - 1;
-    SP_FOR_PAR(pv, Vb[n] = Vb[n] + la * ((double)n * n) + ((n == m) ? lb * lam : cd(0.0));)
-    SP_FOR_PAR(po, if (n == N && m == N - 1) Pb[n] = Pb[n] + lb * (2.0 * N);)
     __syncthreads();
-    // v_p = H(D P - F_v)
-    wsweep_T<E>(helm, hw, N, pv, Vb, Rb, W, lane);
-    SP_FOR_PAR(pv, Fvb[n] = -Rb[n];)
+    if (vrow) {
+      SP_ROW_PAR(pv, Vb[n] = Vb[n] + la * ((double)n * n) + ((n == m) ? lb * lam : cd(0.0));)
+      SP_ROW_PAR(po, if (n == N && m == N - 1) Pb[n] = Pb[n] + lb * (2.0 * N);)
+    }
     __syncthreads();
-    wderiv_T<E>(N, pv, Rb, Tm, W, lane);
+    // v_p = H(D P - F_v) on rows 0, 1; u_perp = H(-F_perp) on rows 2, 3
+    wsweep_T<E>(helm, hw, N, pv, vrow ? Vb : Ub, vrow ? Rb : Rb2, vrow ? W : W2, l);
+    if (vrow)
+      SP_ROW_PAR(pv, Fvb[n] = -Rb[n];)
+    else
+      SP_ROW_PAR(pv, Fpp[n] = -Rb2[n];)
     __syncthreads();
-    SP_FOR_PAR(po, Pb[n] = Pb[n] + Tm[n];)
+    wderiv_T<E>(N, pv, vrow ? Rb : Ub, vrow ? Tm : Dm, vrow ? W : W2, l);
+    __syncthreads();
+    if (vrow) SP_ROW_PAR(po, Pb[n] = Pb[n] + Tm[n];)
     __syncthreads();
     // P = Pois(div F), div F = i k F_par + D F_v
-    wsweep_T<E>(pois, hw, N, po, Pb, Db, W, lane);
-    SP_FOR_PAR(po, Fpb[n] = mul_i(-Db[n]) * k;)
+    wsweep_T<E>(vrow ? pois : helm, hw, N, vrow ? po : pv, vrow ? Pb : Ub, vrow ? Db : Dm,
+                vrow ? W : W2, l);
+    if (vrow) SP_ROW_PAR(po, Fpb[n] = mul_i(-Db[n]) * k;)
     __syncthreads();
-    wderiv_T<E>(N, po, Db, Tm, W, lane);
+    wderiv_T<E>(N, po, vrow ? Db : Ub, vrow ? Tm : Dm, vrow ? W : W2, l);
     __syncthreads();
-    SP_FOR_PAR(pv, Fvb[n] = Fvb[n] + Tm[n];)
+    if (vrow) SP_ROW_PAR(pv, Fvb[n] = Fvb[n] + Tm[n];)
   }
   __syncthreads();
   for (int n = tid; n < n1; n += 64) {
@@ -300,7 +339,7 @@ int solve_lanes_per_chain(int ny);
 hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out) {
   const Dims& d = p->d;
   const size_t sh = (size_t)p->mode_stride * sizeof(double) + 3 * (size_t)d.ny * sizeof(double) +
-                    12 * (size_t)d.ny * sizeof(cd);
+                    15 * (size_t)d.ny * sizeof(cd);
   SP_PROF_BEGIN(p, KID_SOLVE_ADJ);
 #define SP_SOLVE_ADJ_LAUNCH(EV)                                                                \
   hipLaunchKernelGGL((k_stokes_solve_adj<EV>), dim3(d.nx * d.nzh), dim3(64), sh, p->stream, w, \
@@ -309,7 +348,9 @@ hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out) {
   switch (solve_lanes_per_chain(d.ny)) {
     case 1: SP_SOLVE_ADJ_LAUNCH(1); break;
     case 2: SP_SOLVE_ADJ_LAUNCH(2); break;
-    default: SP_SOLVE_ADJ_LAUNCH(3); break;
+    case 3: SP_SOLVE_ADJ_LAUNCH(3); break;
+    case 4: SP_SOLVE_ADJ_LAUNCH(4); break;
+    default: SP_SOLVE_ADJ_LAUNCH(5); break;
   }
 #undef SP_SOLVE_ADJ_LAUNCH
   SP_PROF_END(p, KID_SOLVE_ADJ);

@@ -19,7 +19,7 @@
 
 #include "device_common.h"
 #include "solve_core.h"
-#include "solve_wave.h"
+#include "solve_row.h"
 #include "sp_internal.h"
 
 namespace sp {
@@ -254,15 +254,20 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------
-// stokes_solve: per-mode implicit solve (FP64). One 64-lane wave per mode:
-// lanes 0-31 run parity class 0 (v even), lanes 32-63 class 1, each chain as
-// 32-lane scans (solve_wave.h).
+// stokes_solve: per-mode implicit solve (FP64), paper Sec. 2 (the constrained
+// inverse of I - dt L) in the Chebyshev-tau / influence-matrix form.
 // out = S(g): velocity of (1/Re) Lap phi - phi/dt - grad p = -g, div phi = 0,
 // walls (wall_upper, wall_lower) for the (0,0) mode when inhomogeneous, else 0.
+// One 64-lane wave per mode, four 16-lane rows (solve_row.h):
+//   rows 0, 1: the coupled (v, p) chain with v of parity r (p of the other),
+//   rows 2, 3: the decoupled u_perp Helmholtz problem on parity r - 2, swept in
+//              the same instruction stream as the Poisson sweep of rows 0, 1.
+// (0,0) mode: rows 0, 1 solve for u (parity r), rows 2, 3 for w (parity r - 2).
+// Rows without work in a step run it on a dummy array.
 // ---------------------------------------------------------------------------
-#define SP_FOR_PAR(par, body)                       \
+#define SP_ROW_PAR(par, body)                       \
   _Pragma("unroll") for (int e_ = 0; e_ < E; ++e_) { \
-    const int n = (par) + 2 * (lane * E + e_);       \
+    const int n = (par) + 2 * (l * E + e_);          \
     if (n <= N) {                                    \
       body                                           \
     }                                                \
@@ -281,21 +286,21 @@ __global__ void __launch_bounds__(64)
   double* hw = rec + stride;
   cd* Fpar = reinterpret_cast<cd*>(hw + 3 * n1);
   cd* Fv = Fpar + n1;
-  cd* Fperp = Fv + n1;
-  cd* A = Fperp + n1;
+  cd* A = Fv + n1;
   cd* divF = A + n1;
   cd* P = divF + n1;
   cd* Rv = P + n1;
   cd* V = Rv + n1;
   cd* Rp = V + n1;
   cd* U = Rp + n1;
+  cd* Dm = U + n1;  // output of the idle rows
 
   const int mode = blockIdx.x;
   const int i = mode / nzh;
   const int j = mode - i * nzh;
   const int tid = threadIdx.x;
-  const int half = tid >> 5;
-  const int lane = tid & 31;
+  const int row = tid >> 4;
+  const int l = tid & 15;
   const size_t cs = (size_t)nx * nzh * ny;  // component stride
   const size_t mo = ((size_t)i * nzh + j) * ny;
   const bool nyq = (i == nx / 2) || (j == nzh - 1);
@@ -307,10 +312,6 @@ __global__ void __launch_bounds__(64)
     }
     return;
   }
-  const double* src = modedata + (size_t)mode * stride;
-  #pragma unroll 8
-  for (int t = tid; t < stride; t += 64) rec[t] = src[t];
-  for (int t = tid; t < 3 * n1; t += 64) hw[t] = hw_g[t];
   const int mxv = (i < nx / 2) ? i : i - nx;
   const double kx = alpha * mxv;
   const double kz = gamma * j;
@@ -319,54 +320,87 @@ __global__ void __launch_bounds__(64)
   const double k = sqrt(k2);
   const double ik = mean ? 0.0 : 1.0 / k;
   const double lam = k2 + re * inv_dt;
-  for (int n = tid; n < n1; n += 64) {
-    cd fu, fv, fw;
-    if (n <= N - 2) {
-      const double2 a = g[mo + n];
-      const double2 b = g[cs + mo + n];
-      const double2 c = g[2 * cs + mo + n];
-      fu = cd(re * a.x, re * a.y);
-      fv = cd(re * b.x, re * b.y);
-      fw = cd(re * c.x, re * c.y);
+  // right-hand side columns first (registers), then the mode record, so the
+  // global loads overlap
+  double2 ga[3], gb[3], gc[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {  // clamped loads, masked after (no per-load branches)
+    const int n = tid + 64 * t;
+    const int nc = n <= N - 2 ? n : N - 2;
+    const double keep = n <= N - 2 ? 1.0 : 0.0;
+    ga[t] = g[mo + nc];
+    gb[t] = g[cs + mo + nc];
+    gc[t] = g[2 * cs + mo + nc];
+    ga[t] = make_double2(ga[t].x * keep, ga[t].y * keep);
+    gb[t] = make_double2(gb[t].x * keep, gb[t].y * keep);
+    gc[t] = make_double2(gc[t].x * keep, gc[t].y * keep);
+  }
+  // mode record and weights (contiguous in LDS: hw = rec + stride) in one round
+  // trip: all loads are issued before the first LDS store
+  {
+    constexpr int RPL = (416 * E + 63) / 64;  // (13 ny + 12) / 64 for ny <= 32 E - 1
+    const double* src = modedata + (size_t)mode * stride;
+    const int tot = stride + 3 * n1;
+    double rv[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int t = tid + 64 * q;
+      const int tc = t < tot ? t : tot - 1;
+      rv[q] = (tc < stride) ? src[tc] : hw_g[tc - stride];
     }
-    if (mean) {
-      Rv[n] = -fu;  // (0,0): u and w solve Dirichlet Helmholtz problems
-      Rp[n] = -fw;
-    } else {
-      Fpar[n] = (fu * kx + fw * kz) * ik;
-      Fperp[n] = (fu * kz - fw * kx) * ik;
-      Fv[n] = fv;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int t = tid + 64 * q;
+      if (t < tot) rec[t] = rv[q];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const int n = tid + 64 * t;
+    if (n < n1) {
+      const cd fu(re * ga[t].x, re * ga[t].y);
+      const cd fv(re * gb[t].x, re * gb[t].y);
+      const cd fw(re * gc[t].x, re * gc[t].y);
+      if (mean) {
+        Rv[n] = -fu;  // (0,0): u and w solve Dirichlet Helmholtz problems
+        Rp[n] = -fw;
+      } else {
+        Fpar[n] = (fu * kx + fw * kz) * ik;
+        Rp[n] = -((fu * kz - fw * kx) * ik);  // -F_perp
+        Fv[n] = fv;
+      }
     }
   }
   __syncthreads();
   const ModeLayout L{n1};
-  SweepView helm(rec + L.helm(), n1);
-  SweepView pois(rec + L.pois(), n1);
+  const SweepView helm(rec + L.helm(), n1);
+  const SweepView pois(rec + L.pois(), n1);
+  const bool vrow = row < 2;
+  const int pv = row & 1;  // v parity (rows 0, 1), u_perp / w parity (rows 2, 3)
+  const int po = 1 - pv;
   if (mean) {
-    const int p = half;
     cd bu(0.0);
-    if (inhomogeneous) bu = cd(p == 0 ? 0.5 * (wu + wl) : 0.5 * (wu - wl));
-    wsweep<E>(helm, hw, N, p, Rv, bu, P, lane);
-    wsweep<E>(helm, hw, N, p, Rp, cd(0.0), U, lane);
+    if (inhomogeneous && vrow) bu = cd(pv == 0 ? 0.5 * (wu + wl) : 0.5 * (wu - wl));
+    wsweep<E>(helm, hw, N, pv, vrow ? Rv : Rp, bu, vrow ? P : U, l);
   } else {
-    const int pv = half;
-    const int po = 1 - pv;
-    wderiv<E>(N, pv, Fv, A, lane);
+    wderiv<E>(N, pv, vrow ? Fv : Rp, vrow ? A : Dm, l);
     __syncthreads();
-    SP_FOR_PAR(po, divF[n] = mul_i(Fpar[n] * k) + A[n];)
+    if (vrow) SP_ROW_PAR(po, divF[n] = mul_i(Fpar[n] * k) + A[n];)
     __syncthreads();
-    wsweep<E>(pois, hw, N, po, divF, cd(0.0), P, lane);
+    // P = Pois(div F) on rows 0, 1; U = Helm(-F_perp) on rows 2, 3
+    wsweep<E>(vrow ? pois : helm, hw, N, vrow ? po : pv, vrow ? divF : Rp, cd(0.0),
+              vrow ? P : U, l);
     __syncthreads();
-    wderiv<E>(N, po, P, A, lane);
+    wderiv<E>(N, po, vrow ? P : Rp, vrow ? A : Dm, l);
     __syncthreads();
-    SP_FOR_PAR(pv, Rv[n] = A[n] - Fv[n];)
+    if (vrow) SP_ROW_PAR(pv, Rv[n] = A[n] - Fv[n];)
     __syncthreads();
-    wsweep<E>(helm, hw, N, pv, Rv, cd(0.0), V, lane);
+    wsweep<E>(helm, hw, N, pv, vrow ? Rv : Rp, cd(0.0), vrow ? V : Dm, l);
     __syncthreads();
     // influence correction: (c_delta, c_b) = -Minv (D v(1), tau definition)
     cd la(0.0);
-    SP_FOR_PAR(pv, la = la + V[n] * ((double)n * n);)
-    la = sum32(la);
+    SP_ROW_PAR(pv, la = la + V[n] * ((double)n * n);)
+    la = row_sum(la);
     const int m = (N % 2 == pv) ? N : N - 1;
     cd lb = V[m] * lam;
     if (m == N - 1) lb = lb + P[N] * (2.0 * N);
@@ -376,12 +410,9 @@ __global__ void __launch_bounds__(64)
     const double* vdel = rec + L.vdel();
     const double* vb = rec + L.vb();
     __syncthreads();
-    SP_FOR_PAR(pv, V[n] = V[n] + ca * vdel[n] + cb * vb[n];)
+    if (vrow) SP_ROW_PAR(pv, V[n] = V[n] + ca * vdel[n] + cb * vb[n];)
     __syncthreads();
-    wderiv<E>(N, pv, V, A, lane);
-    SP_FOR_PAR(po, Rp[n] = -Fperp[n];)
-    __syncthreads();
-    wsweep<E>(helm, hw, N, po, Rp, cd(0.0), U, lane);
+    wderiv<E>(N, pv, vrow ? V : Rp, vrow ? A : Dm, l);
   }
   __syncthreads();
   for (int n = tid; n < n1; n += 64) {
@@ -629,7 +660,8 @@ hipError_t launch_fft_x_fwd_lds(sp_plan* p, const void* in, void* out, int nfiel
   return hipGetLastError();
 }
 
-int solve_lanes_per_chain(int ny) { return ((ny - 1) / 2 + 1 + 31) / 32; }
+// elements per lane of a 16-lane row covering one parity chain (ny <= 129)
+int solve_lanes_per_chain(int ny) { return ((ny - 1) / 2 + 1 + 15) / 16; }
 
 hipError_t launch_stokes_solve(sp_plan* p, const double2* g, double2* out, int inhomogeneous) {
   const Dims& d = p->d;
@@ -643,7 +675,9 @@ hipError_t launch_stokes_solve(sp_plan* p, const double2* g, double2* out, int i
   switch (solve_lanes_per_chain(d.ny)) {
     case 1: SP_SOLVE_LAUNCH(1); break;
     case 2: SP_SOLVE_LAUNCH(2); break;
-    default: SP_SOLVE_LAUNCH(3); break;
+    case 3: SP_SOLVE_LAUNCH(3); break;
+    case 4: SP_SOLVE_LAUNCH(4); break;
+    default: SP_SOLVE_LAUNCH(5); break;
   }
 #undef SP_SOLVE_LAUNCH
   SP_PROF_END(p, KID_SOLVE);
