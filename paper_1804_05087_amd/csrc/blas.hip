@@ -8,57 +8,76 @@
 
 namespace sp {
 
-__device__ inline double packed_weight(size_t t, int nx, int ny, int nzh) {
-  const int j = (int)((t / ny) % nzh);
-  const int i = (int)((t / ((size_t)ny * nzh)) % nx);
-  if (i == nx / 2 || j == nzh - 1) return 0.0;
-  if (j > 0) return 1.0;
-  return (i == 0) ? 1.0 : 0.5;
-}
-
-// partial[v * nb + block] = block's share of <V_v, w>, v = 0..nvec-1.
-// V is nvec contiguous canonical vectors of n complex entries. Vectors are
-// taken eight at a time: each thread streams its grid-strided entries of w
-// once per group, then the eight sums are reduced with wave shuffles.
+// partial[(v * NR + r) * nb + chunk] = a chunk's share of <V_v, w_r>,
+// v = 0..nvec-1, r < NR (one or two right-hand vectors). V is nvec contiguous
+// canonical vectors of n complex entries. Block (chunk, g) owns 256 * kDotEPT
+// consecutive entries and the vectors 32 g .. 32 g + 31: each thread keeps its
+// weighted entries of the w_r in registers (weights computed once), streams
+// the vectors eight at a time, and the sums are reduced with wave shuffles
+// and LDS.
 constexpr int kDotGroup = 8;
+constexpr int kDotEPT = 4;
+constexpr int kDotVecs = 32;
 
+template <int NR>
 __global__ void __launch_bounds__(256)
-    k_multidot(const double2* __restrict__ V, int nvec, const double2* __restrict__ w,
-               double* __restrict__ partial, size_t n, int nx, int ny, int nzh) {
-  __shared__ double red[4][kDotGroup];
+    k_multidot(const double2* __restrict__ V, int nvec, const double2* __restrict__ w0,
+               const double2* __restrict__ w1, double* __restrict__ partial, int n, int nx,
+               int ny, int nzh) {
+  __shared__ double red[4][kDotGroup * NR];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (int v0 = 0; v0 < nvec; v0 += kDotGroup) {
-    const int nv = (nvec - v0 < kDotGroup) ? nvec - v0 : kDotGroup;
-    double acc[kDotGroup];
+  const int t0 = blockIdx.x * 256 * kDotEPT + threadIdx.x;
+  double wr[NR][kDotEPT], wi[NR][kDotEPT];
+  int tc[kDotEPT];
 #pragma unroll
-    for (int q = 0; q < kDotGroup; ++q) acc[q] = 0.0;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
-      const double wt = packed_weight(t, nx, ny, nzh);
-      const double2 x = w[t];
-      const double wr = wt * x.x, wi = wt * x.y;
+  for (int i = 0; i < kDotEPT; ++i) {
+    const int t = t0 + 256 * i;
+    tc[i] = t < n ? t : n - 1;
+    const int j = (tc[i] / ny) % nzh;
+    const int m = (tc[i] / (ny * nzh)) % nx;
+    double wt = (m == nx / 2 || j == nzh - 1) ? 0.0 : (j > 0 ? 1.0 : (m == 0 ? 1.0 : 0.5));
+    if (t >= n) wt = 0.0;
 #pragma unroll
-      for (int q = 0; q < kDotGroup; ++q) {
-        if (q < nv) {
-          const double2 a = V[(size_t)(v0 + q) * n + t];
-          acc[q] += a.x * wr + a.y * wi;
-        }
+    for (int r = 0; r < NR; ++r) {
+      const double2 x = (r == 0 ? w0 : w1)[tc[i]];
+      wr[r][i] = wt * x.x;
+      wi[r][i] = wt * x.y;
+    }
+  }
+  const int vbeg = blockIdx.y * kDotVecs;
+  const int vend = min(nvec, vbeg + kDotVecs);
+  for (int v0 = vbeg; v0 < vend; v0 += kDotGroup) {
+    double acc[kDotGroup * NR];
+#pragma unroll
+    for (int q = 0; q < kDotGroup; ++q) {
+      const int v = (v0 + q < vend) ? v0 + q : vend - 1;  // clamped; extra sums are dropped
+      const double2* Vv = V + (size_t)v * n;
+      double2 av[kDotEPT];
+#pragma unroll
+      for (int i = 0; i < kDotEPT; ++i) av[i] = Vv[tc[i]];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < kDotEPT; ++i) s += av[i].x * wr[r][i] + av[i].y * wi[r][i];
+        acc[q * NR + r] = s;
       }
     }
 #pragma unroll
-    for (int q = 0; q < kDotGroup; ++q) {
+    for (int q = 0; q < kDotGroup * NR; ++q) {
 #pragma unroll
       for (int d = 32; d >= 1; d >>= 1) acc[q] += __shfl_xor(acc[q], d);
     }
     if (lane == 0) {
 #pragma unroll
-      for (int q = 0; q < kDotGroup; ++q) red[wid][q] = acc[q];
+      for (int q = 0; q < kDotGroup * NR; ++q) red[wid][q] = acc[q];
     }
     __syncthreads();
-    if (threadIdx.x < nv)
-      partial[(size_t)(v0 + threadIdx.x) * gridDim.x + blockIdx.x] =
-          red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+    const int q = threadIdx.x;
+    if (q < kDotGroup * NR && v0 + q / NR < vend)
+      partial[((size_t)v0 * NR + q) * gridDim.x + blockIdx.x] =
+          red[0][q] + red[1][q] + red[2][q] + red[3][q];
     __syncthreads();
   }
 }
@@ -79,22 +98,74 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0) out[v] = red[0];
 }
 
-// w = beta * w + alpha * sum_v h[v] V_v   (h in device memory)
+// w = beta * w + alpha * sum_v h[v] V_v   (h in device memory). One entry per
+// thread; the vector loop is unrolled by eight so eight loads are in flight.
 __global__ void __launch_bounds__(256)
     k_multiaxpy(const double2* __restrict__ V, int nvec, const double* __restrict__ h,
-                double alpha, double beta, double2* __restrict__ w, size_t n) {
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
-       t += (size_t)gridDim.x * blockDim.x) {
-    double rx = 0.0, ry = 0.0;
-    for (int v = 0; v < nvec; ++v) {
-      const double c = h[v];
-      const double2 a = V[(size_t)v * n + t];
-      rx += c * a.x;
-      ry += c * a.y;
+                double alpha, double beta, double2* __restrict__ w, int n) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  double rx = 0.0, ry = 0.0;
+  int v = 0;
+  for (; v + 8 <= nvec; v += 8) {
+    double2 a[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = V[(size_t)(v + q) * n + t];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double c = h[v + q];
+      rx += c * a[q].x;
+      ry += c * a[q].y;
     }
-    const double2 o = w[t];
-    w[t] = make_double2(beta * o.x + alpha * rx, beta * o.y + alpha * ry);
   }
+  for (; v < nvec; ++v) {
+    const double c = h[v];
+    const double2 a = V[(size_t)v * n + t];
+    rx += c * a.x;
+    ry += c * a.y;
+  }
+  const double2 o = w[t];
+  w[t] = make_double2(beta * o.x + alpha * rx, beta * o.y + alpha * ry);
+}
+
+// One pass of the delayed-reorthogonalisation Arnoldi step (newton.cpp):
+//   q    = (u - sum_{i<j} a_i V_i) * inv_gamma            (written over u = V_j)
+//   unew = w * inv_gamma - sum_{i<j} c_i V_i - c_j q
+// Each V_i is read once for both sums.
+__global__ void __launch_bounds__(256)
+    k_dcgs2_update(double2* V, int j, const double* __restrict__ a, const double* __restrict__ c,
+                   double inv_gamma, const double2* __restrict__ w, double2* __restrict__ unew,
+                   int n) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  double ax = 0.0, ay = 0.0, cx = 0.0, cy = 0.0;
+  int i = 0;
+  for (; i + 8 <= j; i += 8) {
+    double2 v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = V[(size_t)(i + q) * n + t];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double ai = a[i + q], ci = c[i + q];
+      ax += ai * v[q].x;
+      ay += ai * v[q].y;
+      cx += ci * v[q].x;
+      cy += ci * v[q].y;
+    }
+  }
+  for (; i < j; ++i) {
+    const double2 v = V[(size_t)i * n + t];
+    ax += a[i] * v.x;
+    ay += a[i] * v.y;
+    cx += c[i] * v.x;
+    cy += c[i] * v.y;
+  }
+  const double2 u = V[(size_t)j * n + t];
+  const double qx = (u.x - ax) * inv_gamma, qy = (u.y - ay) * inv_gamma;
+  V[(size_t)j * n + t] = make_double2(qx, qy);
+  const double2 wv = w[t];
+  const double cj = c[j];
+  unew[t] = make_double2(wv.x * inv_gamma - cx - cj * qx, wv.y * inv_gamma - cy - cj * qy);
 }
 
 // x = s * y
@@ -140,14 +211,19 @@ static int nblocks_for(size_t n) {
   return (int)b;
 }
 
+int multidot_blocks(const sp_plan* p) {
+  const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
+  return (n + 256 * kDotEPT - 1) / (256 * kDotEPT);  // element chunks
+}
+
 hipError_t launch_multidot(sp_plan* p, const double2* V, int nvec, const double2* w,
                            double* partial, double* out, int* nb_out) {
-  const size_t n = (size_t)3 * p->d.nx * p->d.nzh * p->d.ny;
-  int nb = nblocks_for(n);
-  if (nb > 256) nb = 256;
+  const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
+  const int nb = multidot_blocks(p);
   SP_PROF_BEGIN(p, KID_MULTIDOT);
-  hipLaunchKernelGGL(k_multidot, dim3(nb), dim3(256), 0, p->stream, V, nvec, w, partial, n, p->d.nx,
-                     p->d.ny, p->d.nzh);
+  const dim3 grid(nb, (nvec + kDotVecs - 1) / kDotVecs);
+  hipLaunchKernelGGL(k_multidot<1>, grid, dim3(256), 0, p->stream, V, nvec, w, w, partial, n,
+                     p->d.nx, p->d.ny, p->d.nzh);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_rows, dim3(nvec), dim3(256), 0, p->stream, partial, nb, out);
@@ -156,12 +232,37 @@ hipError_t launch_multidot(sp_plan* p, const double2* V, int nvec, const double2
   return hipGetLastError();
 }
 
+hipError_t launch_multidot2(sp_plan* p, const double2* V, int nvec, const double2* w0,
+                            const double2* w1, double* partial, double* out) {
+  const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
+  const int nb = multidot_blocks(p);
+  SP_PROF_BEGIN(p, KID_MULTIDOT);
+  const dim3 grid(nb, (nvec + kDotVecs - 1) / kDotVecs);
+  hipLaunchKernelGGL(k_multidot<2>, grid, dim3(256), 0, p->stream, V, nvec, w0, w1, partial, n,
+                     p->d.nx, p->d.ny, p->d.nzh);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_rows, dim3(2 * nvec), dim3(256), 0, p->stream, partial, nb, out);
+  SP_PROF_END(p, KID_MULTIDOT);
+  return hipGetLastError();
+}
+
 hipError_t launch_multiaxpy(sp_plan* p, const double2* V, int nvec, const double* h, double alpha,
                             double beta, double2* w) {
-  const size_t n = (size_t)3 * p->d.nx * p->d.nzh * p->d.ny;
+  const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
   SP_PROF_BEGIN(p, KID_MULTIAXPY);
-  hipLaunchKernelGGL(k_multiaxpy, dim3(nblocks_for(n)), dim3(256), 0, p->stream, V, nvec, h, alpha,
+  hipLaunchKernelGGL(k_multiaxpy, dim3((n + 255) / 256), dim3(256), 0, p->stream, V, nvec, h, alpha,
                      beta, w, n);
+  SP_PROF_END(p, KID_MULTIAXPY);
+  return hipGetLastError();
+}
+
+hipError_t launch_dcgs2_update(sp_plan* p, double2* V, int j, const double* a, const double* c,
+                              double inv_gamma, const double2* w, double2* unew) {
+  const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
+  SP_PROF_BEGIN(p, KID_MULTIAXPY);
+  hipLaunchKernelGGL(k_dcgs2_update, dim3((n + 255) / 256), dim3(256), 0, p->stream, V, j, a, c,
+                     inv_gamma, w, unew, n);
   SP_PROF_END(p, KID_MULTIAXPY);
   return hipGetLastError();
 }

@@ -1,11 +1,25 @@
 // Host Newton-GMRES driver (paper Sec. 2, eqs. linear, biglin, Kspace).
 //
 // Newton: U <- U - du with J_r(U) du = r(U), r = (Phi_dt(U) - U)/dt.
-// GMRES: unrestarted, x0 = 0, Arnoldi with classical Gram-Schmidt applied
-// twice (CGS2) on the device, the Hessenberg column read back once per
-// iteration, Givens rotations and the least-squares solve on the host.
-// The residual, its norm and the orthogonalisation are FP64; the Jacobian
-// actions use the plan's precision.
+// GMRES: unrestarted, x0 = 0, Givens rotations and the least-squares solve on
+// the host. The residual, its norm and the orthogonalisation are FP64; the
+// Jacobian actions use the plan's precision.
+//
+// Arnoldi orthogonalisation: classical Gram-Schmidt with the second
+// (re-orthogonalising) pass delayed by one iteration, so every iteration reads
+// the basis twice instead of four times (the delayed CGS2 of Swirydowicz,
+// Langou et al., "Low synchronization Gram-Schmidt and GMRES algorithms").
+// Iteration j holds u_j, the first-pass-orthogonalised candidate for q_j, and
+// its image w = A u_j. One fused reduction gives a = Q^T u_j, b = Q^T w,
+// u_j^T u_j and u_j^T w (Q = q_0..q_{j-1}); then
+//   gamma_j = sqrt(u_j^T u_j - a^T a),  q_j = (u_j - Q a) / gamma_j,
+//   column j-1 of H: h_{j-1} + a, subdiagonal gamma_j (u_j = A q_{j-1} - Q h_{j-1}),
+//   A q_j = (w - A Q a) / gamma_j with A Q a = Q_{j+1} H a (Arnoldi relation),
+//   h_j = Q_{j+1}^T A q_j  from b, u_j^T w and H a,
+//   u_{j+1} = A q_j - Q_{j+1} h_j = w / gamma_j - Q_{j+1} (H a / gamma_j + h_j),
+// and one fused pass over Q writes q_j and u_{j+1}. The GMRES residual of the
+// j-dimensional space is known once column j-1 is complete, one iteration
+// after the Jacobian action that produced it.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -40,8 +54,8 @@ size_t ws_bytes_for(const sp_plan* p, int K) {
   b += align256((size_t)(K + 1) * canon_bytes(p));         // Krylov basis
   b += align256(canon_bytes(p));                           // w
   b += align256(canon_bytes(p));                           // scratch field
-  b += align256((size_t)(K + 1) * kMultidotBlocks * sizeof(double));  // partials
-  b += 3 * align256((size_t)(K + 2) * sizeof(double));     // h1, h2, y
+  b += align256((size_t)2 * (K + 1) * multidot_blocks(p) * sizeof(double));  // partials
+  b += 3 * align256((size_t)2 * (K + 2) * sizeof(double));  // dots, a|c, y
   return b;
 }
 
@@ -65,11 +79,11 @@ Workspace carve(sp_plan* p, int K) {
   W.s = (double2*)c;
   c += align256(canon_bytes(p));
   W.partial = (double*)c;
-  c += align256((size_t)(K + 1) * kMultidotBlocks * sizeof(double));
+  c += align256((size_t)2 * (K + 1) * multidot_blocks(p) * sizeof(double));
   W.h1 = (double*)c;
-  c += align256((size_t)(K + 2) * sizeof(double));
+  c += align256((size_t)2 * (K + 2) * sizeof(double));
   W.h2 = (double*)c;
-  c += align256((size_t)(K + 2) * sizeof(double));
+  c += align256((size_t)2 * (K + 2) * sizeof(double));
   W.y = (double*)c;
   return W;
 }
@@ -140,18 +154,24 @@ extern "C" sp_status sp_newton_gmres(sp_plan* p, double* u_inout, const sp_newto
   double2* U = (double2*)u_inout;
   double2* r = p->t3;
 
-  double* hbuf = nullptr;  // pinned: h1[K+2] h2[K+2] hn[1]
-  SP_TRY_HIP(hipHostMalloc((void**)&hbuf, (2 * (K + 2) + 2) * sizeof(double)), "hipHostMalloc");
+  double* hbuf = nullptr;  // pinned: dots[2(K+2)], a|c[2(K+2)]
+  SP_TRY_HIP(hipHostMalloc((void**)&hbuf, 4 * (K + 2) * sizeof(double)), "hipHostMalloc");
   struct Free {
     double* b;
     ~Free() { (void)hipHostFree(b); }
   } guard{hbuf};
-  double* hh1 = hbuf;
-  double* hh2 = hbuf + (K + 2);
-  double* hn = hbuf + 2 * (K + 2);
+  double* hdots = hbuf;             // [2 v + r]: r = 0 against u_j, r = 1 against w
+  double* hac = hbuf + 2 * (K + 2);  // a[0..K+1] then c[0..K+1]
+  double* d_dots = W.h1;             // 2 (K + 2) doubles
+  double* d_ac = W.h2;               // 2 (K + 2) doubles
+  const size_t nc = canon / sizeof(double2);
 
-  std::vector<double> H((size_t)(K + 1) * K), cs(K), sn(K), gv(K + 1), yv(K);
-  auto Hat = [&](int i, int k) -> double& { return H[(size_t)i * K + k]; };
+  // H (unrotated, column-major, (K+1) x K) for the Arnoldi relation; R the
+  // Givens-rotated copy for the least squares.
+  std::vector<double> H((size_t)(K + 1) * K), R((size_t)(K + 1) * K), cs(K), sn(K), gv(K + 1),
+      yv(K), hprev(K + 1), a(K + 1), b(K + 1), Ha(K + 1), cvec(K + 1);
+  auto Hat = [&](int i, int k) -> double& { return H[(size_t)k * (K + 1) + i]; };
+  auto Rat = [&](int i, int k) -> double& { return R[(size_t)k * (K + 1) + i]; };
   const auto t0 = std::chrono::steady_clock::now();
   sp_status result = SP_ERR_NOT_CONVERGED;
   for (int it = 0; it <= o->max_newton; ++it) {
@@ -174,72 +194,105 @@ extern "C" sp_status sp_newton_gmres(sp_plan* p, double* u_inout, const sp_newto
       SP_TRY(dot_host(p, U, U, W.partial, W.h1, &u2));
       unorm = std::sqrt(u2);
     }
-    double b2 = 0.0;
-    SP_TRY(dot_host(p, r, r, W.partial, W.h1, &b2));
-    const double beta = std::sqrt(b2);
-    if (!std::isfinite(beta)) return set_error(p, SP_ERR_NONFINITE, "residual is not finite");
-    SP_TRY_HIP(launch_scale(p, r, 1.0 / beta, W.V), "scale");
+    // u_0 = r (unnormalised; gamma_0 = ||r|| comes out of the first reduction)
+    SP_TRY_HIP(hipMemcpyAsync(W.V, r, canon, hipMemcpyDeviceToDevice, p->stream), "copy r");
     SP_TRY_HIP(launch_hermitian(p, W.V), "hermitian");
     std::fill(H.begin(), H.end(), 0.0);
+    std::fill(R.begin(), R.end(), 0.0);
     std::fill(gv.begin(), gv.end(), 0.0);
-    gv[0] = beta;
+    double beta = 0.0;
     int kd = 0;
     double relres = 1.0;
-    for (int k = 0; k < K; ++k) {
-      double2* vk = W.V + (size_t)k * (canon / sizeof(double2));
-      if (o->jvp_mode == 0) {
-        SP_TRY(jvp_lin(p, SP_OP_RESIDUAL, vk, W.w));
-      } else {
-        const double eps = o->fd_eps * (unorm > 0 ? unorm : 1.0);
-        SP_TRY_HIP(launch_axpby(p, U, 1.0, vk, eps, W.s, canon / sizeof(double2)), "axpby");
-        SP_TRY(residual_into(p, W.s, W.w));
-        SP_TRY_HIP(launch_axpby(p, W.w, 1.0 / eps, r, -1.0 / eps, W.w, canon / sizeof(double2)),
-                   "axpby");
+    for (int j = 0; j <= K; ++j) {
+      double2* uj = W.V + (size_t)j * nc;
+      const bool last = (j == K);  // only completes column K-1: no new direction
+      if (!last) {
+        if (o->jvp_mode == 0) {
+          SP_TRY(jvp_lin(p, SP_OP_RESIDUAL, uj, W.w));
+        } else {
+          // finite difference along u_j / ||u_j||, scaled back by ||u_j||
+          double uu = 0.0;
+          SP_TRY(dot_host(p, uj, uj, W.partial, W.h1, &uu));
+          const double un = std::sqrt(uu > 0 ? uu : 1.0);
+          const double eps = o->fd_eps * (unorm > 0 ? unorm : 1.0) / un;
+          SP_TRY_HIP(launch_axpby(p, U, 1.0, uj, eps, W.s, nc), "axpby");
+          SP_TRY(residual_into(p, W.s, W.w));
+          SP_TRY_HIP(launch_axpby(p, W.w, 1.0 / eps, r, -1.0 / eps, W.w, nc), "axpby");
+        }
+        rep->total_actions += 1;
+        SP_TRY_HIP(launch_hermitian(p, W.w), "hermitian");
       }
-      rep->total_actions += 1;
-      SP_TRY_HIP(launch_hermitian(p, W.w), "hermitian");
-      // CGS2
-      SP_TRY_HIP(launch_multidot(p, W.V, k + 1, W.w, W.partial, W.h1, nullptr), "multidot");
-      SP_TRY_HIP(launch_multiaxpy(p, W.V, k + 1, W.h1, -1.0, 1.0, W.w), "multiaxpy");
-      SP_TRY_HIP(launch_multidot(p, W.V, k + 1, W.w, W.partial, W.h2, nullptr), "multidot");
-      SP_TRY_HIP(launch_multiaxpy(p, W.V, k + 1, W.h2, -1.0, 1.0, W.w), "multiaxpy");
-      SP_TRY_HIP(launch_multidot(p, W.w, 1, W.w, W.partial, W.y, nullptr), "norm");
-      SP_TRY_HIP(hipMemcpyAsync(hh1, W.h1, (k + 1) * sizeof(double), hipMemcpyDeviceToHost,
-                                p->stream),
-                 "copy h1");
-      SP_TRY_HIP(hipMemcpyAsync(hh2, W.h2, (k + 1) * sizeof(double), hipMemcpyDeviceToHost,
-                                p->stream),
-                 "copy h2");
-      SP_TRY_HIP(hipMemcpyAsync(hn, W.y, sizeof(double), hipMemcpyDeviceToHost, p->stream),
-                 "copy hn");
+      // dots of q_0..q_{j-1} and u_j with u_j and with w
+      SP_TRY_HIP(launch_multidot2(p, W.V, j + 1, uj, last ? uj : W.w, W.partial, d_dots),
+                 "multidot");
+      SP_TRY_HIP(hipMemcpyAsync(hdots, d_dots, 2 * (j + 1) * sizeof(double),
+                                hipMemcpyDeviceToHost, p->stream),
+                 "copy dots");
       SP_TRY_HIP(hipStreamSynchronize(p->stream), "sync");
-      for (int i = 0; i <= k; ++i) Hat(i, k) = hh1[i] + hh2[i];
-      const double hk1 = std::sqrt(hn[0] > 0 ? hn[0] : 0.0);
-      if (!std::isfinite(hk1)) return set_error(p, SP_ERR_NONFINITE, "Arnoldi norm not finite");
-      Hat(k + 1, k) = hk1;
-      if (hk1 > 0 && k + 1 < K + 1)
-        SP_TRY_HIP(launch_scale(p, W.w, 1.0 / hk1, W.V + (size_t)(k + 1) * (canon / sizeof(double2))),
-                   "scale");
-      for (int i = 0; i < k; ++i) {
-        const double t = cs[i] * Hat(i, k) + sn[i] * Hat(i + 1, k);
-        Hat(i + 1, k) = -sn[i] * Hat(i, k) + cs[i] * Hat(i + 1, k);
-        Hat(i, k) = t;
+      double aa = 0.0;
+      for (int i = 0; i < j; ++i) {
+        a[i] = hdots[2 * i];
+        b[i] = hdots[2 * i + 1];
+        aa += a[i] * a[i];
       }
-      const double dd = std::hypot(Hat(k, k), Hat(k + 1, k));
-      cs[k] = Hat(k, k) / dd;
-      sn[k] = Hat(k + 1, k) / dd;
-      Hat(k, k) = dd;
-      Hat(k + 1, k) = 0.0;
-      gv[k + 1] = -sn[k] * gv[k];
-      gv[k] = cs[k] * gv[k];
-      kd = k + 1;
-      relres = std::fabs(gv[k + 1]) / beta;
-      if (std::fabs(gv[k + 1]) <= o->gmres_rtol * beta || hk1 == 0.0) break;
+      const double alpha = hdots[2 * j];
+      const double uw = hdots[2 * j + 1];
+      const double g2 = alpha - aa;
+      if (!std::isfinite(g2)) return set_error(p, SP_ERR_NONFINITE, "Arnoldi norm not finite");
+      const double gamma = g2 > 0 ? std::sqrt(g2) : 0.0;
+      bool stop = false;
+      if (j == 0) {
+        beta = gamma;
+        if (!(beta > 0)) return set_error(p, SP_ERR_NONFINITE, "zero or non-finite residual");
+        gv[0] = beta;
+      } else {
+        // complete column j-1, rotate it, test convergence of the j-dimensional space
+        const int k = j - 1;
+        for (int i = 0; i < j; ++i) Hat(i, k) = hprev[i] + a[i];
+        Hat(j, k) = gamma;
+        for (int i = 0; i <= j; ++i) Rat(i, k) = Hat(i, k);
+        for (int i = 0; i < k; ++i) {
+          const double t = cs[i] * Rat(i, k) + sn[i] * Rat(i + 1, k);
+          Rat(i + 1, k) = -sn[i] * Rat(i, k) + cs[i] * Rat(i + 1, k);
+          Rat(i, k) = t;
+        }
+        const double dd = std::hypot(Rat(k, k), Rat(k + 1, k));
+        cs[k] = Rat(k, k) / dd;
+        sn[k] = Rat(k + 1, k) / dd;
+        Rat(k, k) = dd;
+        Rat(k + 1, k) = 0.0;
+        gv[k + 1] = -sn[k] * gv[k];
+        gv[k] = cs[k] * gv[k];
+        kd = j;
+        relres = std::fabs(gv[k + 1]) / beta;
+        stop = std::fabs(gv[k + 1]) <= o->gmres_rtol * beta || !(gamma > 0) || last;
+      }
+      if (stop) break;
+      // H a (rows 0..j) from the completed columns 0..j-1
+      std::fill(Ha.begin(), Ha.begin() + j + 1, 0.0);
+      for (int i = 0; i < j; ++i) {
+        const double ai = a[i];
+        const double* col = &H[(size_t)i * (K + 1)];
+        for (int l = 0; l <= i + 1; ++l) Ha[l] += col[l] * ai;
+      }
+      const double ig = 1.0 / gamma;
+      double ab = 0.0;
+      for (int i = 0; i < j; ++i) ab += a[i] * b[i];
+      for (int i = 0; i < j; ++i) hprev[i] = (b[i] - Ha[i]) * ig;
+      hprev[j] = ((uw - ab) * ig - Ha[j]) * ig;
+      for (int i = 0; i <= j; ++i) cvec[i] = Ha[i] * ig + hprev[i];
+      for (int i = 0; i < j; ++i) hac[i] = a[i];
+      for (int i = 0; i <= j; ++i) hac[(K + 2) + i] = cvec[i];
+      SP_TRY_HIP(hipMemcpyAsync(d_ac, hac, 2 * (K + 2) * sizeof(double), hipMemcpyHostToDevice,
+                                p->stream),
+                 "upload a, c");
+      SP_TRY_HIP(launch_dcgs2_update(p, W.V, j, d_ac, d_ac + (K + 2), ig, W.w, uj + nc),
+                 "dcgs2 update");
     }
     for (int i = kd - 1; i >= 0; --i) {
-      double s = gv[i];
-      for (int j = i + 1; j < kd; ++j) s -= Hat(i, j) * yv[j];
-      yv[i] = s / Hat(i, i);
+      double s2 = gv[i];
+      for (int j2 = i + 1; j2 < kd; ++j2) s2 -= Rat(i, j2) * yv[j2];
+      yv[i] = s2 / Rat(i, i);
     }
     SP_TRY_HIP(hipMemcpyAsync(W.y, yv.data(), kd * sizeof(double), hipMemcpyHostToDevice,
                               p->stream),

@@ -141,11 +141,19 @@ hipError_t launch_unpack(sp_plan* p, const double* packed, double2* c);
 // GMRES BLAS (blas.hip)
 hipError_t launch_multidot(sp_plan* p, const double2* V, int nvec, const double2* w,
                            double* partial, double* out, int* nb_out);
+// out[2 v + r] = <V_v, w_r> for r = 0, 1 (partial: 2 nvec multidot_blocks(p) doubles)
+hipError_t launch_multidot2(sp_plan* p, const double2* V, int nvec, const double2* w0,
+                            const double2* w1, double* partial, double* out);
 hipError_t launch_multiaxpy(sp_plan* p, const double2* V, int nvec, const double* h, double alpha,
                             double beta, double2* w);
+// V_j <- (V_j - sum_{i<j} a_i V_i) inv_gamma ; unew <- w inv_gamma - sum_{i<j} c_i V_i - c_j V_j
+hipError_t launch_dcgs2_update(sp_plan* p, double2* V, int j, const double* a, const double* c,
+                              double inv_gamma, const double2* w, double2* unew);
 hipError_t launch_scale(sp_plan* p, const double2* y, double s, double2* x);
 hipError_t launch_hermitian(sp_plan* p, double2* a);
-constexpr int kMultidotBlocks = 256;
+// element chunks of launch_multidot (1024 consecutive complex entries each); the
+// partial buffer passed to it holds nvec * multidot_blocks(p) doubles
+int multidot_blocks(const sp_plan* p);
 
 // compositions (api.cpp)
 sp_status host_norm_of(sp_plan* p, const double2* a, double* out);
