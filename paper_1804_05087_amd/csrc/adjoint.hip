@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(64)
     if (vrow) SP_ROW_PAR(po, Pb[n] = Pb[n] + Tm[n];)
     __syncthreads();
     // P = Pois(div F), div F = i k F_par + D F_v
-    wsweep_T<E>(vrow ? pois : helm, hw, N, vrow ? po : pv, vrow ? Pb : Ub, vrow ? Db : Dm,
+    wsweep_T<E>(SweepView(rec + (vrow ? L.pois() : L.helm()), n1), hw, N, vrow ? po : pv, vrow ? Pb : Ub, vrow ? Db : Dm,
                 vrow ? W : W2, l);
     if (vrow) SP_ROW_PAR(po, Fpb[n] = mul_i(-Db[n]) * k;)
     __syncthreads();

@@ -47,8 +47,7 @@ sp_status host_norm_of(sp_plan* p, const double2* a, double* out) {
 sp_status befe_into(sp_plan* p, const double2* u, double2* out, bool fp32) {
   sp_status s = nonlinear_to_nv(p, u, 0, fp32);
   if (s) return s;
-  SP_TRY_HIP(launch_analysis_rhs(p, u, p->d.inv_dt, p->g, fp32), "analysis_rhs");
-  SP_TRY_HIP(launch_stokes_solve(p, p->g, out, 1), "stokes_solve");
+  SP_TRY_HIP(launch_analysis_solve(p, u, p->d.inv_dt, out, 1, fp32), "analysis+solve");
   return SP_OK;
 }
 
@@ -74,8 +73,7 @@ sp_status jvp_lin(sp_plan* p, int op, const double2* du, double2* out) {
   sp_status s = nonlinear_to_nv(p, du, 1, fp32);
   if (s) return s;
   double2* dst = (op == SP_OP_PHI) ? out : p->t2;
-  SP_TRY_HIP(launch_analysis_rhs(p, du, p->d.inv_dt, p->g, fp32), "analysis_rhs");
-  SP_TRY_HIP(launch_stokes_solve(p, p->g, dst, 0), "stokes_solve");
+  SP_TRY_HIP(launch_analysis_solve(p, du, p->d.inv_dt, dst, 0, fp32), "analysis+solve");
   if (op != SP_OP_PHI)
     SP_TRY_HIP(launch_axpby(p, p->t2, p->d.inv_dt, du, -p->d.inv_dt, out, canon_count(p)),
                "axpby");

@@ -17,6 +17,8 @@
 // implicit solve is FP64 only.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "solve_core.h"
 #include "solve_row.h"
@@ -273,12 +275,21 @@ __global__ void __launch_bounds__(256)
     }                                                \
   }
 
-template <int E>
+// AN = 0: the right-hand side g is read from a canonical field. AN = 1 (FP64)
+// or 2 (FP32 transform path): g = Tinv nv + xa x is formed here from the
+// y-valued product fields nv [3][ny][nz/2][nx] of this mode and the canonical
+// field x (a6 fused into a7): the columns are folded into their even and odd
+// halves in y (Tinv[n][N-j] = (-1)^n Tinv[n][j]), so each lane forms its
+// coefficients n from N/2+1 terms; tinv is the folded half transposed,
+// th[j][n] = Tinv[n][j], so the lanes' loads are contiguous.
+template <int E, int AN>
 __global__ void __launch_bounds__(64)
     k_stokes_solve(const double2* __restrict__ g, double2* __restrict__ out,
                    const double* __restrict__ modedata, const double* __restrict__ hw_g,
                    int stride, int nx, int ny, int nzh, double alpha, double gamma, double re,
-                   double inv_dt, double wu, double wl, int inhomogeneous) {
+                   double inv_dt, double wu, double wl, int inhomogeneous,
+                   const void* __restrict__ nv_raw, const void* __restrict__ tinv_raw,
+                   const double2* __restrict__ x, double xa) {
   extern __shared__ unsigned char smem_raw[];
   const int N = ny - 1;
   const int n1 = ny;
@@ -294,6 +305,10 @@ __global__ void __launch_bounds__(64)
   cd* Rp = V + n1;
   cd* U = Rp + n1;
   cd* Dm = U + n1;  // output of the idle rows
+  const int jh = (ny - 1) / 2 + 1;  // folded column length (AN != 0)
+  const int jh8 = (jh + 7) & ~7;    // padded with zeros to whole groups of 8
+  cd* colE = Dm + n1;               // [3][jh8] even halves f_j + f_{N-j}
+  cd* colO = colE + 3 * jh8;        // [3][jh8] odd halves  f_j - f_{N-j}
 
   const int mode = blockIdx.x;
   const int i = mode / nzh;
@@ -323,17 +338,50 @@ __global__ void __launch_bounds__(64)
   // right-hand side columns first (registers), then the mode record, so the
   // global loads overlap
   double2 ga[3], gb[3], gc[3];
+  if constexpr (AN == 0) {
 #pragma unroll
-  for (int t = 0; t < 3; ++t) {  // clamped loads, masked after (no per-load branches)
-    const int n = tid + 64 * t;
-    const int nc = n <= N - 2 ? n : N - 2;
-    const double keep = n <= N - 2 ? 1.0 : 0.0;
-    ga[t] = g[mo + nc];
-    gb[t] = g[cs + mo + nc];
-    gc[t] = g[2 * cs + mo + nc];
-    ga[t] = make_double2(ga[t].x * keep, ga[t].y * keep);
-    gb[t] = make_double2(gb[t].x * keep, gb[t].y * keep);
-    gc[t] = make_double2(gc[t].x * keep, gc[t].y * keep);
+    for (int t = 0; t < 3; ++t) {  // clamped loads, masked after (no per-load branches)
+      const int n = tid + 64 * t;
+      const int nc = n <= N - 2 ? n : N - 2;
+      const double keep = n <= N - 2 ? 1.0 : 0.0;
+      ga[t] = g[mo + nc];
+      gb[t] = g[cs + mo + nc];
+      gc[t] = g[2 * cs + mo + nc];
+      ga[t] = make_double2(ga[t].x * keep, ga[t].y * keep);
+      gb[t] = make_double2(gb[t].x * keep, gb[t].y * keep);
+      gc[t] = make_double2(gc[t].x * keep, gc[t].y * keep);
+    }
+  } else {
+    // u/dt part of the right-hand side: issued first, consumed after the analysis
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int n = tid + 64 * t;
+      const int nc = n <= N - 2 ? n : N - 2;
+      ga[t] = x[mo + nc];
+      gb[t] = x[cs + mo + nc];
+      gc[t] = x[2 * cs + mo + nc];
+    }
+  }
+  // fold loads of the y-valued columns (AN != 0) into registers: lane jj takes
+  // f_jj and f_{N-jj}; issued before the record loads so both overlap
+  using RA = typename std::conditional<AN == 2, float, double>::type;
+  using CA = typename V2<RA>::T;
+  CA fa[2][3], fb[2][3];
+  if constexpr (AN != 0) {
+    const CA* nv = reinterpret_cast<const CA*>(nv_raw);
+    const int nzm = nzh - 1;
+    const size_t cstride = (size_t)ny * nzm * nx;
+    const size_t base = (size_t)j * nx + i;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int jj = tid + 64 * q;
+      const int jc = jj < jh ? jj : jh - 1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        fa[q][c] = nv[c * cstride + (size_t)jc * nzm * nx + base];
+        fb[q][c] = nv[c * cstride + (size_t)(N - jc) * nzm * nx + base];
+      }
+    }
   }
   // mode record and weights (contiguous in LDS: hw = rec + stride) in one round
   // trip: all loads are issued before the first LDS store
@@ -348,10 +396,74 @@ __global__ void __launch_bounds__(64)
       const int tc = t < tot ? t : tot - 1;
       rv[q] = (tc < stride) ? src[tc] : hw_g[tc - stride];
     }
+    if constexpr (AN != 0) {
+      // even / odd halves, zero padded to jh8 entries
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int jj = tid + 64 * q;
+        if (jj < jh8) {
+          const double in = jj < jh ? 1.0 : 0.0;
+          const double same = (jj == N - jj) ? 0.0 : 1.0;  // middle point counted once
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double ar = fa[q][c].x, ai = fa[q][c].y, br = fb[q][c].x, bi = fb[q][c].y;
+            colE[c * jh8 + jj] = cd((ar + same * br) * in, (ai + same * bi) * in);
+            colO[c * jh8 + jj] = cd((ar - br) * same * in, (ai - bi) * same * in);
+          }
+        }
+      }
+    }
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const int t = tid + 64 * q;
       if (t < tot) rec[t] = rv[q];
+    }
+  }
+  if constexpr (AN != 0) {
+    // g_n = sum_j Tinv[n][j] f_j + xa x_n for n <= N-2 (the tau rows), one n per lane
+    using R = typename std::conditional<AN == 2, float, double>::type;
+    const R* Ti = reinterpret_cast<const R*>(tinv_raw);
+    __syncthreads();
+    const int tmax = (N - 2) / 64 + 1;  // passes over n <= N-2 (uniform)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      if (t >= tmax) {
+        ga[t] = gb[t] = gc[t] = make_double2(0.0, 0.0);
+        continue;
+      }
+      const int n = tid + 64 * t;
+      const int nc = n <= N - 2 ? n : N - 2;
+      const cd* src = (nc & 1) ? colO : colE;
+      const R* col = Ti + nc;  // th[j][n]: consecutive n across lanes
+      R a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0;
+      {
+        for (int j0 = 0; j0 < jh8; j0 += 8) {  // branch-free: padded entries are zero
+          R tv[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) tv[q] = col[(size_t)(j0 + q < jh ? j0 + q : jh - 1) * ny];
+          cd e0[8], e1[8], e2[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            e0[q] = src[j0 + q];
+            e1[q] = src[jh8 + j0 + q];
+            e2[q] = src[2 * jh8 + j0 + q];
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            a0r += tv[q] * (R)e0[q].re;
+            a0i += tv[q] * (R)e0[q].im;
+            a1r += tv[q] * (R)e1[q].re;
+            a1i += tv[q] * (R)e1[q].im;
+            a2r += tv[q] * (R)e2[q].re;
+            a2i += tv[q] * (R)e2[q].im;
+          }
+        }
+      }
+      const double keep = n <= N - 2 ? 1.0 : 0.0;
+      const double2 x0 = ga[t], x1 = gb[t], x2 = gc[t];
+      ga[t] = make_double2(((double)a0r + xa * x0.x) * keep, ((double)a0i + xa * x0.y) * keep);
+      gb[t] = make_double2(((double)a1r + xa * x1.x) * keep, ((double)a1i + xa * x1.y) * keep);
+      gc[t] = make_double2(((double)a2r + xa * x2.x) * keep, ((double)a2i + xa * x2.y) * keep);
     }
   }
 #pragma unroll
@@ -388,7 +500,7 @@ __global__ void __launch_bounds__(64)
     if (vrow) SP_ROW_PAR(po, divF[n] = mul_i(Fpar[n] * k) + A[n];)
     __syncthreads();
     // P = Pois(div F) on rows 0, 1; U = Helm(-F_perp) on rows 2, 3
-    wsweep<E>(vrow ? pois : helm, hw, N, vrow ? po : pv, vrow ? divF : Rp, cd(0.0),
+    wsweep<E>(SweepView(rec + (vrow ? L.pois() : L.helm()), n1), hw, N, vrow ? po : pv, vrow ? divF : Rp, cd(0.0),
               vrow ? P : U, l);
     __syncthreads();
     wderiv<E>(N, po, vrow ? P : Rp, vrow ? A : Dm, l);
@@ -663,22 +775,55 @@ hipError_t launch_fft_x_fwd_lds(sp_plan* p, const void* in, void* out, int nfiel
 // elements per lane of a 16-lane row covering one parity chain (ny <= 129)
 int solve_lanes_per_chain(int ny) { return ((ny - 1) / 2 + 1 + 15) / 16; }
 
+static size_t solve_lds_bytes(const sp_plan* p, bool fused) {
+  const Dims& d = p->d;
+  const int jh8 = (((d.ny - 1) / 2 + 1) + 7) & ~7;
+  return (size_t)p->mode_stride * sizeof(double) + 3 * (size_t)d.ny * sizeof(double) +
+         10 * (size_t)d.ny * sizeof(cd) + (fused ? 6 * (size_t)jh8 * sizeof(cd) : 0);
+}
+
+#define SP_SOLVE_DISPATCH(LAUNCH)                   \
+  switch (solve_lanes_per_chain(p->d.ny)) {         \
+    case 1: LAUNCH(1); break;                       \
+    case 2: LAUNCH(2); break;                       \
+    case 3: LAUNCH(3); break;                       \
+    case 4: LAUNCH(4); break;                       \
+    default: LAUNCH(5); break;                      \
+  }
+
 hipError_t launch_stokes_solve(sp_plan* p, const double2* g, double2* out, int inhomogeneous) {
   const Dims& d = p->d;
-  const size_t sh = (size_t)p->mode_stride * sizeof(double) + 3 * (size_t)d.ny * sizeof(double) +
-                    10 * (size_t)d.ny * sizeof(cd);
+  const size_t sh = solve_lds_bytes(p, false);
   SP_PROF_BEGIN(p, KID_SOLVE);
-#define SP_SOLVE_LAUNCH(EV)                                                                  \
-  hipLaunchKernelGGL((k_stokes_solve<EV>), dim3(d.nx * d.nzh), dim3(64), sh, p->stream, g, out, \
-                     p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh, d.alpha, d.gamma,  \
-                     d.re, d.inv_dt, d.wall_upper, d.wall_lower, inhomogeneous)
-  switch (solve_lanes_per_chain(d.ny)) {
-    case 1: SP_SOLVE_LAUNCH(1); break;
-    case 2: SP_SOLVE_LAUNCH(2); break;
-    case 3: SP_SOLVE_LAUNCH(3); break;
-    case 4: SP_SOLVE_LAUNCH(4); break;
-    default: SP_SOLVE_LAUNCH(5); break;
-  }
+#define SP_SOLVE_LAUNCH(EV)                                                                     \
+  hipLaunchKernelGGL((k_stokes_solve<EV, 0>), dim3(d.nx * d.nzh), dim3(64), sh, p->stream, g,   \
+                     out, p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh, d.alpha,       \
+                     d.gamma, d.re, d.inv_dt, d.wall_upper, d.wall_lower, inhomogeneous, nullptr, \
+                     nullptr, nullptr, 0.0)
+  SP_SOLVE_DISPATCH(SP_SOLVE_LAUNCH)
+#undef SP_SOLVE_LAUNCH
+  SP_PROF_END(p, KID_SOLVE);
+  return hipGetLastError();
+}
+
+// Chebyshev analysis of p->nv fused into the solve: out = S(Tinv nv + xa x).
+hipError_t launch_analysis_solve(sp_plan* p, const double2* x, double xa, double2* out,
+                                 int inhomogeneous, bool fp32) {
+  const Dims& d = p->d;
+  const size_t sh = solve_lds_bytes(p, true);
+  SP_PROF_BEGIN(p, KID_SOLVE);
+#define SP_SOLVE_LAUNCH(EV)                                                                       \
+  if (fp32)                                                                                       \
+    hipLaunchKernelGGL((k_stokes_solve<EV, 2>), dim3(d.nx * d.nzh), dim3(64), sh, p->stream,      \
+                       nullptr, out, p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh,      \
+                       d.alpha, d.gamma, d.re, d.inv_dt, d.wall_upper, d.wall_lower,             \
+                       inhomogeneous, p->nv, p->f_tinv_th, x, xa);                                   \
+  else                                                                                            \
+    hipLaunchKernelGGL((k_stokes_solve<EV, 1>), dim3(d.nx * d.nzh), dim3(64), sh, p->stream,      \
+                       nullptr, out, p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh,      \
+                       d.alpha, d.gamma, d.re, d.inv_dt, d.wall_upper, d.wall_lower,             \
+                       inhomogeneous, p->nv, p->d_tinv_th, x, xa)
+  SP_SOLVE_DISPATCH(SP_SOLVE_LAUNCH)
 #undef SP_SOLVE_LAUNCH
   SP_PROF_END(p, KID_SOLVE);
   return hipGetLastError();

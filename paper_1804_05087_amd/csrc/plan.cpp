@@ -206,7 +206,7 @@ static std::vector<F> convert(const std::vector<D>& v) {
 static void free_plan(sp_plan* p) {
   void* ptrs[] = {p->d_T,   p->d_TD,  p->d_Tinv, p->d_G,    p->d_hw,   p->d_mode, p->d_twx,
                   p->d_twz, p->f_twx, p->f_twz,  p->f_T,    p->f_TD,   p->f_Tinv, p->d_scratch,
-                  p->d_yfrag, p->f_yfrag};
+                  p->d_yfrag, p->f_yfrag, p->d_tinv_th, p->f_tinv_th};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (p->h_partial) (void)hipHostFree(p->h_partial);
@@ -283,6 +283,17 @@ extern "C" sp_status sp_plan_create(const sp_params* prm, void* hip_stream, sp_p
     if ((s = upload(p, (void**)&p->f_T, fT.data(), fb, "upload fT"))) return fail(s);
     if ((s = upload(p, (void**)&p->f_TD, fTD.data(), fb, "upload fTD"))) return fail(s);
     if ((s = upload(p, (void**)&p->f_Tinv, fTi.data(), fb, "upload fTinv"))) return fail(s);
+  }
+  {
+    const int jh = (d.ny - 1) / 2 + 1;
+    std::vector<double> th((size_t)jh * d.ny);
+    for (int j = 0; j < jh; ++j)
+      for (int n = 0; n < d.ny; ++n) th[(size_t)j * d.ny + n] = Tinv[(size_t)n * d.ny + j];
+    if ((s = upload(p, (void**)&p->d_tinv_th, th.data(), th.size() * sizeof(double), "tinv_th")))
+      return fail(s);
+    auto fth = convert<float>(th);
+    if ((s = upload(p, (void**)&p->f_tinv_th, fth.data(), fth.size() * sizeof(float), "ftinv_th")))
+      return fail(s);
   }
   {
     // MFMA fragment tables of the six y-contraction matrices

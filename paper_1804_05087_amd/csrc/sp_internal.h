@@ -75,6 +75,9 @@ struct sp_plan {
   float* f_Tinv = nullptr;
   // y-contraction matrices in MFMA fragment order (sp::YMatId), zero padded:
   // frag[m][t][s][l] = M_m(16 t + l % 16, 4 s + l / 16), t < ny / 16, s < ycontract_ks(ny)
+  // Tinv transposed over the folded half: th[j][n] = Tinv[n][j], j <= N/2 (fused analysis)
+  double* d_tinv_th = nullptr;
+  float* f_tinv_th = nullptr;
   double* d_yfrag = nullptr;
   float* f_yfrag = nullptr;
   size_t yfrag_stride = 0;    // elements per matrix
@@ -132,6 +135,9 @@ hipError_t launch_adj_synth(sp_plan* p, const double2* x, double a, double2* out
 hipError_t launch_mean_scale(sp_plan* p, double2* a, double s);
 hipError_t launch_analysis_rhs(sp_plan* p, const double2* x, double a, double2* g, bool fp32);
 hipError_t launch_stokes_solve(sp_plan* p, const double2* g, double2* out, int inhomogeneous);
+// y-valued product fields p->nv -> Chebyshev analysis + xa * x -> solve, one kernel
+hipError_t launch_analysis_solve(sp_plan* p, const double2* x, double xa, double2* out,
+                                 int inhomogeneous, bool fp32);
 hipError_t launch_axpby(sp_plan* p, const double2* x, double a, const double2* y, double b,
                         double2* out, size_t n);
 hipError_t launch_norm_partial(sp_plan* p, const double2* a, double* partial, int* nblocks);
