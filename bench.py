@@ -48,6 +48,7 @@ CAL_COPY_BYTES = 256 * 1024 * 1024
 # sources the counters were taken with: a changed source reports traffic null.
 SOLVE_SOURCES = ["kernels.hip", "solve_row.h", "solve_core.h"]
 MEASURED_TRAFFIC = {}
+STAGE_OF_KERNEL = {}  # profiler kernel name -> sp_time_stage stage (filled in main)
 
 
 def solve_sources_sha256():
@@ -81,7 +82,8 @@ def algorithmic_bytes(w, fp32=False, jvp=False):
         "k_z_product": 6 * xp1 + 3 * xp1 + (6 * ny * px * pz * r if jvp else 0),
         "k_fft_x_fwd": 3 * xp1 + 3 * yv1,
         "k_analysis_rhs": 3 * yv1 + 2 * canon,
-        "k_stokes_solve": 2 * canon + modes * stride * 8 + 3 * n1 * 8,
+        # FP64 step: the analysis is fused into the solve (reads nv and u, writes Phi)
+        "k_stokes_solve": 3 * yv1 + 2 * canon + modes * stride * 8 + 3 * n1 * 8,
     }
 
 
@@ -170,7 +172,12 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
-    from paper_1804_05087_amd import SP_FP64, SP_MIXED, SP_OP_RESIDUAL, Plan, synth
+    from paper_1804_05087_amd import (SP_FP64, SP_MIXED, SP_OP_RESIDUAL, SP_STAGE_SOLVE,
+                                      SP_STAGE_SYNTH, SP_STAGE_XFWD, SP_STAGE_XINV,
+                                      SP_STAGE_ZLINE, Plan, synth)
+    STAGE_OF_KERNEL.update({"k_synth_y": SP_STAGE_SYNTH, "k_fft_x_inv": SP_STAGE_XINV,
+                            "k_z_product": SP_STAGE_ZLINE, "k_fft_x_fwd": SP_STAGE_XFWD,
+                            "k_stokes_solve": SP_STAGE_SOLVE})
 
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
@@ -227,15 +234,12 @@ def main():
     d = kernels[dom]
     dom_us = d["avg_us"]
     timing = "hip events around each launch"
-    if dom == "k_stokes_solve":
-        # the solve has an entry point of its own: time back-to-back launches of
-        # just that kernel between two events on the plan's stream
-        g = P.nonlinear(u)
+    stage = STAGE_OF_KERNEL.get(dom)
+    if stage is not None:
+        # back-to-back launches of just that kernel between two events on the plan's stream
         reps = max(50, min(1000, args.steps))
-        gs, _ = time_loop(torch, lambda: P.stokes_solve(g, out, True), reps, 10)
-        dom_us = 1e6 * gs / reps
-        timing = f"hip events around {reps} back-to-back launches"
-        del g
+        dom_us = P.time_stage(stage, u, out, reps=reps)
+        timing = f"hip events around {reps} back-to-back launches (sp_time_stage)"
     alg = d.get("alg_bytes")
     achieved = round(alg / (dom_us * 1e-6) / 1e9, 1) if alg else 0.0
     traffic = None

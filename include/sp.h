@@ -188,6 +188,24 @@ sp_status sp_profile_enable(sp_plan* plan, int32_t on);
 sp_status sp_profile_read(sp_plan* plan, int32_t n_max, char* names, int64_t* counts,
                           double* total_ms, int32_t* n_out, int32_t reset);
 
+/* Stage timing (measurement aid). Evaluates Phi_dt(u) into out once, then
+ * launches the kernel of one stage of that evaluation reps times back to back
+ * on the plan's stream, between two HIP events, on the scratch state the
+ * evaluation left (each stage reads its input buffer and writes its output
+ * buffer, so repeated launches recompute the same result). Synchronises and
+ * writes the average duration per launch in microseconds to *avg_us. On
+ * return out holds Phi_dt(u). stage: SP_STAGE_*; reps in [1, 100000]; u and
+ * out as for sp_befe_step, out must not alias u. Uses the plan's precision. */
+typedef enum {
+  SP_STAGE_SYNTH = 0, /* y-synthesis of u, du/dy, v, w, dw/dy (Sec. 3.2) */
+  SP_STAGE_XINV = 1,  /* curl factors, 3/2 padding, inverse x FFT */
+  SP_STAGE_ZLINE = 2, /* inverse z FFT, u x omega, forward z FFT */
+  SP_STAGE_XFWD = 3,  /* forward x FFT, truncation */
+  SP_STAGE_SOLVE = 4  /* Chebyshev analysis + u/dt + per-mode implicit solve */
+} sp_stage;
+sp_status sp_time_stage(sp_plan* plan, int32_t stage, const double* u, double* out, int32_t reps,
+                        double* avg_us);
+
 const char* sp_status_string(sp_status s);
 const char* sp_last_error(const sp_plan* plan);
 

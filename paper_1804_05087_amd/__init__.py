@@ -10,10 +10,12 @@ import ctypes as C
 import math
 
 from . import _lib
-from ._lib import SP_FP64, SP_MIXED, SP_OP_PHI, SP_OP_RESIDUAL, SPError
+from ._lib import (SP_FP64, SP_MIXED, SP_OP_PHI, SP_OP_RESIDUAL, SP_STAGE_SOLVE, SP_STAGE_SYNTH,
+                   SP_STAGE_XFWD, SP_STAGE_XINV, SP_STAGE_ZLINE, SPError)
 
 __all__ = ["Plan", "PhiFunction", "SPError", "SP_FP64", "SP_MIXED", "SP_OP_PHI",
-           "SP_OP_RESIDUAL", "couette_box"]
+           "SP_OP_RESIDUAL", "SP_STAGE_SYNTH", "SP_STAGE_XINV", "SP_STAGE_ZLINE", "SP_STAGE_XFWD",
+           "SP_STAGE_SOLVE", "couette_box"]
 
 
 def couette_box():
@@ -165,6 +167,15 @@ class Plan:
         out = self.empty() if out is None else out
         self._check(self.lib.sp_unpack(self.h, self._packed(x, "x"), self._field(out, "out")))
         return out
+
+    def time_stage(self, stage: int, u, out=None, reps: int = 100) -> float:
+        """Average microseconds per launch of one stage kernel of Phi_dt(u)
+        (SP_STAGE_*), launched back to back; out receives Phi_dt(u)."""
+        out = self.empty() if out is None else out
+        us = C.c_double(0.0)
+        self._check(self.lib.sp_time_stage(self.h, int(stage), self._field(u, "u"),
+                                           self._field(out, "out"), int(reps), C.byref(us)))
+        return us.value
 
     def profile_enable(self, on: bool = True):
         self._check(self.lib.sp_profile_enable(self.h, 1 if on else 0))

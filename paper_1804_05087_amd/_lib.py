@@ -18,6 +18,7 @@ SP_FP64 = 0
 SP_MIXED = 1
 SP_OP_PHI = 0
 SP_OP_RESIDUAL = 1
+SP_STAGE_SYNTH, SP_STAGE_XINV, SP_STAGE_ZLINE, SP_STAGE_XFWD, SP_STAGE_SOLVE = 0, 1, 2, 3, 4
 
 
 class sp_params(C.Structure):
@@ -72,6 +73,8 @@ SIGNATURES = {
     "sp_newton_gmres": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(sp_newton_opts),
                                   C.POINTER(sp_newton_report)]),
     "sp_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
+    "sp_time_stage": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                C.POINTER(C.c_double)]),
     "sp_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.POINTER(C.c_int64),
                                   C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_int32]),
     "sp_status_string": (C.c_char_p, [C.c_int]),

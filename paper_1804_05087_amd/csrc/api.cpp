@@ -213,3 +213,45 @@ extern "C" sp_status sp_profile_read(sp_plan* p, int32_t n_max, char* names, int
   if (reset) p->prof.reset();
   return SP_OK;
 }
+
+extern "C" sp_status sp_time_stage(sp_plan* p, int32_t stage, const double* u, double* out,
+                                   int32_t reps, double* avg_us) {
+  CHECK_PLAN();
+  CHECK_PTR(u);
+  CHECK_PTR(out);
+  CHECK_PTR(avg_us);
+  if (u == out) return set_error(p, SP_ERR_INVALID, "sp_time_stage: out aliases u");
+  if (stage < SP_STAGE_SYNTH || stage > SP_STAGE_SOLVE)
+    return set_error(p, SP_ERR_INVALID, "sp_time_stage: unknown stage");
+  if (reps < 1 || reps > 100000) return set_error(p, SP_ERR_INVALID, "sp_time_stage: bad reps");
+  const bool fp32 = (p->precision == SP_MIXED);
+  const double2* uu = (const double2*)u;
+  double2* oo = (double2*)out;
+  sp_status s = befe_into(p, uu, oo, fp32);
+  if (s) return s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  SP_TRY_HIP(hipEventCreate(&e0), "event");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return set_error(p, SP_ERR_HIP, "event");
+  }
+  hipError_t e = hipEventRecord(e0, p->stream);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    switch (stage) {
+      case SP_STAGE_SYNTH: e = launch_synth_y(p, uu, fp32); break;
+      case SP_STAGE_XINV: e = launch_fft_x_inv(p, fp32); break;
+      case SP_STAGE_ZLINE: e = launch_z_product(p, 0, fp32); break;
+      case SP_STAGE_XFWD: e = launch_fft_x_fwd(p, fp32); break;
+      default: e = launch_analysis_solve(p, uu, p->d.inv_dt, oo, 1, fp32); break;
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, p->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_check(p, e, "sp_time_stage");
+  *avg_us = 1000.0 * ms / reps;
+  return SP_OK;
+}

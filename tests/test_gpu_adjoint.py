@@ -13,7 +13,8 @@ from paper_1804_05087_amd import synth
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
 GRIDS = [(8, 9, 8, 400.0, 100.0), (16, 17, 16, 400.0, 100.0), (12, 21, 24, 1000.0, 1.0),
-         (32, 33, 32, 400.0, 100.0)]
+         (32, 33, 32, 400.0, 100.0),
+         (8, 97, 8, 400.0, 100.0), (8, 129, 8, 1000.0, 10.0)]
 
 
 @pytest.fixture(scope="module")
@@ -35,6 +36,21 @@ def _setup(dims, re, dt):
     return _cache[key]
 
 
+def _tol(case):
+    """1e-12, or machine epsilon times the largest condition number of the
+    per-mode tau systems where that is larger (tall grids): the oracle's refined
+    solve is accurate to ~1e-15, while a direct FP64 solve of the same system is
+    only backward stable, so adjoint directions that probe the ill-conditioned
+    high Chebyshev coefficients may differ by up to eps * cond."""
+    import math
+    from oracle.stokes import mode_matrix
+    nx, ny, nz, re, dt = case
+    kx, kz = 2 * math.pi / BOX[0], 2 * math.pi / BOX[1]
+    cond = max(np.linalg.cond(mode_matrix(ny - 1, a, b, re, 1.0 / dt))
+               for a, b in ((kx, 0.0), (0.0, kz)))
+    return max(TOL, np.finfo(float).eps * cond)
+
+
 @pytest.mark.parametrize("case", GRIDS)
 def test_vjp_parity(torch_mod, case):
     from paper_1804_05087_amd import SP_OP_PHI, SP_OP_RESIDUAL
@@ -44,10 +60,11 @@ def test_vjp_parity(torch_mod, case):
     u = synth.perturbation_field(nx, ny, nz, *BOX, seed=1)
     w = synth.random_spectral(nx, ny, nz, seed=3)
     P.linearize(to_dev(u))
+    tol = _tol(case)
     for op, name in ((SP_OP_PHI, "phi"), (SP_OP_RESIDUAL, "residual")):
         ref = B.vjp(u, w, name)
         got = to_np(P.vjp_lin(to_dev(w), op))
-        assert rel(got, ref) < TOL, (name, rel(got, ref))
+        assert rel(got, ref) < tol, (name, rel(got, ref), tol)
 
 
 @pytest.mark.parametrize("case", GRIDS)
@@ -63,7 +80,8 @@ def test_vjp_dot_product(torch_mod, case):
     P.linearize(u)
     lhs = torch.dot(P.pack(w), P.pack(P.jvp_lin(v, SP_OP_RESIDUAL))).item()
     rhs = torch.dot(P.pack(P.vjp_lin(w, SP_OP_RESIDUAL)), P.pack(v)).item()
-    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + abs(rhs)), (lhs, rhs)
+    tol = _tol(case)
+    assert abs(lhs - rhs) <= tol * (abs(lhs) + abs(rhs)), (lhs, rhs, tol)
 
 
 def test_dense_jacobian_transpose_8x9x8(torch_mod):

@@ -18,7 +18,8 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
 GRIDS = [(8, 9, 8, 400.0, 100.0), (16, 17, 16, 400.0, 100.0), (12, 21, 24, 1000.0, 1.0),
-         (32, 33, 32, 400.0, 10.0)]
+         (32, 33, 32, 400.0, 10.0),
+         (8, 97, 8, 400.0, 100.0), (8, 129, 8, 1000.0, 10.0)]
 
 
 @pytest.fixture(scope="module")
