@@ -46,8 +46,17 @@ CAL_COPY_BYTES = 256 * 1024 * 1024
 # --pmc WRITE_SIZE over this script (KiB per dispatch, see profiles/), the
 # calibration factors from the 256 MiB copy above, and the hash of the kernel
 # sources the counters were taken with: a changed source reports traffic null.
-SOLVE_SOURCES = ["kernels.hip", "solve_row.h", "solve_core.h"]
-MEASURED_TRAFFIC = {}
+SOLVE_SOURCES = ["kernels.hip", "solve_row.h", "solve_core.h", "device_common.h"]
+MEASURED_TRAFFIC = {
+    "couette_48x65x48_re1000_dt100": {
+        "k_stokes_solve": {
+            "fetch_kib": 6769.8, "write_kib": 3676.2,
+            # 256 MiB copy: FETCH_SIZE 131089.9 KiB, WRITE_SIZE 262144.0 KiB
+            "fetch_factor": 262144.0 / 131089.9, "write_factor": 1.0,
+            "sources_sha256": "1e309cf2481179edd0d08f414dd28eb829e06403601ded326bbfeaa67ea51ef0",
+        },
+    },
+}
 STAGE_OF_KERNEL = {}  # profiler kernel name -> sp_time_stage stage (filled in main)
 
 

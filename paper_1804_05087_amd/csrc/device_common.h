@@ -19,6 +19,19 @@ struct V2<float> {
   using T = float2;
 };
 
+// The workgroups of a launch are handed to the chip's 8 XCDs in turn
+// (workgroup b to XCD b mod 8), and each XCD has its own L2. xcd_order maps the
+// hardware workgroup index to a logical one so that every XCD receives one
+// contiguous range of logical indices (a bijection on [0, nb)): workgroups
+// whose data share cache lines then share an L2.
+__device__ inline int xcd_order(int b, int nb) {
+  constexpr int G = 8;
+  const int x = b % G;
+  const int q = nb / G;
+  const int r = nb - q * G;
+  return x * q + (x < r ? x : r) + b / G;
+}
+
 __device__ inline double2 mk(double a, double b) { return make_double2(a, b); }
 __device__ inline float2 mk(float a, float b) { return make_float2(a, b); }
 __device__ inline double2 cadd(double2 a, double2 b) { return mk(a.x + b.x, a.y + b.y); }

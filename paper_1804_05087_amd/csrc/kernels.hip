@@ -310,9 +310,12 @@ __global__ void __launch_bounds__(64)
   cd* colE = Dm + n1;               // [3][jh8] even halves f_j + f_{N-j}
   cd* colO = colE + 3 * jh8;        // [3][jh8] odd halves  f_j - f_{N-j}
 
-  const int mode = blockIdx.x;
-  const int i = mode / nzh;
-  const int j = mode - i * nzh;
+  // logical order: x mode fastest, so the modes whose product-field entries
+  // share a cache line (consecutive m_x at one m_z) run on one XCD
+  const int lo = xcd_order(blockIdx.x, gridDim.x);
+  const int j = lo / nx;
+  const int i = lo - j * nx;
+  const int mode = i * nzh + j;
   const int tid = threadIdx.x;
   const int row = tid >> 4;
   const int l = tid & 15;

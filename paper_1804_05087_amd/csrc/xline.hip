@@ -17,6 +17,20 @@
 
 namespace sp {
 
+// Logical block (y, field, z-chunk) of an x-line grid (hardware grid
+// (ny, nfields, chunks)), reordered by xcd_order with the field fastest and
+// then the chunk: the blocks of one (y, chunk), which read the same spectral
+// lines for different output fields, share an L2.
+struct XBlk {
+  int y, f, ch;
+};
+__device__ inline XBlk xline_block() {
+  const int gy = gridDim.x, gf = gridDim.y, gc = gridDim.z;
+  const int b = blockIdx.x + gy * (blockIdx.y + gf * blockIdx.z);
+  const int l = xcd_order(b, gy * gf * gc);
+  return XBlk{l / (gf * gc), l % gf, (l / gf) % gc};
+}
+
 // plain == 0: output field f of (u, v, w, omega_x, omega_y, omega_z) from the
 // five y-valued fields (u, du/dy, v, w, dw/dy) with i k_x, i k_z; plain != 0:
 // output field f is input field f.
@@ -31,9 +45,10 @@ __global__ void __launch_bounds__(128)
   extern __shared__ unsigned char smem_raw[];
   C* twl = reinterpret_cast<C*>(smem_raw);
   C* ex = twl + P;  // [kc][P2][S1]
-  const int y = blockIdx.x;
-  const int f = blockIdx.y;
-  const int kz0 = blockIdx.z * kc;
+  const XBlk bk = xline_block();
+  const int y = bk.y;
+  const int f = bk.f;
+  const int kz0 = bk.ch * kc;
   const int nl = min(kc, nzm - kz0);
   for (int t = threadIdx.x; t < P; t += blockDim.x) twl[t] = tw[t];
   __syncthreads();
@@ -109,9 +124,10 @@ __global__ void __launch_bounds__(128)
   extern __shared__ unsigned char smem_raw[];
   C* twl = reinterpret_cast<C*>(smem_raw);
   C* ex = twl + P;  // [kc][P2][S1]
-  const int y = blockIdx.x;
-  const int c = blockIdx.y;
-  const int kz0 = blockIdx.z * kc;
+  const XBlk bk = xline_block();
+  const int y = bk.y;
+  const int c = bk.f;
+  const int kz0 = bk.ch * kc;
   const int nl = min(kc, nzm - kz0);
   for (int t = threadIdx.x; t < P; t += blockDim.x) twl[t] = tw[t];
   __syncthreads();
@@ -163,10 +179,24 @@ hipError_t launch_fft_x_inv_lds(sp_plan* p, const void* in, void* out, int nfiel
                                 bool fp32);
 hipError_t launch_fft_x_fwd_lds(sp_plan* p, const void* in, void* out, int nfields, bool fp32);
 
-// z-modes per block: halve until the grid has at least 512 blocks
-static int xline_chunk(const Dims& d, int nfields) {
-  int kc = d.nzm;
-  while (kc > 4 && (long)d.ny * nfields * ((d.nzm + kc - 1) / kc) < 512) kc = (kc + 1) / 2;
+// z-modes per block: the fewest chunks that give the grid at least 512 blocks
+// (and at least 4 modes per chunk) and keep the exchange buffer within 64 KiB
+// of LDS, split evenly; a chunk is widened to a whole number of 128-byte cache
+// lines (8 FP64 or 16 FP32 complex values) when that keeps the same even split,
+// so that chunks of the x-physical rows [x][kz] start on line boundaries
+static int xline_chunk(const Dims& d, int nfields, bool fp32, int P1, int P2) {
+  const int lw = fp32 ? 16 : 8;
+  const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
+  const long per = (long)d.ny * nfields;
+  const int nmax = d.nzm / 4 > 1 ? d.nzm / 4 : 1;
+  auto lds = [&](int kc) { return ((size_t)d.px + (size_t)kc * P2 * (P1 + 1)) * el; };
+  int nch = 1;
+  while (nch < d.nzm &&
+         ((nch < nmax && per * nch < 512) || lds((d.nzm + nch - 1) / nch) > 65536))
+    ++nch;
+  int kc = (d.nzm + nch - 1) / nch;
+  const int ka = (kc + lw - 1) / lw * lw;
+  if (d.nzm % ka == 0 && d.nzm / ka == nch) kc = ka;
   return kc;
 }
 
@@ -176,7 +206,7 @@ hipError_t launch_fft_x_inv_gen(sp_plan* p, const void* in, void* out, int nfiel
   const int P1 = reg_fft_split(d.px);
   if (P1 == 0) return launch_fft_x_inv_lds(p, in, out, nfields, plain, fp32);
   const int P2 = d.px / P1;
-  const int kc = xline_chunk(d, nfields);
+  const int kc = xline_chunk(d, nfields, fp32, P1, P2);
   const dim3 grid(d.ny, nfields, (d.nzm + kc - 1) / kc);
   const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
   const size_t sh = ((size_t)d.px + (size_t)kc * P2 * (P1 + 1)) * el;
@@ -201,7 +231,7 @@ hipError_t launch_fft_x_fwd_gen(sp_plan* p, const void* in, void* out, int nfiel
   const int P1 = reg_fft_split(d.px);
   if (P1 == 0) return launch_fft_x_fwd_lds(p, in, out, nfields, fp32);
   const int P2 = d.px / P1;
-  const int kc = xline_chunk(d, nfields);
+  const int kc = xline_chunk(d, nfields, fp32, P1, P2);
   const dim3 grid(d.ny, nfields, (d.nzm + kc - 1) / kc);
   const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
   const size_t sh = ((size_t)d.px + (size_t)kc * P2 * (P1 + 1)) * el;

@@ -80,6 +80,20 @@ struct SynthSpec {
   YMat<R> mat[3][2];
 };
 
+// Logical (x, y, z) block of a contraction grid: the hardware index is
+// reordered by xcd_order with the y index (output row tile) fastest, so the
+// blocks that read the same columns for different row tiles share an L2.
+struct Blk3 {
+  int x, y, z;
+};
+__device__ inline Blk3 ycontract_block() {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int l = xcd_order(b, gx * gy * (int)gridDim.z);
+  const int rest = l / gy;
+  return Blk3{rest % gx, l % gy, rest / gx};
+}
+
 template <typename R, int KS>
 __global__ void __launch_bounds__(256)
     k_ysynth_mfma(const double2* __restrict__ u, SynthSpec<R> spec, R* __restrict__ out, int nx,
@@ -88,8 +102,9 @@ __global__ void __launch_bounds__(256)
   const int lane = threadIdx.x & 63;
   const int kq = lane >> 4;
   const int nq = nzm * nx;
-  const int g = blockIdx.z;
-  const int q0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 8;
+  const Blk3 bk = ycontract_block();
+  const int g = bk.z;
+  const int q0 = (bk.x * 4 + (threadIdx.x >> 6)) * 8;
   const int q = q0 + ((lane & 15) >> 1);
   const bool qv = q < nq;
   const size_t fstride = (size_t)ny * nq * 2;
@@ -114,7 +129,7 @@ __global__ void __launch_bounds__(256)
     }
   }
   const int nt = ny >> 4;
-  const int t = blockIdx.y;
+  const int t = bk.y;
   for (int mi = 0; mi < spec.nmat[g]; ++mi) {
     const YMat<R> M = spec.mat[g][mi];
     R* o = out + (size_t)spec.field[g][mi] * fstride + 2 * (size_t)q0 + (lane & 15);
@@ -201,19 +216,20 @@ struct AdjSynthLoad {
 // out[c][mx][kz][n] = sum_t sum_j M_t(n, j) Y_t[j][(kz, mx)] + xa * x[c][mx][kz][n]
 // for kz < nz/2 (x may be NULL); the z Nyquist rows kz = nz/2 get xa * x (or
 // zero) from the blocks past the first nqb column blocks. nterm[c] terms for
-// component c = blockIdx.z.
+// component c = the logical z block index.
 template <typename R, int KS, class Load>
 __global__ void __launch_bounds__(256)
     k_ycoef_mfma(Load load, int nterm0, int nterm1, int nterm2, YMat<R> M0, YMat<R> M1,
                  const double2* __restrict__ x, double xa, double2* __restrict__ out, int nx,
                  int ny, int nzh, int nzm, int nqb) {
   using MF = Mfma<R>;
-  if ((int)blockIdx.x >= nqb) {  // block-uniform
-    const int e = ((int)blockIdx.x - nqb) * 256 + (int)threadIdx.x;
-    if (blockIdx.y == 0 && e < nx * ny) {
+  const Blk3 bk = ycontract_block();
+  if (bk.x >= nqb) {  // block-uniform
+    const int e = (bk.x - nqb) * 256 + (int)threadIdx.x;
+    if (bk.y == 0 && e < nx * ny) {
       const int mx = e / ny;
       const int n = e - mx * ny;
-      const size_t o = (((size_t)blockIdx.z * nx + mx) * nzh + (nzh - 1)) * ny + n;
+      const size_t o = (((size_t)bk.z * nx + mx) * nzh + (nzh - 1)) * ny + n;
       double2 v = make_double2(0.0, 0.0);
       if (x != nullptr) v = make_double2(xa * x[o].x, xa * x[o].y);
       out[o] = v;
@@ -223,9 +239,9 @@ __global__ void __launch_bounds__(256)
   const int lane = threadIdx.x & 63;
   const int kq = lane >> 4;
   const int nq = nzm * nx;
-  const int c = blockIdx.z;
+  const int c = bk.z;
   const int nterm = (c == 0) ? nterm0 : (c == 1 ? nterm1 : nterm2);
-  const int q0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 8;
+  const int q0 = (bk.x * 4 + (threadIdx.x >> 6)) * 8;
   // A fragments: this lane's column (mode qa, part ra) at j = 4 s + kq; indexes
   // clamped into range, values past the range zeroed after the load
   const int qa = q0 + ((lane & 15) >> 1);
@@ -235,7 +251,7 @@ __global__ void __launch_bounds__(256)
   const int kza = qcl / nx;
   const int mxa = qcl - kza * nx;
   const int nt = ny >> 4;
-  const int t = blockIdx.y;
+  const int t = bk.y;
   const bool tile = t < nt;
   const bool tail = (t == (int)gridDim.y - 1) && (16 * nt < ny);
   R a[2][KS];
