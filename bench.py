@@ -36,7 +36,7 @@ WORKLOADS = {
     "couette_32x33x32_re400_dt100": dict(nx=32, ny=33, nz=32, re=400.0, dt=100.0,
                                           lx=2 * math.pi / 1.14, lz=2 * math.pi / 2.5),
     "couette_96x97x96_re2000_dt100": dict(nx=96, ny=97, nz=96, re=2000.0, dt=100.0,
-                                           lx=4 * math.pi, lz=2 * math.pi),
+                                           lx=4 * math.pi, lz=2 * math.pi, input="streak_roll"),
 }
 DEFAULT = "couette_48x65x48_re1000_dt100"
 HBM_PEAK_GBS = 8000.0
@@ -159,6 +159,60 @@ def cpu_baseline(w, u_np, budget_s=12.0):
                        f"{len(valid)} modes), extrapolated to all modes; 1 thread")}
 
 
+def dt_sweep(seeds=range(10), dts=(1.0, 10.0, 100.0), max_krylov=400,
+             first_rtols=(1e-2, 1e-3, 1e-6), solve_rtol=1e-4, max_newton=30):
+    """Krylov counts against the time step at 32x33x32, Re = 400, from the
+    perturbation family (energy 1e-2, seeds 0-9): for each dt and seed, the
+    GMRES iterations of the first Newton step to each relative tolerance in
+    `first_rtols` (at most `max_krylov`, with the relative residual reached),
+    then the trust-region (hookstep) Newton solve to ||r|| < 1e-10 with GMRES
+    to `solve_rtol` (converged flag, Newton steps, total Krylov iterations,
+    Phi/JVP evaluations, seconds, distance of the root from laminar flow)."""
+    import torch
+    from paper_1804_05087_amd import Plan, synth
+    w = WORKLOADS["couette_32x33x32_re400_dt100"]
+    dev = torch.device("cuda", 0)
+    dims = (w["nx"], w["ny"], w["nz"])
+    lam = torch.from_numpy(synth.laminar_field(*dims)).to(dev)
+    out = {}
+    for dt in dts:
+        P = Plan(*dims, w["lx"], w["lz"], w["re"], dt, device=dev)
+        rows = []
+        for seed in seeds:
+            u0 = torch.from_numpy(synth.perturbation_field(*dims, w["lx"], w["lz"],
+                                                           seed=seed)).to(dev)
+            row = {"seed": seed}
+            for rt in first_rtols:
+                u = u0.clone()
+                first = P.newton_gmres(u, max_newton=1, max_krylov=max_krylov, gmres_rtol=rt,
+                                       newton_tol=0.0)
+                row[f"K_first_{rt:g}"] = first["krylov"][0]
+                row[f"relres_first_{rt:g}"] = float(f"{first['gmres_relres'][0]:.2e}")
+            u = u0.clone()
+            full = P.newton_hookstep(u, max_newton=max_newton, max_krylov=max_krylov,
+                                     gmres_rtol=solve_rtol, newton_tol=1e-10)
+            row.update({"converged": full["converged"], "newton_iters": full["newton_iters"],
+                        "K_total": full["total_krylov"], "actions": full["total_actions"],
+                        "final_res": float(f"{full['res_norm'][-1]:.3e}"),
+                        "seconds": round(full["seconds"], 3),
+                        "dist_to_laminar_L2": float(f"{P.norm((u - lam).contiguous()):.3e}")})
+            log("dt", dt, row)
+            rows.append(row)
+        summary = {}
+        for rt in first_rtols:
+            ks = [r[f"K_first_{rt:g}"] for r in rows]
+            summary[f"K_first_{rt:g}"] = {"mean": sum(ks) / len(ks), "min": min(ks),
+                                          "max": max(ks)}
+        conv = [r for r in rows if r["converged"]]
+        summary["converged"] = len(conv)
+        if conv:
+            summary["K_total_mean_converged"] = sum(r["K_total"] for r in conv) / len(conv)
+        out[str(dt)] = {"summary": summary, "runs": rows}
+    return {"metric": "krylov_iterations_vs_dt", "workload": "couette_32x33x32_re400",
+            "max_krylov": max_krylov, "solve_gmres_rtol": solve_rtol, "energy": 1e-2,
+            "newton": "hookstep", "sweep": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,12 +227,18 @@ def main():
     ap.add_argument("--newton-energy", type=float, default=1e-6,
                     help="perturbation energy of the Newton start (E = 1e-2 does not "
                          "converge without a hookstep)")
+    ap.add_argument("--dt-sweep", action="store_true",
+                    help="instead of the benchmark line, print the Krylov-count sweep over "
+                         "dt in {1, 10, 100} and seeds 0-9 at 32x33x32, Re 400")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
               "(this build runs on a single MI355X; see DESIGN.md for how it would shard)",
               file=sys.stderr)
         sys.exit(2)
+    if args.dt_sweep:
+        print(json.dumps(dt_sweep()), flush=True)
+        return
     import numpy as np
     import torch
     from paper_1804_05087_amd import (SP_FP64, SP_MIXED, SP_OP_RESIDUAL, SP_STAGE_SOLVE,
@@ -191,7 +251,10 @@ def main():
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    u_np = synth.perturbation_field(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], seed=0)
+    if w.get("input") == "streak_roll":
+        u_np = synth.streak_roll_field(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], seed=0)
+    else:
+        u_np = synth.perturbation_field(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], seed=0)
     u = torch.from_numpy(u_np).to(dev)
     du_np = synth.random_admissible(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], seed=1)
     du = torch.from_numpy(du_np).to(dev)

@@ -177,6 +177,50 @@ typedef struct {
 sp_status sp_newton_gmres(sp_plan* plan, double* u_inout, const sp_newton_opts* opts,
                           sp_newton_report* report);
 
+typedef struct {
+  int32_t max_trials;  /* candidate steps per Newton iteration (>= 1)            */
+  double delta_init;   /* first trust radius; <= 0: length of the first Newton step */
+  double delta_min;    /* give up when a rejection takes the radius below (> 0)  */
+  double delta_max;    /* upper limit of the radius (>= delta_min)                */
+} sp_hook_opts;
+
+typedef struct {
+  int32_t trials[64];    /* candidates evaluated in each accepted Newton step    */
+  double delta[64];      /* trust radius the accepted step was computed with      */
+  double mu[64];         /* its Lagrange multiplier (0: the unconstrained step)   */
+  double step_norm[64];  /* its length ||y|| in the packed Euclidean norm          */
+  double rho[64];        /* actual / predicted decrease of ||r||^2                 */
+} sp_hook_report;
+
+/* Newton-GMRES with the hookstep (Sec. 3.1: the step is kept inside a trusted
+ * region of validity of the linearisation, after Viswanath 2007). Each Newton
+ * iteration runs GMRES as sp_newton_gmres does, then takes du = Q y with y
+ * minimising the GMRES model ||beta e_1 - Hbar y|| subject to ||y|| <= delta
+ * (Q the orthonormal Krylov basis, so ||du|| = ||y|| in the packed Euclidean
+ * norm). The candidate U - du is evaluated; with rho the ratio of the actual
+ * to the predicted decrease of ||r||^2 (packed Euclidean), a candidate with
+ * rho < 0.01 is rejected and delta set to half of min(delta, ||y||); an
+ * accepted step halves delta (to ||y|| / 2) when rho < 0.25 and doubles it (up
+ * to delta_max) when rho > 0.75 and the constraint was active. A rejected
+ * candidate costs one Phi evaluation and no new Krylov work. Stops with
+ * SP_ERR_NOT_CONVERGED when max_trials candidates in a row are rejected or the
+ * radius falls below delta_min. Arguments as for sp_newton_gmres; hook_report
+ * may be NULL. The residual of an accepted candidate is reused by the next
+ * iteration, so total_actions counts every Phi and JVP evaluation once. */
+sp_status sp_newton_hookstep(sp_plan* plan, double* u_inout, const sp_newton_opts* opts,
+                             const sp_hook_opts* hook, sp_newton_report* report,
+                             sp_hook_report* hook_report);
+
+/* The hookstep subproblem alone, on the host (no plan, no device work): R is
+ * the k x k upper-triangular Givens-rotated GMRES matrix (column-major, leading
+ * dimension ld >= k, nonzero diagonal), g the k+1 rotated right-hand side.
+ * Writes y[k] minimising ||g[0..k-1] - R y||^2 + g[k]^2 over ||y|| <= delta
+ * (delta > 0), its Lagrange multiplier *mu (0 when the unconstrained minimiser
+ * fits) and the model residual norm *model_res. SP_ERR_INVALID on bad
+ * arguments. This is the computation sp_newton_hookstep performs per trial. */
+sp_status sp_hook_step(const double* R, int32_t ld, const double* g, int32_t k, double delta,
+                       double* y, double* mu, double* model_res);
+
 /* Per-kernel timing (tracing aid): when on != 0, every kernel the plan launches
  * is bracketed by HIP events on the plan's stream, which adds a small gap
  * between launches; leave it off for throughput measurements. */

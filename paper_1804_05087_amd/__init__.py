@@ -15,7 +15,7 @@ from ._lib import (SP_FP64, SP_MIXED, SP_OP_PHI, SP_OP_RESIDUAL, SP_STAGE_SOLVE,
 
 __all__ = ["Plan", "PhiFunction", "SPError", "SP_FP64", "SP_MIXED", "SP_OP_PHI",
            "SP_OP_RESIDUAL", "SP_STAGE_SYNTH", "SP_STAGE_XINV", "SP_STAGE_ZLINE", "SP_STAGE_XFWD",
-           "SP_STAGE_SOLVE", "couette_box"]
+           "SP_STAGE_SOLVE", "couette_box", "hook_step"]
 
 
 def couette_box():
@@ -26,6 +26,26 @@ def couette_box():
 def _torch():
     import torch
     return torch
+
+
+def hook_step(R, g, delta: float):
+    """The hookstep subproblem of sp_newton_hookstep on the host (numpy
+    arrays): R k x k upper triangular, g the k+1 rotated right-hand side.
+    Returns (y, mu, model residual norm)."""
+    import numpy as np
+    lib = _lib.load()
+    Rf = np.asfortranarray(np.asarray(R, dtype=np.float64))
+    gv = np.ascontiguousarray(np.asarray(g, dtype=np.float64))
+    k = Rf.shape[1]
+    if Rf.shape != (k, k) or gv.shape != (k + 1,):
+        raise ValueError("R must be k x k and g of length k + 1")
+    y = np.zeros(k)
+    mu, res = C.c_double(), C.c_double()
+    st = lib.sp_hook_step(Rf.ctypes.data, k, gv.ctypes.data, k, float(delta), y.ctypes.data,
+                          C.byref(mu), C.byref(res))
+    if st != 0:
+        raise SPError(st, lib.sp_status_string(st).decode())
+    return y, mu.value, res.value
 
 
 class Plan:
@@ -216,6 +236,45 @@ class Plan:
             "krylov": list(rep.krylov[:n]),
             "gmres_relres": list(rep.gmres_relres[:n]),
         }
+
+
+    def newton_hookstep(self, u, max_newton: int = 5, max_krylov: int = 40,
+                        gmres_rtol: float = 1e-4, newton_tol: float = 1e-10,
+                        jvp_mode: int = 0, fd_eps: float = 1e-7, max_trials: int = 10,
+                        delta_init: float = 0.0, delta_min: float = 1e-12,
+                        delta_max: float = 1e300):
+        """Trust-region Newton-GMRES (hookstep) in place on u; returns the
+        report of newton_gmres plus the per-step trials, delta, mu, step_norm
+        and rho of the accepted steps."""
+        opts = _lib.sp_newton_opts(max_newton, max_krylov, gmres_rtol, newton_tol, jvp_mode,
+                                   fd_eps)
+        hook = _lib.sp_hook_opts(max_trials, delta_init, delta_min, delta_max)
+        rep = _lib.sp_newton_report()
+        hrep = _lib.sp_hook_report()
+        st = self.lib.sp_newton_hookstep(self.h, self._field(u, "u"), C.byref(opts),
+                                         C.byref(hook), C.byref(rep), C.byref(hrep))
+        if st not in (0, _lib.SP_ERR_NOT_CONVERGED):
+            self._check(st)
+        n = rep.newton_iters
+        na = sum(1 for t in hrep.trials[:n] if t > 0)
+        out = {
+            "converged": bool(rep.converged),
+            "newton_iters": n,
+            "total_krylov": rep.total_krylov,
+            "total_actions": rep.total_actions,
+            "seconds": rep.seconds,
+            "res_norm": list(rep.res_norm[: n + 1]),
+            "krylov": list(rep.krylov[:n]),
+            "gmres_relres": list(rep.gmres_relres[:n]),
+            "trials": list(hrep.trials[:na]),
+            "delta": list(hrep.delta[:na]),
+            "mu": list(hrep.mu[:na]),
+            "step_norm": list(hrep.step_norm[:na]),
+            "rho": list(hrep.rho[:na]),
+        }
+        if st == _lib.SP_ERR_NOT_CONVERGED:
+            out["message"] = self.lib.sp_last_error(self.h).decode()
+        return out
 
 
 def _make_phi_function():

@@ -49,6 +49,20 @@ class sp_newton_report(C.Structure):
     ]
 
 
+class sp_hook_opts(C.Structure):
+    _fields_ = [
+        ("max_trials", C.c_int32), ("delta_init", C.c_double),
+        ("delta_min", C.c_double), ("delta_max", C.c_double),
+    ]
+
+
+class sp_hook_report(C.Structure):
+    _fields_ = [
+        ("trials", C.c_int32 * 64), ("delta", C.c_double * 64), ("mu", C.c_double * 64),
+        ("step_norm", C.c_double * 64), ("rho", C.c_double * 64),
+    ]
+
+
 # name -> (restype, argtypes); every exported entry point of include/sp.h
 SIGNATURES = {
     "sp_plan_create": (C.c_int, [C.POINTER(sp_params), C.c_void_p, C.POINTER(C.c_void_p)]),
@@ -72,6 +86,11 @@ SIGNATURES = {
     "sp_unpack": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "sp_newton_gmres": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(sp_newton_opts),
                                   C.POINTER(sp_newton_report)]),
+    "sp_newton_hookstep": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(sp_newton_opts),
+                                     C.POINTER(sp_hook_opts), C.POINTER(sp_newton_report),
+                                     C.POINTER(sp_hook_report)]),
+    "sp_hook_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_double,
+                               C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "sp_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "sp_time_stage": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                 C.POINTER(C.c_double)]),

@@ -121,10 +121,9 @@ sp_status dot_host(sp_plan* p, const double2* a, const double2* b, double* parti
 
 }  // namespace
 
-extern "C" sp_status sp_newton_gmres(sp_plan* p, double* u_inout, const sp_newton_opts* o,
-                                     sp_newton_report* rep) {
-  if (!p) return SP_ERR_INVALID;
-  if (!u_inout || !o || !rep) return set_error(p, SP_ERR_INVALID, "null argument");
+namespace {
+
+sp_status check_newton_opts(sp_plan* p, const sp_newton_opts* o) {
   if (o->max_newton < 0 || o->max_newton > 64)
     return set_error(p, SP_ERR_INVALID, "max_newton must be in [0, 64]");
   if (o->max_krylov < 1) return set_error(p, SP_ERR_INVALID, "max_krylov must be >= 1");
@@ -132,77 +131,74 @@ extern "C" sp_status sp_newton_gmres(sp_plan* p, double* u_inout, const sp_newto
     return set_error(p, SP_ERR_INVALID, "tolerances must be >= 0");
   if (o->jvp_mode != 0 && o->jvp_mode != 1) return set_error(p, SP_ERR_INVALID, "bad jvp_mode");
   if (o->jvp_mode == 1 && !(o->fd_eps > 0)) return set_error(p, SP_ERR_INVALID, "fd_eps must be > 0");
-  const int K = o->max_krylov;
+  return SP_OK;
+}
+
+sp_status ensure_workspace(sp_plan* p, int K) {
   const size_t need = ws_bytes_for(p, K);
-  if (!p->ws || p->ws_bytes < need) {
-    if (p->ws && !p->ws_owned)
-      return set_error(p, SP_ERR_INVALID, "supplied workspace is smaller than required");
-    if (p->ws) (void)hipFree(p->ws);
+  if (p->ws && p->ws_bytes >= need) return SP_OK;
+  if (p->ws && !p->ws_owned)
+    return set_error(p, SP_ERR_INVALID, "supplied workspace is smaller than required");
+  if (p->ws) (void)hipFree(p->ws);
+  p->ws = nullptr;
+  hipError_t e = hipMalloc(&p->ws, need);
+  if (e != hipSuccess) {
     p->ws = nullptr;
-    hipError_t e = hipMalloc(&p->ws, need);
-    if (e != hipSuccess) {
-      p->ws = nullptr;
-      p->ws_bytes = 0;
-      return set_error(p, SP_ERR_NOMEM, "cannot allocate the Krylov workspace");
-    }
-    p->ws_bytes = need;
-    p->ws_owned = true;
+    p->ws_bytes = 0;
+    return set_error(p, SP_ERR_NOMEM, "cannot allocate the Krylov workspace");
   }
-  std::memset(rep, 0, sizeof(*rep));
-  Workspace W = carve(p, K);
-  const size_t canon = canon_bytes(p);
-  double2* U = (double2*)u_inout;
-  double2* r = p->t3;
+  p->ws_bytes = need;
+  p->ws_owned = true;
+  return SP_OK;
+}
 
+// Unrestarted GMRES on J_r du = r from du = 0 with delayed CGS2 Arnoldi. After
+// solve(): the first kd basis slots of W.V hold q_0..q_{kd-1} (orthonormal in
+// the packed product), R the Givens-rotated Hessenberg matrix (upper
+// triangular kd x kd, column-major with leading dimension K+1), g the rotated
+// right-hand side (g[kd] the least-squares residual), beta = ||r||.
+struct Gmres {
+  sp_plan* p;
+  const sp_newton_opts* o;
+  int K;
+  Workspace W;
+  size_t canon, nc;
   double* hbuf = nullptr;  // pinned: dots[2(K+2)], a|c[2(K+2)]
-  SP_TRY_HIP(hipHostMalloc((void**)&hbuf, 4 * (K + 2) * sizeof(double)), "hipHostMalloc");
-  struct Free {
-    double* b;
-    ~Free() { (void)hipHostFree(b); }
-  } guard{hbuf};
-  double* hdots = hbuf;             // [2 v + r]: r = 0 against u_j, r = 1 against w
-  double* hac = hbuf + 2 * (K + 2);  // a[0..K+1] then c[0..K+1]
-  double* d_dots = W.h1;             // 2 (K + 2) doubles
-  double* d_ac = W.h2;               // 2 (K + 2) doubles
-  const size_t nc = canon / sizeof(double2);
+  std::vector<double> H, R, cs, sn, g, hprev, a, b, Ha, cvec;
+  int kd = 0;
+  double beta = 0.0, relres = 1.0;
 
-  // H (unrotated, column-major, (K+1) x K) for the Arnoldi relation; R the
-  // Givens-rotated copy for the least squares.
-  std::vector<double> H((size_t)(K + 1) * K), R((size_t)(K + 1) * K), cs(K), sn(K), gv(K + 1),
-      yv(K), hprev(K + 1), a(K + 1), b(K + 1), Ha(K + 1), cvec(K + 1);
-  auto Hat = [&](int i, int k) -> double& { return H[(size_t)k * (K + 1) + i]; };
-  auto Rat = [&](int i, int k) -> double& { return R[(size_t)k * (K + 1) + i]; };
-  const auto t0 = std::chrono::steady_clock::now();
-  sp_status result = SP_ERR_NOT_CONVERGED;
-  for (int it = 0; it <= o->max_newton; ++it) {
-    double rn = 0.0;
-    SP_TRY(residual_into(p, U, r));
-    rep->total_actions += 1;
-    SP_TRY(host_norm_of(p, r, &rn));
-    rep->res_norm[it] = rn;
-    if (rn < o->newton_tol) {
-      result = SP_OK;
-      rep->converged = 1;
-      break;
-    }
-    if (it == o->max_newton) break;
-    double unorm = 0.0;
-    if (o->jvp_mode == 0) {
-      SP_TRY(linearize(p, U));
-    } else {
-      double u2 = 0.0;
-      SP_TRY(dot_host(p, U, U, W.partial, W.h1, &u2));
-      unorm = std::sqrt(u2);
-    }
+  Gmres(sp_plan* p_, const sp_newton_opts* o_)
+      : p(p_), o(o_), K(o_->max_krylov), W(carve(p_, o_->max_krylov)),
+        canon(canon_bytes(p_)), nc(canon_bytes(p_) / sizeof(double2)),
+        H((size_t)(K + 1) * K), R((size_t)(K + 1) * K), cs(K), sn(K), g(K + 1), hprev(K + 1),
+        a(K + 1), b(K + 1), Ha(K + 1), cvec(K + 1) {}
+  ~Gmres() {
+    if (hbuf) (void)hipHostFree(hbuf);
+  }
+  sp_status init() {
+    SP_TRY_HIP(hipHostMalloc((void**)&hbuf, 4 * (K + 2) * sizeof(double)), "hipHostMalloc");
+    return SP_OK;
+  }
+  double& Hat(int i, int k) { return H[(size_t)k * (K + 1) + i]; }
+  double& Rat(int i, int k) { return R[(size_t)k * (K + 1) + i]; }
+
+  // U the linearisation point (its base state must be cached for the exact
+  // JVP), r = r(U); unorm = ||U|| for the finite-difference mode.
+  sp_status solve(const double2* U, const double2* r, double unorm, int* actions) {
+    double* hdots = hbuf;              // [2 v + r]: r = 0 against u_j, r = 1 against w
+    double* hac = hbuf + 2 * (K + 2);  // a[0..K+1] then c[0..K+1]
+    double* d_dots = W.h1;             // 2 (K + 2) doubles
+    double* d_ac = W.h2;               // 2 (K + 2) doubles
     // u_0 = r (unnormalised; gamma_0 = ||r|| comes out of the first reduction)
     SP_TRY_HIP(hipMemcpyAsync(W.V, r, canon, hipMemcpyDeviceToDevice, p->stream), "copy r");
     SP_TRY_HIP(launch_hermitian(p, W.V), "hermitian");
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(R.begin(), R.end(), 0.0);
-    std::fill(gv.begin(), gv.end(), 0.0);
-    double beta = 0.0;
-    int kd = 0;
-    double relres = 1.0;
+    std::fill(g.begin(), g.end(), 0.0);
+    beta = 0.0;
+    kd = 0;
+    relres = 1.0;
     for (int j = 0; j <= K; ++j) {
       double2* uj = W.V + (size_t)j * nc;
       const bool last = (j == K);  // only completes column K-1: no new direction
@@ -219,7 +215,7 @@ extern "C" sp_status sp_newton_gmres(sp_plan* p, double* u_inout, const sp_newto
           SP_TRY(residual_into(p, W.s, W.w));
           SP_TRY_HIP(launch_axpby(p, W.w, 1.0 / eps, r, -1.0 / eps, W.w, nc), "axpby");
         }
-        rep->total_actions += 1;
+        *actions += 1;
         SP_TRY_HIP(launch_hermitian(p, W.w), "hermitian");
       }
       // dots of q_0..q_{j-1} and u_j with u_j and with w
@@ -244,7 +240,7 @@ extern "C" sp_status sp_newton_gmres(sp_plan* p, double* u_inout, const sp_newto
       if (j == 0) {
         beta = gamma;
         if (!(beta > 0)) return set_error(p, SP_ERR_NONFINITE, "zero or non-finite residual");
-        gv[0] = beta;
+        g[0] = beta;
       } else {
         // complete column j-1, rotate it, test convergence of the j-dimensional space
         const int k = j - 1;
@@ -261,11 +257,11 @@ extern "C" sp_status sp_newton_gmres(sp_plan* p, double* u_inout, const sp_newto
         sn[k] = Rat(k + 1, k) / dd;
         Rat(k, k) = dd;
         Rat(k + 1, k) = 0.0;
-        gv[k + 1] = -sn[k] * gv[k];
-        gv[k] = cs[k] * gv[k];
+        g[k + 1] = -sn[k] * g[k];
+        g[k] = cs[k] * g[k];
         kd = j;
-        relres = std::fabs(gv[k + 1]) / beta;
-        stop = std::fabs(gv[k + 1]) <= o->gmres_rtol * beta || !(gamma > 0) || last;
+        relres = std::fabs(g[k + 1]) / beta;
+        stop = std::fabs(g[k + 1]) <= o->gmres_rtol * beta || !(gamma > 0) || last;
       }
       if (stop) break;
       // H a (rows 0..j) from the completed columns 0..j-1
@@ -289,23 +285,301 @@ extern "C" sp_status sp_newton_gmres(sp_plan* p, double* u_inout, const sp_newto
       SP_TRY_HIP(launch_dcgs2_update(p, W.V, j, d_ac, d_ac + (K + 2), ig, W.w, uj + nc),
                  "dcgs2 update");
     }
+    return SP_OK;
+  }
+
+  // the least-squares minimiser: R y = g[0..kd-1]
+  void newton_step(double* y) {
     for (int i = kd - 1; i >= 0; --i) {
-      double s2 = gv[i];
-      for (int j2 = i + 1; j2 < kd; ++j2) s2 -= Rat(i, j2) * yv[j2];
-      yv[i] = s2 / Rat(i, i);
+      double s2 = g[i];
+      for (int j2 = i + 1; j2 < kd; ++j2) s2 -= Rat(i, j2) * y[j2];
+      y[i] = s2 / Rat(i, i);
     }
-    SP_TRY_HIP(hipMemcpyAsync(W.y, yv.data(), kd * sizeof(double), hipMemcpyHostToDevice,
-                              p->stream),
+  }
+
+  // target <- target - Q y (y on the host)
+  sp_status apply(const double* y, double2* target) {
+    SP_TRY_HIP(hipMemcpyAsync(W.y, y, kd * sizeof(double), hipMemcpyHostToDevice, p->stream),
                "upload y");
-    SP_TRY_HIP(launch_multiaxpy(p, W.V, kd, W.y, -1.0, 1.0, U), "update");
+    SP_TRY_HIP(launch_multiaxpy(p, W.V, kd, W.y, -1.0, 1.0, target), "update");
+    return SP_OK;
+  }
+};
+
+double norm2(const double* v, int n) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += v[i] * v[i];
+  return std::sqrt(s);
+}
+
+// The damped least-squares solution y(mu) = argmin ||R y - g||^2 + mu ||y||^2
+// for the k x k upper-triangular R (column-major, leading dimension ld): the
+// rows sqrt(mu) e_i are rotated into R with Givens rotations (no normal
+// equations, so the conditioning stays that of R), giving S upper triangular
+// with S^T S = R^T R + mu I and z = the rotated right-hand side; y = S^{-1} z
+// and q = S^{-T} y (for the Newton correction of mu). S row-major k x k.
+void damped_solve(const double* R, int ld, const double* g, int k, double mu,
+                  std::vector<double>& S, std::vector<double>& e, double* z, double* y,
+                  double* q) {
+  for (int i = 0; i < k; ++i) {
+    for (int j = 0; j < i; ++j) S[(size_t)i * k + j] = 0.0;
+    for (int j = i; j < k; ++j) S[(size_t)i * k + j] = R[(size_t)j * ld + i];
+    z[i] = g[i];
+  }
+  const double sm = std::sqrt(mu);
+  for (int i = 0; i < k; ++i) {
+    std::fill(e.begin() + i, e.begin() + k, 0.0);
+    e[i] = sm;
+    double t = 0.0;  // right-hand side of the extra row
+    for (int j = i; j < k; ++j) {
+      if (e[j] == 0.0) continue;
+      double* Sj = &S[(size_t)j * k];
+      const double r = std::hypot(Sj[j], e[j]);
+      const double c = Sj[j] / r, s = e[j] / r;
+      Sj[j] = r;
+      for (int l = j + 1; l < k; ++l) {
+        const double a = Sj[l], b = e[l];
+        Sj[l] = c * a + s * b;
+        e[l] = -s * a + c * b;
+      }
+      const double zj = z[j];
+      z[j] = c * zj + s * t;
+      t = -s * zj + c * t;
+    }
+  }
+  for (int i = k - 1; i >= 0; --i) {
+    double s2 = z[i];
+    const double* Si = &S[(size_t)i * k];
+    for (int j = i + 1; j < k; ++j) s2 -= Si[j] * y[j];
+    y[i] = s2 / Si[i];
+  }
+  for (int i = 0; i < k; ++i) {
+    double s2 = y[i];
+    for (int j = 0; j < i; ++j) s2 -= S[(size_t)j * k + i] * q[j];
+    q[i] = s2 / S[(size_t)i * k + i];
+  }
+}
+
+// The hookstep: y minimising ||g[0..k-1] - R y|| over ||y|| <= delta, given the
+// unconstrained minimiser yN. mu from Newton's method on 1/||y(mu)|| = 1/delta
+// (Hebden; More & Sorensen), which increases monotonically from mu = 0 when
+// ||yN|| > delta. Returns mu; y holds the step.
+double hook_solve(const double* R, int ld, const double* g, int k, const double* yN,
+                  double delta, double* y) {
+  const double nN = norm2(yN, k);
+  if (nN <= delta) {
+    std::copy(yN, yN + k, y);
+    return 0.0;
+  }
+  std::vector<double> S((size_t)k * k), e(k), z(k), q(k);
+  // mu = 0: S = R, y = yN, q = R^{-T} yN
+  for (int i = 0; i < k; ++i) {
+    double s2 = yN[i];
+    for (int j = 0; j < i; ++j) s2 -= R[(size_t)i * ld + j] * q[j];
+    q[i] = s2 / R[(size_t)i * ld + i];
+  }
+  double mu = 0.0, ny = nN, nq = norm2(q.data(), k);
+  std::copy(yN, yN + k, y);
+  double lo = 0.0, hi = HUGE_VAL;
+  for (int it = 0; it < 100; ++it) {
+    if (std::fabs(ny - delta) <= 1e-13 * delta) break;
+    if (ny > delta) lo = mu; else hi = mu;
+    double mn = mu + (ny / nq) * (ny / nq) * (ny - delta) / delta;
+    if (!(mn > lo && mn < hi)) mn = std::isfinite(hi) ? 0.5 * (lo + hi) : 2.0 * lo + 1e-300;
+    if (mn == mu) break;
+    mu = mn;
+    damped_solve(R, ld, g, k, mu, S, e, z.data(), y, q.data());
+    ny = norm2(y, k);
+    nq = norm2(q.data(), k);
+  }
+  return mu;
+}
+
+// ||g[0..k-1] - R y||^2 + g[k]^2: the GMRES model's squared residual at y
+double model_res2(const double* R, int ld, const double* g, int k, const double* y) {
+  double s = g[k] * g[k];
+  for (int i = 0; i < k; ++i) {
+    double t = g[i];
+    for (int j = i; j < k; ++j) t -= R[(size_t)j * ld + i] * y[j];
+    s += t * t;
+  }
+  return s;
+}
+
+}  // namespace
+
+extern "C" sp_status sp_hook_step(const double* R, int32_t ld, const double* g, int32_t k,
+                                  double delta, double* y, double* mu, double* model_res) {
+  if (!R || !g || !y || !mu || !model_res || k < 1 || ld < k || !(delta > 0))
+    return SP_ERR_INVALID;
+  for (int i = 0; i < k; ++i)
+    if (!(R[(size_t)i * ld + i] != 0.0) || !std::isfinite(R[(size_t)i * ld + i]))
+      return SP_ERR_INVALID;
+  std::vector<double> yN(k);
+  for (int i = k - 1; i >= 0; --i) {
+    double s2 = g[i];
+    for (int j = i + 1; j < k; ++j) s2 -= R[(size_t)j * ld + i] * yN[j];
+    yN[i] = s2 / R[(size_t)i * ld + i];
+  }
+  *mu = hook_solve(R, ld, g, k, yN.data(), delta, y);
+  *model_res = std::sqrt(model_res2(R, ld, g, k, y));
+  return SP_OK;
+}
+
+extern "C" sp_status sp_newton_gmres(sp_plan* p, double* u_inout, const sp_newton_opts* o,
+                                     sp_newton_report* rep) {
+  if (!p) return SP_ERR_INVALID;
+  if (!u_inout || !o || !rep) return set_error(p, SP_ERR_INVALID, "null argument");
+  SP_TRY(check_newton_opts(p, o));
+  SP_TRY(ensure_workspace(p, o->max_krylov));
+  std::memset(rep, 0, sizeof(*rep));
+  Gmres G(p, o);
+  SP_TRY(G.init());
+  double2* U = (double2*)u_inout;
+  double2* r = p->t3;
+  std::vector<double> yv(o->max_krylov);
+  const auto t0 = std::chrono::steady_clock::now();
+  sp_status result = SP_ERR_NOT_CONVERGED;
+  for (int it = 0; it <= o->max_newton; ++it) {
+    double rn = 0.0;
+    SP_TRY(residual_into(p, U, r));
+    rep->total_actions += 1;
+    SP_TRY(host_norm_of(p, r, &rn));
+    rep->res_norm[it] = rn;
+    if (rn < o->newton_tol) {
+      result = SP_OK;
+      rep->converged = 1;
+      break;
+    }
+    if (it == o->max_newton) break;
+    double unorm = 0.0;
+    if (o->jvp_mode == 0) {
+      SP_TRY(linearize(p, U));
+    } else {
+      double u2 = 0.0;
+      SP_TRY(dot_host(p, U, U, G.W.partial, G.W.h1, &u2));
+      unorm = std::sqrt(u2);
+    }
+    int actions = 0;
+    SP_TRY(G.solve(U, r, unorm, &actions));
+    rep->total_actions += actions;
+    G.newton_step(yv.data());
+    SP_TRY(G.apply(yv.data(), U));
     SP_TRY_HIP(hipStreamSynchronize(p->stream), "sync");
-    rep->krylov[it] = kd;
-    rep->gmres_relres[it] = relres;
-    rep->total_krylov += kd;
+    rep->krylov[it] = G.kd;
+    rep->gmres_relres[it] = G.relres;
+    rep->total_krylov += G.kd;
     rep->newton_iters = it + 1;
   }
   rep->seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (result != SP_OK) set_error(p, SP_ERR_NOT_CONVERGED, "Newton did not reach newton_tol");
+  return result;
+}
+
+extern "C" sp_status sp_newton_hookstep(sp_plan* p, double* u_inout, const sp_newton_opts* o,
+                                        const sp_hook_opts* h, sp_newton_report* rep,
+                                        sp_hook_report* hrep) {
+  if (!p) return SP_ERR_INVALID;
+  if (!u_inout || !o || !h || !rep) return set_error(p, SP_ERR_INVALID, "null argument");
+  SP_TRY(check_newton_opts(p, o));
+  if (h->max_trials < 1) return set_error(p, SP_ERR_INVALID, "max_trials must be >= 1");
+  if (!(h->delta_min > 0) || !(h->delta_max >= h->delta_min) || std::isnan(h->delta_init))
+    return set_error(p, SP_ERR_INVALID, "need 0 < delta_min <= delta_max");
+  SP_TRY(ensure_workspace(p, o->max_krylov));
+  std::memset(rep, 0, sizeof(*rep));
+  if (hrep) std::memset(hrep, 0, sizeof(*hrep));
+  Gmres G(p, o);
+  SP_TRY(G.init());
+  const int K = o->max_krylov;
+  double2* U = (double2*)u_inout;
+  double2* r = p->t3;
+  double2* Uc = G.W.s;  // candidate state
+  double2* rc = G.W.w;  // its residual
+  std::vector<double> yN(K), y(K);
+  double delta = std::min(h->delta_init, h->delta_max);
+  const auto t0 = std::chrono::steady_clock::now();
+  sp_status result = SP_ERR_NOT_CONVERGED;
+  const char* why = "Newton did not reach newton_tol";
+  SP_TRY(residual_into(p, U, r));
+  rep->total_actions += 1;
+  for (int it = 0; it <= o->max_newton; ++it) {
+    double rn = 0.0;
+    SP_TRY(host_norm_of(p, r, &rn));
+    rep->res_norm[it] = rn;
+    if (rn < o->newton_tol) {
+      result = SP_OK;
+      rep->converged = 1;
+      break;
+    }
+    if (it == o->max_newton) break;
+    double unorm = 0.0;
+    if (o->jvp_mode == 0) {
+      SP_TRY(linearize(p, U));
+    } else {
+      double u2 = 0.0;
+      SP_TRY(dot_host(p, U, U, G.W.partial, G.W.h1, &u2));
+      unorm = std::sqrt(u2);
+    }
+    int actions = 0;
+    SP_TRY(G.solve(U, r, unorm, &actions));
+    rep->total_actions += actions;
+    rep->krylov[it] = G.kd;
+    rep->gmres_relres[it] = G.relres;
+    rep->total_krylov += G.kd;
+    rep->newton_iters = it + 1;
+    const int k = G.kd;
+    G.newton_step(yN.data());
+    if (!(delta > 0)) delta = std::min(norm2(yN.data(), k), h->delta_max);
+    const double b2 = G.beta * G.beta;
+    bool accepted = false;
+    for (int trial = 1; trial <= h->max_trials; ++trial) {
+      const double mu = hook_solve(G.R.data(), K + 1, G.g.data(), k, yN.data(), delta, y.data());
+      const double ny = norm2(y.data(), k);
+      const double pred = b2 - model_res2(G.R.data(), K + 1, G.g.data(), k, y.data());
+      SP_TRY_HIP(hipMemcpyAsync(Uc, U, G.canon, hipMemcpyDeviceToDevice, p->stream), "copy U");
+      SP_TRY(G.apply(y.data(), Uc));
+      SP_TRY(residual_into(p, Uc, rc));
+      rep->total_actions += 1;
+      SP_TRY_HIP(launch_hermitian(p, rc), "hermitian");
+      double rc2 = 0.0;
+      SP_TRY(dot_host(p, rc, rc, G.W.partial, G.W.h1, &rc2));
+      const double rho = pred > 0 ? (b2 - rc2) / pred : -HUGE_VAL;
+      if (!(rho >= 0.01)) {  // also rejects a non-finite candidate
+        delta = 0.5 * std::min(delta, ny);
+        if (delta < h->delta_min) {
+          why = "hookstep: trust radius fell below delta_min";
+          break;
+        }
+        continue;
+      }
+      accepted = true;
+      if (hrep) {
+        hrep->trials[it] = trial;
+        hrep->delta[it] = delta;
+        hrep->mu[it] = mu;
+        hrep->step_norm[it] = ny;
+        hrep->rho[it] = rho;
+      }
+      SP_TRY_HIP(hipMemcpyAsync(U, Uc, G.canon, hipMemcpyDeviceToDevice, p->stream), "accept U");
+      SP_TRY_HIP(hipMemcpyAsync(r, rc, G.canon, hipMemcpyDeviceToDevice, p->stream), "accept r");
+      if (rho < 0.25)
+        delta = 0.5 * ny;
+      else if (rho > 0.75 && mu > 0)
+        delta = std::min(2.0 * delta, h->delta_max);
+      break;
+    }
+    if (!accepted) {
+      if (std::strcmp(why, "Newton did not reach newton_tol") == 0)
+        why = "hookstep: max_trials candidates rejected";
+      // report the residual of the unchanged state as the last entry
+      rep->res_norm[it + 1] = rn;
+      break;
+    }
+  }
+  SP_TRY_HIP(hipStreamSynchronize(p->stream), "sync");
+  rep->seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (result != SP_OK) set_error(p, SP_ERR_NOT_CONVERGED, why);
   return result;
 }

@@ -55,3 +55,44 @@ def test_null_arguments(lib):
     assert lib.sp_plan_create(None, None, None) == -1
     assert lib.sp_befe_step(None, None, None) == -1
     assert lib.sp_status_string(-5) == b"not converged"
+
+
+def test_hook_step_host_routine_matches_oracle(lib):
+    """sp_hook_step (the per-trial computation of sp_newton_hookstep: Givens-QR
+    of the damped system and Newton iterations on the multiplier) against the
+    oracle's SVD form of the same constrained least-squares problem."""
+    import numpy as np
+    from oracle import krylov
+    from paper_1804_05087_amd import hook_step
+    rng = np.random.default_rng(11)
+    for k in (1, 3, 10, 40):
+        n = 2 * k + 5
+        A = 3 * np.eye(n) + rng.standard_normal((n, n)) / np.sqrt(n)
+        b = rng.standard_normal(n)
+        _, H, beta, kd, _ = krylov.gmres_basis(lambda v: A @ v, b, k, 0.0)
+        Q, R = np.linalg.qr(H, mode="complete")
+        g = Q.T @ (beta * np.eye(k + 1)[0])
+        yls = np.linalg.lstsq(H, beta * np.eye(k + 1)[0], rcond=None)[0]
+        for f in (3.0, 0.99, 0.5, 0.05, 1e-4):
+            delta = f * np.linalg.norm(yls)
+            y, mu, model = hook_step(R[:k, :k], g, delta)
+            yo, muo, modelo = krylov.hook_step(H, beta, delta)
+            assert np.linalg.norm(y - yo) <= 1e-11 * np.linalg.norm(yo), (k, f)
+            assert abs(mu - muo) <= 1e-9 * max(muo, 1e-12), (k, f, mu, muo)
+            assert abs(model - modelo) <= 1e-12 * beta
+            assert (mu == 0.0) == (f >= 1.0)
+
+
+def test_hook_step_rejects_bad_arguments(lib):
+    import numpy as np
+    R = np.eye(2, order="F")
+    g = np.ones(3)
+    y = np.zeros(2)
+    mu, res = C.c_double(), C.c_double()
+    assert lib.sp_hook_step(R.ctypes.data, 2, g.ctypes.data, 2, 0.0, y.ctypes.data,
+                            C.byref(mu), C.byref(res)) == -1
+    assert lib.sp_hook_step(R.ctypes.data, 1, g.ctypes.data, 2, 1.0, y.ctypes.data,
+                            C.byref(mu), C.byref(res)) == -1
+    Z = np.zeros((2, 2), order="F")
+    assert lib.sp_hook_step(Z.ctypes.data, 2, g.ctypes.data, 2, 1.0, y.ctypes.data,
+                            C.byref(mu), C.byref(res)) == -1

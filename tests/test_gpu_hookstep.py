@@ -1,0 +1,109 @@
+"""GPU parity of the trust-region Newton-GMRES (hookstep, Sec. 3.1) against the
+oracle's newton_hook: same residual history, trials, radii, multipliers, step
+lengths and ratios. The cases are chosen with every ratio at least 0.019 away
+from the thresholds 0.01 / 0.25 / 0.75, so rounding cannot flip a decision."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import BOX, say, to_dev
+from oracle import krylov
+from oracle import pack as opack
+from oracle.befe import Befe
+from oracle.grid import Grid
+from paper_1804_05087_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (8, 9, 8)
+
+
+def _compare(rep, ref, rtol=1e-8):
+    say("gpu", [f"{x:.6e}" for x in rep["res_norm"]], rep["trials"], rep["mu"], rep["rho"])
+    say("ref", [f"{x:.6e}" for x in ref["res_norm"]], ref["trials"], ref["mu"], ref["rho"])
+    assert rep["krylov"] == ref["krylov"]
+    assert rep["trials"] == ref["trials"]
+    assert len(rep["res_norm"]) == len(ref["res_norm"])
+    for a, b in zip(rep["res_norm"], ref["res_norm"]):
+        assert abs(a - b) <= rtol * b
+    for key in ("delta", "step_norm"):
+        for a, b in zip(rep[key], ref[key]):
+            assert abs(a - b) <= rtol * b, key
+    for a, b in zip(rep["mu"], ref["mu"]):
+        assert (a == 0.0) == (b == 0.0)
+        assert abs(a - b) <= 1e-6 * b
+    for a, b in zip(rep["rho"], ref["rho"]):
+        assert abs(a - b) <= 1e-6
+
+
+def test_hookstep_constrained_steps_match_oracle():
+    """Exact JVPs, a small first radius: every step is on the boundary (mu > 0)
+    and the radius doubles after each very successful step."""
+    from paper_1804_05087_amd import Plan
+    say("hookstep constrained 8x9x8")
+    g = Grid(*DIMS, *BOX)
+    B = Befe(g, 400.0, 100.0)
+    P = Plan(*DIMS, *BOX, 400.0, 100.0)
+    u0 = synth.perturbation_field(*DIMS, *BOX, seed=0, energy=1e-2)
+    kw = dict(delta_init=0.01, delta_min=1e-12, delta_max=1e300, max_trials=10)
+    _, ref = krylov.newton_hook_befe(B, u0, 1e-10, 4, 20, 1e-6, **kw)
+    u = to_dev(u0)
+    rep = P.newton_hookstep(u, max_newton=4, max_krylov=20, gmres_rtol=1e-6, newton_tol=1e-10,
+                            **kw)
+    assert all(m > 0 for m in ref["mu"])
+    _compare(rep, ref)
+    assert rep["total_actions"] == ref["actions"]
+
+
+def test_hookstep_rejections_match_oracle():
+    """Finite-difference Jacobian actions with a deliberately large step
+    (fd_eps = 1) make the linear model poor: three accepted steps, then every
+    candidate of the fourth step is rejected and the radius halves four times;
+    the driver stops with 'not converged' and the state of the last accepted
+    step."""
+    from paper_1804_05087_amd import Plan
+    say("hookstep rejections 8x9x8 (FD)")
+    g = Grid(*DIMS, *BOX)
+    B = Befe(g, 400.0, 100.0)
+    P = Plan(*DIMS, *BOX, 400.0, 100.0)
+    u0 = synth.perturbation_field(*DIMS, *BOX, seed=0, energy=1e-1)
+
+    def res(x):
+        return opack.pack(B.residual(opack.unpack(x, g)), g)
+
+    def jvp(x, v):
+        eps = 1.0 * np.linalg.norm(x) / np.linalg.norm(v)
+        return (res(x + eps * v) - res(x)) / eps
+
+    def norm(rx):
+        return B.norm_l2(opack.unpack(rx, g))
+
+    xf, ref = krylov.newton_hook(res, jvp, norm, opack.pack(u0, g), 1e-10, 4, 20, 1e-6,
+                                 max_trials=4)
+    assert ref.get("failed") == "no acceptable step"
+    u = to_dev(u0)
+    rep = P.newton_hookstep(u, max_newton=4, max_krylov=20, gmres_rtol=1e-6, newton_tol=1e-10,
+                            jvp_mode=1, fd_eps=1.0, max_trials=4)
+    assert not rep["converged"]
+    assert "max_trials" in rep["message"]
+    _compare(rep, ref, rtol=1e-7)
+    got = opack.pack(u.cpu().numpy(), g)
+    assert np.linalg.norm(got - xf) <= 1e-7 * np.linalg.norm(xf)
+
+
+def test_hookstep_with_unbounded_radius_is_newton():
+    from paper_1804_05087_amd import Plan
+    say("hookstep == newton 8x9x8")
+    P = Plan(*DIMS, *BOX, 400.0, 100.0)
+    u0 = synth.perturbation_field(*DIMS, *BOX, seed=0, energy=1e-6)
+    a, b = to_dev(u0), to_dev(u0)
+    r1 = P.newton_gmres(a, max_newton=3, max_krylov=30, gmres_rtol=1e-8, newton_tol=1e-12)
+    r2 = P.newton_hookstep(b, max_newton=3, max_krylov=30, gmres_rtol=1e-8, newton_tol=1e-12,
+                           delta_init=1e300)
+    say(r1["res_norm"], r2["res_norm"])
+    assert r1["krylov"] == r2["krylov"]
+    assert all(m == 0.0 for m in r2["mu"]) and all(t == 1 for t in r2["trials"])
+    for x, y in zip(r1["res_norm"], r2["res_norm"]):
+        assert abs(x - y) <= 1e-9 * y + 1e-15
+    assert float((a - b).abs().max()) <= 1e-12
