@@ -213,6 +213,105 @@ def dt_sweep(seeds=range(10), dts=(1.0, 10.0, 100.0), max_krylov=400,
             "newton": "hookstep", "sweep": out}
 
 
+def _timesteps(rep, n):
+    """BEFE steps spent by a Newton solve on an n-step operator: every residual
+    and every Jacobian action costs n (linearised) steps, and each Newton step
+    recomputes its n - 1 step trajectory for the chain rule."""
+    return rep["total_actions"] * n + rep["newton_iters"] * (n - 1)
+
+
+def _history(rep, n):
+    """(cumulative BEFE steps, ||r||) after each Newton iteration."""
+    out, steps = [], n
+    out.append((steps, rep["res_norm"][0]))
+    for i, k in enumerate(rep["krylov"]):
+        trials = rep["trials"][i] if i < len(rep["trials"]) else 0
+        steps += (k + trials) * n + (n - 1)
+        out.append((steps, rep["res_norm"][i + 1]))
+    return [(s_, float(f"{r:.3e}")) for s_, r in out]
+
+
+def _steps_to_reduction(hist, factor):
+    """BEFE steps after which ||r|| first fell below factor * ||r_0||."""
+    r0 = hist[0][1]
+    for steps, r in hist:
+        if r <= factor * r0:
+            return steps
+    return None
+
+
+def gint_compare(seeds=(8, 1, 0, 2, 3), re_find=400.0, re=380.0, t_stokes=100.0,
+                 dt_int=0.03125, t_int=(0.5, 1.0, 2.0), max_krylov=1000, rtol=1e-4,
+                 max_newton=12):
+    """The paper's comparison of the Stokes operator B_T - I (one BEFE step,
+    T = 100) with the time-integration operator (B_dt)^{T/dt} - I (dt =
+    0.03125) in plane Couette flow (Sec. 3.3): a non-laminar equilibrium is
+    found at Re = 400 with the Stokes operator from the perturbation family at
+    32x33x32, Re is lowered to 380, and both operators' hookstep Newton solves
+    start from it; the cost is counted in BEFE time steps."""
+    import torch
+    from paper_1804_05087_amd import Plan, synth
+    w = WORKLOADS["couette_32x33x32_re400_dt100"]
+    dev = torch.device("cuda", 0)
+    dims = (w["nx"], w["ny"], w["nz"])
+    box = (w["lx"], w["lz"])
+    lam = torch.from_numpy(synth.laminar_field(*dims)).to(dev)
+    P = Plan(*dims, *box, re_find, t_stokes, device=dev)
+    start = None
+    for seed in seeds:
+        u = torch.from_numpy(synth.perturbation_field(*dims, *box, seed=seed)).to(dev)
+        rep = P.newton_hookstep(u, max_newton=30, max_krylov=400, gmres_rtol=rtol,
+                                newton_tol=1e-12)
+        dist = P.norm((u - lam).contiguous())
+        log("equilibrium search seed", seed, rep["converged"], rep["res_norm"][-1], dist)
+        if rep["converged"] and dist > 1e-3:
+            start = {"seed": seed, "dist_to_laminar_L2": dist, "res": rep["res_norm"][-1]}
+            break
+    if start is None:
+        return {"metric": "gint_vs_stokes_timesteps", "error": "no non-laminar equilibrium"}
+    u_eq = u.clone()
+    out = {"metric": "gint_vs_stokes_timesteps", "workload": "couette_32x33x32",
+           "re_found": re_find, "re": re, "start": start, "gmres_rtol": rtol,
+           "max_krylov": max_krylov, "newton_tol": 1e-10, "runs": {}}
+    finals = {}
+    PS = Plan(*dims, *box, re, t_stokes, device=dev)
+    uS = u_eq.clone()
+    rep = PS.newton_hookstep(uS, max_newton=max_newton, max_krylov=max_krylov,
+                             gmres_rtol=rtol, newton_tol=1e-10)
+    finals["stokes"] = uS
+    out["runs"][f"stokes_T{t_stokes:g}"] = {
+        "converged": rep["converged"], "newton_iters": rep["newton_iters"],
+        "total_krylov": rep["total_krylov"], "timesteps": _timesteps(rep, 1),
+        "seconds": round(rep["seconds"], 3), "history": _history(rep, 1)}
+    log("stokes", out["runs"][f"stokes_T{t_stokes:g}"])
+    PI = Plan(*dims, *box, re, dt_int, device=dev)
+    for T in t_int:
+        n = int(round(T / dt_int))
+        PI.set_steps(n)
+        uI = u_eq.clone()
+        rep = PI.newton_hookstep(uI, max_newton=max_newton, max_krylov=max_krylov,
+                                 gmres_rtol=rtol, newton_tol=1e-10)
+        key = f"int_T{T:g}"
+        finals[key] = uI
+        out["runs"][key] = {
+            "nsteps": n, "converged": rep["converged"], "newton_iters": rep["newton_iters"],
+            "total_krylov": rep["total_krylov"], "timesteps": _timesteps(rep, n),
+            "seconds": round(rep["seconds"], 3), "history": _history(rep, n),
+            "dist_to_stokes_root_L2": P.norm((uI - uS).contiguous())}
+        log(key, out["runs"][key])
+    for v in out["runs"].values():
+        for f in (1e-4, 1e-6):
+            v[f"steps_to_reduce_{f:g}"] = _steps_to_reduction(v["history"], f)
+    st = out["runs"][f"stokes_T{t_stokes:g}"]
+    for f in (1e-4, 1e-6):
+        key = f"steps_to_reduce_{f:g}"
+        ints = [v[key] for k, v in out["runs"].items() if k.startswith("int") and v[key]]
+        if ints and st[key]:
+            out[f"int_best_over_stokes_{f:g}"] = min(ints) / st[key]
+    out["root_dist_to_laminar_L2"] = P.norm((uS - lam).contiguous())
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +329,10 @@ def main():
     ap.add_argument("--dt-sweep", action="store_true",
                     help="instead of the benchmark line, print the Krylov-count sweep over "
                          "dt in {1, 10, 100} and seeds 0-9 at 32x33x32, Re 400")
+    ap.add_argument("--gint-compare", action="store_true",
+                    help="instead of the benchmark line, print the time-step count of "
+                         "Newton solves with the Stokes operator (T = 100) against the "
+                         "time-integration operator (dt = 0.03125) at 32x33x32, Re 380")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
@@ -238,6 +341,9 @@ def main():
         sys.exit(2)
     if args.dt_sweep:
         print(json.dumps(dt_sweep()), flush=True)
+        return
+    if args.gint_compare:
+        print(json.dumps(gint_compare()), flush=True)
         return
     import numpy as np
     import torch

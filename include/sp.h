@@ -94,6 +94,17 @@ sp_status sp_plan_destroy(sp_plan* plan);
 sp_status sp_plan_set_dt(sp_plan* plan, double dt);
 /* Selects the precision of subsequent Jacobian actions. */
 sp_status sp_plan_set_precision(sp_plan* plan, int32_t precision);
+/* Number n of BEFE steps of the plan's dt composing the residual operator
+ * (Sec. 2, eqs. Gstokes and Gint). n = 1 (the default): r = (Phi_dt(U) - U)/dt,
+ * the Stokes-preconditioned operator with T = dt. n > 1: the time-integration
+ * operator r = (Phi_dt^n(U) - U)/T with T = n dt, BEFE as the integrator. It
+ * governs sp_residual, the SP_OP_RESIDUAL Jacobian actions (sp_jvp, sp_jvp_lin:
+ * the chain rule along the trajectory U_k = Phi_dt^k(U), k < n, which
+ * sp_linearize computes and keeps) and the Newton drivers; SP_OP_PHI actions and
+ * sp_befe_step stay one step, and the SP_OP_RESIDUAL VJP of an n > 1 operator is
+ * not provided (SP_ERR_INVALID). n in [1, 100000]; n > 1 allocates the
+ * trajectory, n canonical fields (SP_ERR_NOMEM if that fails). Synchronises. */
+sp_status sp_plan_set_steps(sp_plan* plan, int32_t nsteps);
 /* shape4 = {3, nx, nz/2+1, ny}; packed_n = 3 ny (nx-1)(nz-1). */
 sp_status sp_state_shape(const sp_plan* plan, int64_t shape4[4], int64_t* packed_n);
 /* Device bytes of a Krylov workspace for sp_newton_gmres with max_krylov. */

@@ -75,6 +75,7 @@ class Plan:
         self.lx, self.lz, self.re, self.dt = lx, lz, re, dt
         self.shape = (3, nx, nz // 2 + 1, ny)
         self.packed_n = 3 * ny * (nx - 1) * (nz - 1)
+        self.nsteps = 1
         self._ws = None
 
     # ------------------------------------------------------------------ helpers
@@ -121,6 +122,12 @@ class Plan:
 
     def set_precision(self, precision: int):
         self._check(self.lib.sp_plan_set_precision(self.h, precision))
+
+    def set_steps(self, nsteps: int):
+        """Residual operator of nsteps BEFE steps of dt: 1 = Stokes operator
+        (T = dt), > 1 = time-integration operator with T = nsteps * dt."""
+        self._check(self.lib.sp_plan_set_steps(self.h, nsteps))
+        self.nsteps = nsteps
 
     # ------------------------------------------------------------------ operators
     def nonlinear(self, u, out=None):

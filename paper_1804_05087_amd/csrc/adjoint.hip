@@ -409,6 +409,12 @@ hipError_t launch_mean_scale(sp_plan* p, double2* a, double s) {
 
 sp_status vjp_lin(sp_plan* p, int op, const double2* w, double2* out) {
   if (!p->base_valid) return set_error(p, SP_ERR_INVALID, "no base state: call sp_linearize");
+  if (op == SP_OP_RESIDUAL && p->nsteps > 1)
+    return set_error(p, SP_ERR_INVALID, "the VJP of the multi-step operator is not provided");
+  {
+    sp_status s = base_at(p, 0);
+    if (s) return s;
+  }
   const bool fp32 = (p->precision == SP_MIXED);
   const Dims& d = p->d;
   const size_t n = (size_t)3 * d.nx * d.nzh * d.ny;

@@ -51,32 +51,100 @@ sp_status befe_into(sp_plan* p, const double2* u, double2* out, bool fp32) {
   return SP_OK;
 }
 
+// r = (Phi_dt^n(u) - u) / (n dt) with n = p->nsteps (n = 1: the Stokes
+// operator); the intermediate states ping-pong between t1 and t2.
 sp_status residual_into(sp_plan* p, const double2* u, double2* r) {
-  sp_status s = befe_into(p, u, p->t1, false);
-  if (s) return s;
-  SP_TRY_HIP(launch_axpby(p, p->t1, p->d.inv_dt, u, -p->d.inv_dt, r, canon_count(p)), "axpby");
+  const int n = p->nsteps;
+  const double2* x = u;
+  for (int k = 0; k < n; ++k) {
+    double2* dst = (k & 1) ? p->t2 : p->t1;
+    sp_status s = befe_into(p, x, dst, false);
+    if (s) return s;
+    x = dst;
+  }
+  const double iT = p->d.inv_dt / n;
+  SP_TRY_HIP(launch_axpby(p, x, iT, u, -iT, r, canon_count(p)), "axpby");
   return SP_OK;
 }
 
-sp_status linearize(sp_plan* p, const double2* u) {
+// the cached physical U, Omega of one state (the base of the linearised product)
+static sp_status cache_base(sp_plan* p, const double2* u) {
   const bool fp32 = (p->precision == SP_MIXED);
   SP_TRY_HIP(launch_synth_y(p, u, fp32), "synth_y");
   SP_TRY_HIP(launch_fft_x_inv(p, fp32), "fft_x_inv");
   SP_TRY_HIP(launch_z_product(p, 2, fp32), "z_product(base)");
+  return SP_OK;
+}
+
+// Base state at u; for nsteps > 1 also the trajectory U_k = Phi_dt^k(u),
+// k < nsteps, for the chain rule of the multi-step operator.
+sp_status linearize(sp_plan* p, const double2* u) {
+  p->base_valid = false;
+  p->traj_valid = false;
+  sp_status s = cache_base(p, u);
+  if (s) return s;
   p->base_valid = true;
+  p->base_step = 0;
+  if (p->nsteps > 1) {
+    const size_t nc = canon_count(p);
+    SP_TRY_HIP(hipMemcpyAsync(p->traj, u, nc * sizeof(double2), hipMemcpyDeviceToDevice,
+                              p->stream),
+               "copy U_0");
+    for (int k = 0; k + 1 < p->nsteps; ++k) {
+      s = befe_into(p, p->traj + (size_t)k * nc, p->traj + (size_t)(k + 1) * nc, false);
+      if (s) return s;
+    }
+    p->traj_valid = true;
+  }
+  return SP_OK;
+}
+
+// make the cached base the state U_k of the trajectory (k = 0: the
+// linearisation point itself)
+sp_status base_at(sp_plan* p, int k) {
+  if (p->base_step == k) return SP_OK;
+  if (!p->traj_valid) return set_error(p, SP_ERR_INVALID, "no trajectory: call sp_linearize");
+  sp_status s = cache_base(p, p->traj + (size_t)k * canon_count(p));
+  if (s) return s;
+  p->base_step = k;
+  return SP_OK;
+}
+
+// one linearised BEFE step about the cached base: J_Phi du
+static sp_status jvp_phi_step(sp_plan* p, const double2* du, double2* out) {
+  const bool fp32 = (p->precision == SP_MIXED);
+  sp_status s = nonlinear_to_nv(p, du, 1, fp32);
+  if (s) return s;
+  SP_TRY_HIP(launch_analysis_solve(p, du, p->d.inv_dt, out, 0, fp32), "analysis+solve");
   return SP_OK;
 }
 
 sp_status jvp_lin(sp_plan* p, int op, const double2* du, double2* out) {
   if (!p->base_valid) return set_error(p, SP_ERR_INVALID, "no base state: call sp_linearize");
-  const bool fp32 = (p->precision == SP_MIXED);
-  sp_status s = nonlinear_to_nv(p, du, 1, fp32);
-  if (s) return s;
-  double2* dst = (op == SP_OP_PHI) ? out : p->t2;
-  SP_TRY_HIP(launch_analysis_solve(p, du, p->d.inv_dt, dst, 0, fp32), "analysis+solve");
-  if (op != SP_OP_PHI)
-    SP_TRY_HIP(launch_axpby(p, p->t2, p->d.inv_dt, du, -p->d.inv_dt, out, canon_count(p)),
-               "axpby");
+  const int n = (op == SP_OP_PHI) ? 1 : p->nsteps;
+  if (n == 1) {
+    sp_status s = base_at(p, 0);
+    if (s) return s;
+    double2* dst = (op == SP_OP_PHI) ? out : p->t2;
+    s = jvp_phi_step(p, du, dst);
+    if (s) return s;
+    if (op != SP_OP_PHI)
+      SP_TRY_HIP(launch_axpby(p, p->t2, p->d.inv_dt, du, -p->d.inv_dt, out, canon_count(p)),
+                 "axpby");
+    return SP_OK;
+  }
+  // chain rule along the trajectory: v_{k+1} = J_Phi(U_k) v_k
+  const double2* v = du;
+  for (int k = 0; k < n; ++k) {
+    sp_status s = base_at(p, k);
+    if (s) return s;
+    double2* dst = (k & 1) ? p->t2 : p->t1;
+    s = jvp_phi_step(p, v, dst);
+    if (s) return s;
+    v = dst;
+  }
+  const double iT = p->d.inv_dt / n;
+  SP_TRY_HIP(launch_axpby(p, v, iT, du, -iT, out, canon_count(p)), "axpby");
   return SP_OK;
 }
 
@@ -141,6 +209,28 @@ extern "C" sp_status sp_norm(sp_plan* p, const double* a, double* host_norm) {
   CHECK_PTR(a);
   CHECK_PTR(host_norm);
   return host_norm_of(p, (const double2*)a, host_norm);
+}
+
+extern "C" sp_status sp_plan_set_steps(sp_plan* p, int32_t nsteps) {
+  CHECK_PLAN();
+  if (nsteps < 1 || nsteps > 100000)
+    return set_error(p, SP_ERR_INVALID, "nsteps must be in [1, 100000]");
+  sp_status s = hip_check(p, hipStreamSynchronize(p->stream), "sync");
+  if (s) return s;
+  if (p->traj) (void)hipFree(p->traj);
+  p->traj = nullptr;
+  p->traj_valid = false;
+  p->base_valid = false;
+  p->nsteps = 1;
+  if (nsteps > 1) {
+    const size_t bytes = (size_t)nsteps * canon_count(p) * sizeof(double2);
+    if (hipMalloc((void**)&p->traj, bytes) != hipSuccess) {
+      p->traj = nullptr;
+      return set_error(p, SP_ERR_NOMEM, "cannot allocate the trajectory");
+    }
+  }
+  p->nsteps = nsteps;
+  return SP_OK;
 }
 
 extern "C" sp_status sp_linearize(sp_plan* p, const double* u) {

@@ -212,6 +212,7 @@ static void free_plan(sp_plan* p) {
   if (p->h_partial) (void)hipHostFree(p->h_partial);
   p->prof.release();
   if (p->ws && p->ws_owned) (void)hipFree(p->ws);
+  if (p->traj) (void)hipFree(p->traj);
 }
 
 }  // namespace sp
@@ -393,6 +394,7 @@ extern "C" sp_status sp_plan_set_dt(sp_plan* p, double dt) {
   p->d.dt = dt;
   p->d.inv_dt = 1.0 / dt;
   p->base_valid = false;
+  p->traj_valid = false;
   return build_mode_data(p);
 }
 

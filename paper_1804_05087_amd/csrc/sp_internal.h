@@ -100,6 +100,13 @@ struct sp_plan {
   double* h_partial = nullptr;  // pinned host mirror
   int npartial = 0;
   bool base_valid = false;
+  // residual operator: nsteps BEFE steps of dt (1: Stokes operator, T = dt;
+  // > 1: time-integration operator, T = nsteps dt) and, for nsteps > 1, the
+  // trajectory U_0 .. U_{nsteps-1} of the linearisation point (device)
+  int nsteps = 1;
+  double2* traj = nullptr;
+  bool traj_valid = false;
+  int base_step = 0;  // trajectory index of the cached base state
 
   sp::Profiler prof;
 
@@ -166,6 +173,7 @@ sp_status host_norm_of(sp_plan* p, const double2* a, double* out);
 sp_status befe_into(sp_plan* p, const double2* u, double2* out, bool fp32);
 sp_status residual_into(sp_plan* p, const double2* u, double2* r);
 sp_status linearize(sp_plan* p, const double2* u);
+sp_status base_at(sp_plan* p, int k);
 sp_status jvp_lin(sp_plan* p, int op, const double2* du, double2* out);
 sp_status vjp_lin(sp_plan* p, int op, const double2* w, double2* out);
 
