@@ -312,6 +312,89 @@ def gint_compare(seeds=(8, 1, 0, 2, 3), re_find=400.0, re=380.0, t_stokes=100.0,
     return out
 
 
+def _truncate(u, dims):
+    """Spectral truncation of a canonical field to a smaller grid (Fourier
+    modes |m| < n/2 in x and z, Chebyshev coefficients n < ny; Nyquist zero)."""
+    import numpy as np
+    nx, ny, nz = dims
+    a = u.cpu().numpy()
+    NX = a.shape[1]
+    out = np.zeros((3, nx, nz // 2 + 1, ny), dtype=np.complex128)
+    for i in range(nx):
+        if i == nx // 2:
+            continue
+        m = i if i < nx // 2 else i - nx
+        out[:, i, :nz // 2, :] = a[:, m % NX, :nz // 2, :ny]
+    return out
+
+
+def spectra_report(dims=(12, 17, 12), re_find=400.0, re=500.0, seeds=(8, 1, 0, 2, 3),
+                   stokes_T=(1e-4, 0.1, 100.0), int_T=(1.0, 10.0), dt_int=0.03125):
+    """Spectra of the Newton operators' Jacobians (Sec. 5) on a small grid of
+    the Couette box, restricted to admissible fields. The base state is a
+    non-laminar equilibrium: found by the Stokes solver at 32x33x32, Re = 400
+    from the perturbation family, truncated to the small grid, re-converged
+    there and continued to Re = 500 (laminar flow if any of that fails).
+    Operators: G^Stokes_T for several T (with Beaume's rescaling) and G^int_T
+    with dt = 0.03125. Eigenvalues on the host."""
+    import torch
+    from paper_1804_05087_amd import SP_OP_PHI, Plan, spectra, synth
+    dev = torch.device("cuda", 0)
+    box = (2 * math.pi / 1.14, 2 * math.pi / 2.5)
+    lam0 = torch.from_numpy(synth.laminar_field(*dims)).to(dev)
+    base, where = lam0.clone(), "laminar"
+    big = (32, 33, 32)
+    lamb = torch.from_numpy(synth.laminar_field(*big)).to(dev)
+    PB = Plan(*big, *box, re_find, 100.0, device=dev)
+    for seed in seeds:
+        u = torch.from_numpy(synth.perturbation_field(*big, *box, seed=seed)).to(dev)
+        rep = PB.newton_hookstep(u, max_newton=30, max_krylov=400, gmres_rtol=1e-4,
+                                 newton_tol=1e-12)
+        if not (rep["converged"] and PB.norm((u - lamb).contiguous()) > 1e-3):
+            continue
+        us = torch.from_numpy(_truncate(u, dims)).to(dev)
+        ok = True
+        for r2 in (re_find, 450.0, re):
+            P2 = Plan(*dims, *box, r2, 100.0, device=dev)
+            rep = P2.newton_hookstep(us, max_newton=30, max_krylov=400, gmres_rtol=1e-6,
+                                     newton_tol=1e-12)
+            ok = ok and rep["converged"]
+            log("spectra base seed", seed, "Re", r2, rep["converged"], rep["res_norm"][-1])
+        d = P2.norm((us - lam0).contiguous())
+        if ok and d > 1e-3:
+            base = us.clone()
+            where = (f"equilibrium (seed {seed} at 32x33x32, Re 400, truncated and continued; "
+                     f"||u - U_lam|| = {d:.4f})")
+            break
+    log("spectra base:", where)
+    out = {"metric": "jacobian_spectra", "grid": list(dims), "re": re, "base": where,
+           "operators": {}}
+
+    # the admissible subspace, from one BEFE step's Jacobian (shared by all operators)
+    Q = spectra.admissible_basis(spectra.jacobian_dense(Plan(*dims, *box, re, 1.0, device=dev),
+                                                        base, op=SP_OP_PHI))
+
+    def one(P, T, scale):
+        t0 = time.perf_counter()
+        J = spectra.jacobian_dense(P, base)
+        lam = spectra.eigenvalues(spectra.restrict(J, Q))
+        s = spectra.summary(spectra.beaume_scale(lam, T) if scale else lam)
+        s["admissible_dim"] = int(Q.shape[1])
+        s["seconds"] = round(time.perf_counter() - t0, 2)
+        return s
+
+    for T in stokes_T:
+        out["operators"][f"stokes_T{T:g}_beaume_scaled"] = s = one(
+            Plan(*dims, *box, re, T, device=dev), T, True)
+        log("stokes", T, s)
+    PI = Plan(*dims, *box, re, dt_int, device=dev)
+    for T in int_T:
+        PI.set_steps(int(round(T / dt_int)))
+        out["operators"][f"int_T{T:g}"] = s = one(PI, T, False)
+        log("int", T, s)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,6 +416,9 @@ def main():
                     help="instead of the benchmark line, print the time-step count of "
                          "Newton solves with the Stokes operator (T = 100) against the "
                          "time-integration operator (dt = 0.03125) at 32x33x32, Re 380")
+    ap.add_argument("--spectra", action="store_true",
+                    help="instead of the benchmark line, print spectra statistics of the "
+                         "Stokes and time-integration Jacobians at 12x17x12")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
@@ -344,6 +430,9 @@ def main():
         return
     if args.gint_compare:
         print(json.dumps(gint_compare()), flush=True)
+        return
+    if args.spectra:
+        print(json.dumps(spectra_report()), flush=True)
         return
     import numpy as np
     import torch
