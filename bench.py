@@ -395,6 +395,61 @@ def spectra_report(dims=(12, 17, 12), re_find=400.0, re=500.0, seeds=(8, 1, 0, 2
     return out
 
 
+def advect_compare(seeds=range(5), dts=(10.0, 100.0), max_krylov=400, rtol=1e-3):
+    """The Stokes step against the step with the laminar advection in its
+    implicit operator (Sec. 6's proposed remedy) at 32x33x32, Re = 400:
+    GMRES iterations of the first Newton step to `rtol` (with the relative
+    residual after at most `max_krylov`), and hookstep Newton solves to
+    ||r|| < 1e-10 (GMRES to 1e-4), from the energy-1e-2 perturbation family;
+    plus the cost of one step of each kind."""
+    import torch
+    from paper_1804_05087_amd import Plan, synth
+    w = WORKLOADS["couette_32x33x32_re400_dt100"]
+    dev = torch.device("cuda", 0)
+    dims = (w["nx"], w["ny"], w["nz"])
+    box = (w["lx"], w["lz"])
+    lam = torch.from_numpy(synth.laminar_field(*dims)).to(dev)
+    out = {"metric": "krylov_iterations_stokes_vs_advected", "workload": "couette_32x33x32_re400",
+           "first_step_rtol": rtol, "max_krylov": max_krylov, "energy": 1e-2, "runs": {}}
+    for dt in dts:
+        for adv in (False, True):
+            P = Plan(*dims, *box, w["re"], dt, device=dev)
+            t0 = time.perf_counter()
+            if adv:
+                P.set_advection(True)
+            build = time.perf_counter() - t0
+            u0 = torch.from_numpy(synth.perturbation_field(*dims, *box, seed=0)).to(dev)
+            o = P.empty()
+            s, _ = time_loop(torch, lambda: P.befe_step(u0, o), 200, 20)
+            rows = []
+            for seed in seeds:
+                u0 = torch.from_numpy(synth.perturbation_field(*dims, *box, seed=seed)).to(dev)
+                u = u0.clone()
+                first = P.newton_gmres(u, max_newton=1, max_krylov=max_krylov, gmres_rtol=rtol,
+                                       newton_tol=0.0)
+                u = u0.clone()
+                full = P.newton_hookstep(u, max_newton=30, max_krylov=max_krylov,
+                                         gmres_rtol=1e-4, newton_tol=1e-10)
+                rows.append({"seed": seed, "K_first": first["krylov"][0],
+                             "relres_first": float(f"{first['gmres_relres'][0]:.2e}"),
+                             "converged": full["converged"], "newton_iters": full["newton_iters"],
+                             "K_total": full["total_krylov"], "seconds": round(full["seconds"], 3),
+                             "dist_to_laminar_L2": float(f"{P.norm((u - lam).contiguous()):.3e}")})
+                log("dt", dt, "advected" if adv else "stokes", rows[-1])
+            key = f"dt{dt:g}_{'advected' if adv else 'stokes'}"
+            ks = [r["K_first"] for r in rows]
+            conv = [r for r in rows if r["converged"]]
+            out["runs"][key] = {
+                "phi_us": round(1e6 * s / 200, 2), "build_seconds": round(build, 2),
+                "K_first_mean": sum(ks) / len(ks),
+                "relres_first_mean": sum(r["relres_first"] for r in rows) / len(rows),
+                "converged": len(conv),
+                "K_total_mean_converged": (sum(r["K_total"] for r in conv) / len(conv)
+                                           if conv else None),
+                "runs": rows}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -419,6 +474,9 @@ def main():
     ap.add_argument("--spectra", action="store_true",
                     help="instead of the benchmark line, print spectra statistics of the "
                          "Stokes and time-integration Jacobians at 12x17x12")
+    ap.add_argument("--advect-compare", action="store_true",
+                    help="instead of the benchmark line, compare Krylov counts of the Stokes "
+                         "step and the step with laminar advection in its implicit operator")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
@@ -433,6 +491,9 @@ def main():
         return
     if args.spectra:
         print(json.dumps(spectra_report()), flush=True)
+        return
+    if args.advect_compare:
+        print(json.dumps(advect_compare()), flush=True)
         return
     import numpy as np
     import torch

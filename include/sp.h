@@ -105,6 +105,30 @@ sp_status sp_plan_set_precision(sp_plan* plan, int32_t precision);
  * not provided (SP_ERR_INVALID). n in [1, 100000]; n > 1 allocates the
  * trajectory, n canonical fields (SP_ERR_NOMEM if that fails). Synchronises. */
 sp_status sp_plan_set_steps(sp_plan* plan, int32_t nsteps);
+/* Laminar advection in the implicit operator (the remedy proposed in Sec. 6):
+ * with on != 0 every BEFE step of the plan (sp_befe_step, sp_residual, the
+ * Jacobian actions and the Newton drivers) becomes
+ *   (I - dt (L + M)) Phi~(U) = U + dt (N(U) - M U),
+ *   M u = -(U_lam . grad) u - (u . grad) U_lam,  U_lam = y e_x,
+ * which has the same roots as the Stokes step. Per Fourier mode
+ * M u = -(i k_x y u + v, i k_x y v, i k_x y w); the tau systems lose the parity
+ * splitting, so the plan builds each mode's dense solution operator on the
+ * host (O(modes N^3) work, threaded; seconds at 48x65x48) and keeps
+ * 3 (N-1) x 3 (N+1) complex entries per mode on the device (0.74 GB at
+ * 48x65x48); sp_plan_set_dt rebuilds them. The VJP is not provided for this
+ * operator (SP_ERR_INVALID); sp_stokes_solve stays the Stokes solve. on = 0
+ * restores the Stokes step (the operators stay allocated). Synchronises. */
+sp_status sp_plan_set_advection(sp_plan* plan, int32_t on);
+/* The per-mode computation of sp_plan_set_advection alone, on the host (no
+ * plan, no device work): the solution operator of the advected tau system of
+ * one mode (k_x, k_z) != (0, 0) with N+1 Chebyshev coefficients, written to
+ * S_out as 3(N-1) x 3(N+1) complex values (interleaved re, im), column-major:
+ * entry (row, col) at 2 (col 3(N+1) + row); col = c (N-1) + n for the
+ * right-hand-side coefficient n <= N-2 of component c, row = c (N+1) + n for
+ * the velocity coefficient. The caller owns S_out (18 (N-1)(N+1) doubles).
+ * SP_ERR_INVALID on bad arguments or a singular system. */
+sp_status sp_advected_mode_operator(int32_t N, double kx, double kz, double re, double inv_dt,
+                                    double* S_out);
 /* shape4 = {3, nx, nz/2+1, ny}; packed_n = 3 ny (nx-1)(nz-1). */
 sp_status sp_state_shape(const sp_plan* plan, int64_t shape4[4], int64_t* packed_n);
 /* Device bytes of a Krylov workspace for sp_newton_gmres with max_krylov. */

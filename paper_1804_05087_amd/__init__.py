@@ -123,6 +123,12 @@ class Plan:
     def set_precision(self, precision: int):
         self._check(self.lib.sp_plan_set_precision(self.h, precision))
 
+    def set_advection(self, on: bool = True):
+        """Laminar advection (U_lam . grad) u + (u . grad) U_lam in the
+        implicit operator of every step (same roots, different Jacobian)."""
+        self._check(self.lib.sp_plan_set_advection(self.h, 1 if on else 0))
+        self.advect = bool(on)
+
     def set_steps(self, nsteps: int):
         """Residual operator of nsteps BEFE steps of dt: 1 = Stokes operator
         (T = dt), > 1 = time-integration operator with T = nsteps * dt."""

@@ -70,6 +70,9 @@ SIGNATURES = {
     "sp_plan_set_dt": (C.c_int, [C.c_void_p, C.c_double]),
     "sp_plan_set_precision": (C.c_int, [C.c_void_p, C.c_int32]),
     "sp_plan_set_steps": (C.c_int, [C.c_void_p, C.c_int32]),
+    "sp_plan_set_advection": (C.c_int, [C.c_void_p, C.c_int32]),
+    "sp_advected_mode_operator": (C.c_int, [C.c_int32, C.c_double, C.c_double, C.c_double,
+                                            C.c_double, C.c_void_p]),
     "sp_state_shape": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "sp_plan_workspace_bytes": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_size_t)]),
     "sp_plan_set_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),

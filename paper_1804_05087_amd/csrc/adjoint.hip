@@ -411,6 +411,8 @@ sp_status vjp_lin(sp_plan* p, int op, const double2* w, double2* out) {
   if (!p->base_valid) return set_error(p, SP_ERR_INVALID, "no base state: call sp_linearize");
   if (op == SP_OP_RESIDUAL && p->nsteps > 1)
     return set_error(p, SP_ERR_INVALID, "the VJP of the multi-step operator is not provided");
+  if (p->advect)
+    return set_error(p, SP_ERR_INVALID, "the VJP of the advected step is not provided");
   {
     sp_status s = base_at(p, 0);
     if (s) return s;

@@ -45,8 +45,20 @@ sp_status host_norm_of(sp_plan* p, const double2* a, double* out) {
 }
 
 sp_status befe_into(sp_plan* p, const double2* u, double2* out, bool fp32) {
+  if (p->advect && u == out) {  // the advected step reads u after the solve writes out
+    SP_TRY_HIP(hipMemcpyAsync(p->adv_x, u, canon_count(p) * sizeof(double2),
+                              hipMemcpyDeviceToDevice, p->stream),
+               "copy u");
+    u = p->adv_x;
+  }
   sp_status s = nonlinear_to_nv(p, u, 0, fp32);
   if (s) return s;
+  if (p->advect) {
+    SP_TRY_HIP(launch_analysis_rhs(p, u, p->d.inv_dt, p->g, fp32), "analysis_rhs");
+    SP_TRY_HIP(launch_stokes_solve(p, p->g, out, 1), "stokes_solve (mean mode)");
+    SP_TRY_HIP(launch_adv_apply(p, p->g, u, out), "advected solve");
+    return SP_OK;
+  }
   SP_TRY_HIP(launch_analysis_solve(p, u, p->d.inv_dt, out, 1, fp32), "analysis+solve");
   return SP_OK;
 }
@@ -115,6 +127,12 @@ static sp_status jvp_phi_step(sp_plan* p, const double2* du, double2* out) {
   const bool fp32 = (p->precision == SP_MIXED);
   sp_status s = nonlinear_to_nv(p, du, 1, fp32);
   if (s) return s;
+  if (p->advect) {
+    SP_TRY_HIP(launch_analysis_rhs(p, du, p->d.inv_dt, p->g, fp32), "analysis_rhs");
+    SP_TRY_HIP(launch_stokes_solve(p, p->g, out, 0), "stokes_solve (mean mode)");
+    SP_TRY_HIP(launch_adv_apply(p, p->g, du, out), "advected solve");
+    return SP_OK;
+  }
   SP_TRY_HIP(launch_analysis_solve(p, du, p->d.inv_dt, out, 0, fp32), "analysis+solve");
   return SP_OK;
 }
@@ -230,6 +248,22 @@ extern "C" sp_status sp_plan_set_steps(sp_plan* p, int32_t nsteps) {
     }
   }
   p->nsteps = nsteps;
+  return SP_OK;
+}
+
+extern "C" sp_status sp_plan_set_advection(sp_plan* p, int32_t on) {
+  CHECK_PLAN();
+  sp_status s = hip_check(p, hipStreamSynchronize(p->stream), "sync");
+  if (s) return s;
+  p->base_valid = false;
+  p->traj_valid = false;
+  if (!on) {
+    p->advect = false;
+    return SP_OK;
+  }
+  s = build_advection(p);
+  if (s) return s;
+  p->advect = true;
   return SP_OK;
 }
 

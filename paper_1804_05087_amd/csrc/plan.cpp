@@ -213,6 +213,8 @@ static void free_plan(sp_plan* p) {
   p->prof.release();
   if (p->ws && p->ws_owned) (void)hipFree(p->ws);
   if (p->traj) (void)hipFree(p->traj);
+  if (p->d_adv) (void)hipFree(p->d_adv);
+  if (p->adv_x) (void)hipFree(p->adv_x);
 }
 
 }  // namespace sp
@@ -395,7 +397,9 @@ extern "C" sp_status sp_plan_set_dt(sp_plan* p, double dt) {
   p->d.inv_dt = 1.0 / dt;
   p->base_valid = false;
   p->traj_valid = false;
-  return build_mode_data(p);
+  sp_status bs = build_mode_data(p);
+  if (bs == SP_OK && p->advect) bs = build_advection(p);
+  return bs;
 }
 
 extern "C" sp_status sp_plan_set_precision(sp_plan* p, int32_t precision) {

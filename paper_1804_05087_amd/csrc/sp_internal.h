@@ -107,6 +107,11 @@ struct sp_plan {
   double2* traj = nullptr;
   bool traj_valid = false;
   int base_step = 0;  // trajectory index of the cached base state
+  // laminar advection in the implicit operator: per-mode dense solution
+  // operators [mode][3(N-1)][3 ny] (device) and an input copy for aliasing
+  bool advect = false;
+  double2* d_adv = nullptr;
+  double2* adv_x = nullptr;
 
   sp::Profiler prof;
 
@@ -174,6 +179,8 @@ sp_status befe_into(sp_plan* p, const double2* u, double2* out, bool fp32);
 sp_status residual_into(sp_plan* p, const double2* u, double2* r);
 sp_status linearize(sp_plan* p, const double2* u);
 sp_status base_at(sp_plan* p, int k);
+sp_status build_advection(sp_plan* p);
+hipError_t launch_adv_apply(sp_plan* p, const double2* g, const double2* x, double2* out);
 sp_status jvp_lin(sp_plan* p, int op, const double2* du, double2* out);
 sp_status vjp_lin(sp_plan* p, int op, const double2* w, double2* out);
 

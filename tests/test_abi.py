@@ -96,3 +96,29 @@ def test_hook_step_rejects_bad_arguments(lib):
     Z = np.zeros((2, 2), order="F")
     assert lib.sp_hook_step(Z.ctypes.data, 2, g.ctypes.data, 2, 1.0, y.ctypes.data,
                             C.byref(mu), C.byref(res)) == -1
+
+
+def test_advected_mode_operator_matches_oracle(lib):
+    """The host computation behind sp_plan_set_advection (dense tau system with
+    the laminar advection, LU with partial pivoting, refinement with
+    long-double residuals) against the oracle's refined dense solve."""
+    import numpy as np
+    from oracle import advect
+    from oracle.stokes import _refined_solve, mode_rhs
+    import scipy.linalg as sla
+    for N, kx, kz, re, dt in ((8, 1.14, 2.5, 400.0, 100.0), (16, -2.28, 0.0, 1000.0, 1.0),
+                              (16, 0.0, 5.0, 400.0, 10.0)):
+        n1 = N + 1
+        S = np.zeros(2 * 3 * (N - 1) * 3 * n1)
+        assert lib.sp_advected_mode_operator(N, kx, kz, re, 1.0 / dt, S.ctypes.data) == 0
+        S = S.view(np.complex128).reshape(3 * (N - 1), 3 * n1).T   # rows x cols
+        A = advect.mode_matrix_adv(N, kx, kz, re, 1.0 / dt)
+        lu = sla.lu_factor(A)
+        ref = np.zeros_like(S)
+        for col in range(3 * (N - 1)):
+            gg = np.zeros((3, n1), dtype=np.complex128)
+            gg[col // (N - 1), col % (N - 1)] = 1.0
+            ref[:, col] = _refined_solve(A, lu, mode_rhs(N, gg))[:3 * n1]
+        err = np.abs(S - ref).max() / np.abs(ref).max()
+        assert err < 1e-13, (N, kx, kz, err)
+    assert lib.sp_advected_mode_operator(8, 0.0, 0.0, 400.0, 0.01, S.ctypes.data) == -1
