@@ -638,6 +638,27 @@ def main():
                            "gmres_rtol": args.newton_rtol}
         newton["mixed_vs_fp64_final_L2"] = P.norm((finals["mixed"] - finals["fp64"]).contiguous())
         P.set_precision(SP_FP64)
+        # the same solve with the laminar advection in the implicit operator
+        # (Sec. 6's proposed remedy; same roots, fewer Krylov iterations)
+        PA = Plan(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], w["re"], w["dt"], device=dev)
+        tb = time.perf_counter()
+        PA.set_advection(True)
+        build_s = time.perf_counter() - tb
+        uu = u0.clone()
+        torch.cuda.synchronize()
+        rep = PA.newton_gmres(uu, max_newton=args.newton_max, max_krylov=args.newton_krylov,
+                              gmres_rtol=args.newton_rtol, newton_tol=1e-10)
+        newton["fp64_advected"] = {
+            "converged": rep["converged"], "seconds": round(rep["seconds"], 4),
+            "plan_build_seconds": round(build_s, 3),
+            "newton_iters": rep["newton_iters"], "total_krylov": rep["total_krylov"],
+            "total_actions": rep["total_actions"], "final_res_norm": rep["res_norm"][-1],
+            "res_history": [float(f"{x:.3e}") for x in rep["res_norm"]],
+            "krylov": rep["krylov"],
+            "gmres_relres": [float(f"{x:.2e}") for x in rep["gmres_relres"]],
+            "vs_fp64_final_L2": P.norm((uu - finals["fp64"]).contiguous())}
+        log("newton fp64_advected", newton["fp64_advected"])
+        del PA
 
     cpu = None
     if not args.no_cpu_baseline:
