@@ -460,7 +460,7 @@ def main():
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--newton-krylov", type=int, default=200,
                     help="Krylov cap per Newton step (200 minimises time to 1e-10 at 48x65x48)")
-    ap.add_argument("--newton-max", type=int, default=8)
+    ap.add_argument("--newton-max", type=int, default=16)
     ap.add_argument("--newton-rtol", type=float, default=1e-4)
     ap.add_argument("--newton-energy", type=float, default=1e-6,
                     help="perturbation energy of the Newton start (E = 1e-2 does not "
