@@ -645,6 +645,9 @@ def main():
         tb = time.perf_counter()
         PA.set_advection(True)
         build_s = time.perf_counter() - tb
+        oa = PA.empty()
+        sa, _ = time_loop(torch, lambda: PA.befe_step(u, oa), 200, 20)
+        res["phi_fp64_advected_evals_per_s"] = 200 / sa
         uu = u0.clone()
         torch.cuda.synchronize()
         rep = PA.newton_gmres(uu, max_newton=args.newton_max, max_krylov=args.newton_krylov,

@@ -216,6 +216,7 @@ __global__ void __launch_bounds__(256)
   const double2* Sm = S + (size_t)mode * C * R;
   for (int r = threadIdx.x; r < R; r += blockDim.x) {
     double ar = 0.0, ai = 0.0;
+#pragma unroll 8
     for (int col = 0; col < C; ++col) {
       const double2 s = Sm[(size_t)col * R + r];
       const double2 b = gl[col];

@@ -76,3 +76,34 @@ def test_advected_multistep_and_newton():
     assert rep["converged"]
     lam = synth.laminar_field(*dims)
     assert np.abs(to_np(x) - lam).max() < 1e-9
+
+
+def test_advected_mixed_precision():
+    """FP32 transforms and contractions with the FP64 advected solve, against
+    the FP64 oracle (same bound as the Stokes step's mixed path)."""
+    from paper_1804_05087_amd import SP_MIXED, Plan
+    dims, re, dt = (16, 17, 16), 400.0, 100.0
+    say("advected mixed", dims)
+    g = Grid(*dims, *BOX)
+    A = advect.AdvBefe(g, re, dt)
+    P = Plan(*dims, *BOX, re, dt, precision=SP_MIXED)
+    P.set_advection(True)
+    u = synth.perturbation_field(*dims, *BOX, seed=0)
+    du = synth.random_admissible(*dims, *BOX, seed=1)
+    e_phi = rel(to_np(P.befe_step(to_dev(u))), A.phi(u))
+    e_jvp = rel(to_np(P.jvp(to_dev(u), to_dev(du), SP_OP_PHI)), A.jvp(u, du))
+    say("mixed advected errors phi", e_phi, "jvp", e_jvp)
+    assert e_phi < 2e-5 and e_jvp < 2e-5
+    assert e_phi > 1e-12  # the FP32 path really ran
+
+
+def test_invalid_arguments_are_rejected():
+    from paper_1804_05087_amd import Plan
+    P = Plan(8, 9, 8, *BOX, 400.0, 1.0)
+    for bad in (0, -3, 100001):
+        with pytest.raises(SPError):
+            P.set_steps(bad)
+    u = to_dev(synth.perturbation_field(8, 9, 8, *BOX, seed=0))
+    for kw in (dict(max_trials=0), dict(delta_min=0.0), dict(delta_min=1.0, delta_max=0.5)):
+        with pytest.raises(SPError):
+            P.newton_hookstep(u.clone(), max_newton=1, max_krylov=5, **kw)
