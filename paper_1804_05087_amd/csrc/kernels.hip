@@ -567,40 +567,42 @@ __global__ void k_axpby(const double2* __restrict__ x, double a, const double2* 
 
 // Per-block partial sums of (1/2) sum_modes w_m sum_c a^H G a (volume-normalised
 // squared L2 norm), w_m = 1 (m_z = 0) or 2 (m_z > 0), Nyquist excluded, with the
-// Chebyshev Gram matrix G_nm = int T_n T_m dy = 1/(1-(n+m)^2) + 1/(1-(n-m)^2)
-// for n + m even (0 otherwise) evaluated on the fly.
+// Chebyshev Gram matrix G_nm = int T_n T_m dy (zero for n + m odd; the plan's
+// table, row-major). One wave per column (component, mode): lane n forms
+// (G a)_n from the column's entries of its parity, then a_n^* (G a)_n is
+// reduced over the wave; four columns per block at a time.
 __global__ void __launch_bounds__(256)
-    k_norm_partial(const double2* __restrict__ a, double* __restrict__ partial, int nx, int ny,
-                   int nzh) {
-  __shared__ double red[256];
+    k_norm_partial(const double2* __restrict__ a, const double* __restrict__ G,
+                   double* __restrict__ partial, int nx, int ny, int nzh) {
+  __shared__ double red[4];
   const int ncol = 3 * nx * nzh;
+  const int wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   double acc = 0.0;
-  for (int col = blockIdx.x * blockDim.x + threadIdx.x; col < ncol;
-       col += gridDim.x * blockDim.x) {
+  for (int col = blockIdx.x * 4 + wid; col < ncol; col += gridDim.x * 4) {  // wave-uniform
     const int j = col % nzh;
     const int i = (col / nzh) % nx;
     if (i == nx / 2 || j == nzh - 1) continue;
     const double2* v = a + (size_t)col * ny;
     double s = 0.0;
-    for (int n = 0; n < ny; ++n) {
+    for (int n = lane; n < ny; n += 64) {
+      const double* g = G + (size_t)n * ny;
       double tr = 0.0, ti = 0.0;
       for (int m = (n & 1); m < ny; m += 2) {
-        const double sp = (double)(n + m), dm = (double)(n - m);
-        const double gnm = 1.0 / (1.0 - sp * sp) + 1.0 / (1.0 - dm * dm);
-        tr += gnm * v[m].x;
-        ti += gnm * v[m].y;
+        const double2 vm = v[m];
+        tr += g[m] * vm.x;
+        ti += g[m] * vm.y;
       }
-      s += v[n].x * tr + v[n].y * ti;
+      const double2 vn = v[n];
+      s += vn.x * tr + vn.y * ti;
     }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
     acc += (j == 0 ? 1.0 : 2.0) * s;
   }
-  red[threadIdx.x] = acc;
+  if (lane == 0) red[wid] = acc;
   __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[blockIdx.x] = 0.5 * red[0];
+  if (threadIdx.x == 0) partial[blockIdx.x] = 0.5 * (red[0] + red[1] + red[2] + red[3]);
 }
 
 // Packed real vector <-> canonical (see sp.h for the order).
@@ -845,11 +847,11 @@ hipError_t launch_axpby(sp_plan* p, const double2* x, double a, const double2* y
 hipError_t launch_norm_partial(sp_plan* p, const double2* a, double* partial, int* nblocks) {
   const Dims& d = p->d;
   const int ncol = 3 * d.nx * d.nzh;
-  int blocks = (ncol + 255) / 256;
+  int blocks = (ncol + 3) / 4;  // one wave per column
   if (blocks > p->npartial) blocks = p->npartial;
   SP_PROF_BEGIN(p, KID_NORM);
-  hipLaunchKernelGGL(k_norm_partial, dim3(blocks), dim3(256), 0, p->stream, a, partial, d.nx,
-                     d.ny, d.nzh);
+  hipLaunchKernelGGL(k_norm_partial, dim3(blocks), dim3(256), 0, p->stream, a, p->d_G, partial,
+                     d.nx, d.ny, d.nzh);
   *nblocks = blocks;
   SP_PROF_END(p, KID_NORM);
   return hipGetLastError();
