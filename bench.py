@@ -241,11 +241,12 @@ def _steps_to_reduction(hist, factor):
 
 
 def gint_compare(seeds=(8, 1, 0, 2, 3), re_find=400.0, re=380.0, t_stokes=100.0,
-                 dt_int=0.03125, t_int=(0.5, 1.0, 2.0), max_krylov=1000, rtol=1e-4,
-                 max_newton=12):
+                 int_cases=((0.5, 1 / 32), (1.0, 1 / 32), (2.0, 1 / 32), (1.0, 1 / 64),
+                            (2.0, 1 / 64)),
+                 max_krylov=1000, rtol=1e-4, max_newton=12):
     """The paper's comparison of the Stokes operator B_T - I (one BEFE step,
-    T = 100) with the time-integration operator (B_dt)^{T/dt} - I (dt =
-    0.03125) in plane Couette flow (Sec. 3.3): a non-laminar equilibrium is
+    T = 100) with the time-integration operator (B_dt)^{T/dt} - I (BEFE steps
+    of dt = 1/32 and 1/64) in plane Couette flow (Sec. 3.3): a non-laminar equilibrium is
     found at Re = 400 with the Stokes operator from the perturbation family at
     32x33x32, Re is lowered to 380, and both operators' hookstep Newton solves
     start from it; the cost is counted in BEFE time steps."""
@@ -284,21 +285,23 @@ def gint_compare(seeds=(8, 1, 0, 2, 3), re_find=400.0, re=380.0, t_stokes=100.0,
         "total_krylov": rep["total_krylov"], "timesteps": _timesteps(rep, 1),
         "seconds": round(rep["seconds"], 3), "history": _history(rep, 1)}
     log("stokes", out["runs"][f"stokes_T{t_stokes:g}"])
-    PI = Plan(*dims, *box, re, dt_int, device=dev)
-    for T in t_int:
+    for T, dt_int in int_cases:
+        PI = Plan(*dims, *box, re, dt_int, device=dev)
         n = int(round(T / dt_int))
         PI.set_steps(n)
         uI = u_eq.clone()
         rep = PI.newton_hookstep(uI, max_newton=max_newton, max_krylov=max_krylov,
                                  gmres_rtol=rtol, newton_tol=1e-10)
-        key = f"int_T{T:g}"
+        key = f"int_T{T:g}_dt1/{round(1 / dt_int)}"
         finals[key] = uI
         out["runs"][key] = {
-            "nsteps": n, "converged": rep["converged"], "newton_iters": rep["newton_iters"],
+            "nsteps": n, "dt": dt_int, "krylov": rep["krylov"],
+            "converged": rep["converged"], "newton_iters": rep["newton_iters"],
             "total_krylov": rep["total_krylov"], "timesteps": _timesteps(rep, n),
             "seconds": round(rep["seconds"], 3), "history": _history(rep, n),
             "dist_to_stokes_root_L2": P.norm((uI - uS).contiguous())}
         log(key, out["runs"][key])
+        del PI
     for v in out["runs"].values():
         for f in (1e-4, 1e-6):
             v[f"steps_to_reduce_{f:g}"] = _steps_to_reduction(v["history"], f)
@@ -308,6 +311,9 @@ def gint_compare(seeds=(8, 1, 0, 2, 3), re_find=400.0, re=380.0, t_stokes=100.0,
         ints = [v[key] for k, v in out["runs"].items() if k.startswith("int") and v[key]]
         if ints and st[key]:
             out[f"int_best_over_stokes_{f:g}"] = min(ints) / st[key]
+    done = [v["timesteps"] for k, v in out["runs"].items() if k.startswith("int") and v["converged"]]
+    if done and st["converged"]:
+        out["int_best_over_stokes_converged"] = min(done) / st["timesteps"]
     out["root_dist_to_laminar_L2"] = P.norm((uS - lam).contiguous())
     return out
 
@@ -450,6 +456,91 @@ def advect_compare(seeds=range(5), dts=(10.0, 100.0), max_krylov=400, rtol=1e-3)
     return out
 
 
+def symmetric_compare(seeds=range(10), energies=(1e-2, 5e-2), re_find=400.0, re=380.0,
+                      t_stokes=100.0, int_cases=((1.0, 1 / 32), (2.0, 1 / 32), (1.0, 1 / 64),
+                                                 (2.0, 1 / 64), (1.0, 1 / 128)),
+                      max_krylov=1000, rtol=1e-4):
+    """The Stokes / time-integration comparison of gint_compare confined to the
+    shift-reflect invariant subspace of EQ1's symmetry group (the paper's EQ1
+    computations stay in it): starts are the perturbation family projected
+    onto the subspace (perturbation rescaled to the given energy); the first
+    non-laminar invariant equilibrium found at Re = 400 is continued to 380."""
+    import torch
+    from paper_1804_05087_amd import Plan, synth
+    w = WORKLOADS["couette_32x33x32_re400_dt100"]
+    dev = torch.device("cuda", 0)
+    dims = (w["nx"], w["ny"], w["nz"])
+    box = (w["lx"], w["lz"])
+    lam = torch.from_numpy(synth.laminar_field(*dims)).to(dev)
+    P = Plan(*dims, *box, re_find, t_stokes, device=dev)
+    P.set_symmetry(True)
+    found, tried = None, []
+    for energy in energies:
+        for seed in seeds:
+            pert = torch.from_numpy(synth.perturbation(*dims, *box, seed, 0.5)).to(dev)
+            P.symmetrize(pert)
+            e = 0.5 * P.norm(pert) ** 2
+            u = (lam + pert * math.sqrt(energy / e)).contiguous()
+            rep = P.newton_hookstep(u, max_newton=40, max_krylov=400, gmres_rtol=1e-4,
+                                    newton_tol=1e-12)
+            d = P.norm((u - lam).contiguous())
+            tried.append({"energy": energy, "seed": seed, "converged": rep["converged"],
+                          "dist_to_laminar_L2": float(f"{d:.4e}"),
+                          "newton_iters": rep["newton_iters"]})
+            log("symmetric search", tried[-1])
+            if rep["converged"] and d > 1e-3:
+                found = u.clone()
+                break
+        if found is not None:
+            break
+    out = {"metric": "gint_vs_stokes_timesteps_symmetric", "workload": "couette_32x33x32",
+           "subspace": "shift-reflect {1, s1, s2, s1 s2}", "search": tried}
+    if found is None:
+        return out
+    u_eq = found
+    runs = {}
+    PS = Plan(*dims, *box, re, t_stokes, device=dev)
+    PS.set_symmetry(True)
+    uS = u_eq.clone()
+    rep = PS.newton_hookstep(uS, max_newton=12, max_krylov=max_krylov, gmres_rtol=rtol,
+                             newton_tol=1e-10)
+    runs[f"stokes_T{t_stokes:g}"] = {
+        "converged": rep["converged"], "newton_iters": rep["newton_iters"],
+        "total_krylov": rep["total_krylov"], "timesteps": _timesteps(rep, 1),
+        "seconds": round(rep["seconds"], 3), "history": _history(rep, 1)}
+    log("symmetric stokes", runs[f"stokes_T{t_stokes:g}"])
+    for T, dt_int in int_cases:
+        PI = Plan(*dims, *box, re, dt_int, device=dev)
+        PI.set_symmetry(True)
+        n = int(round(T / dt_int))
+        PI.set_steps(n)
+        uI = u_eq.clone()
+        rep = PI.newton_hookstep(uI, max_newton=12, max_krylov=max_krylov, gmres_rtol=rtol,
+                                 newton_tol=1e-10)
+        runs[f"int_T{T:g}_dt1/{round(1 / dt_int)}"] = {
+            "nsteps": n, "dt": dt_int, "krylov": rep["krylov"],
+            "converged": rep["converged"], "newton_iters": rep["newton_iters"],
+            "total_krylov": rep["total_krylov"], "timesteps": _timesteps(rep, n),
+            "seconds": round(rep["seconds"], 3), "history": _history(rep, n),
+            "dist_to_stokes_root_L2": P.norm((uI - uS).contiguous())}
+        log("symmetric int", T, dt_int, runs[f"int_T{T:g}_dt1/{round(1 / dt_int)}"])
+        del PI
+    out["runs"] = runs
+    out["root_dist_to_laminar_L2"] = P.norm((uS - lam).contiguous())
+    for f in (1e-4, 1e-6):
+        key = f"steps_to_reduce_{f:g}"
+        for v in runs.values():
+            v[key] = _steps_to_reduction(v["history"], f)
+        st = runs[f"stokes_T{t_stokes:g}"][key]
+        ints = [v[key] for k, v in runs.items() if k.startswith("int") and v[key]]
+        if ints and st:
+            out[f"int_best_over_stokes_{f:g}"] = min(ints) / st
+    done = [v["timesteps"] for k, v in runs.items() if k.startswith("int") and v["converged"]]
+    if done and runs[f"stokes_T{t_stokes:g}"]["converged"]:
+        out["int_best_over_stokes_converged"] = min(done) / runs[f"stokes_T{t_stokes:g}"]["timesteps"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -478,6 +569,9 @@ def main():
     ap.add_argument("--advect-compare", action="store_true",
                     help="instead of the benchmark line, compare Krylov counts of the Stokes "
                          "step and the step with laminar advection in its implicit operator")
+    ap.add_argument("--symmetric-compare", action="store_true",
+                    help="instead of the benchmark line, run the Stokes / time-integration "
+                         "comparison inside the shift-reflect invariant subspace")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
@@ -495,6 +589,9 @@ def main():
         return
     if args.advect_compare:
         print(json.dumps(advect_compare()), flush=True)
+        return
+    if args.symmetric_compare:
+        print(json.dumps(symmetric_compare()), flush=True)
         return
     import numpy as np
     import torch

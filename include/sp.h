@@ -246,6 +246,19 @@ sp_status sp_newton_hookstep(sp_plan* plan, double* u_inout, const sp_newton_opt
                              const sp_hook_opts* hook, sp_newton_report* report,
                              sp_hook_report* hook_report);
 
+/* Projection onto the fields invariant under the shift-reflect group of plane
+ * Couette flow that contains EQ1 (Sec. 3.3), {1, s1, s2, s1 s2} with
+ *   s1 [u, v, w](x, y, z) = [u, v, -w](x + Lx/2, y, -z),
+ *   s2 [u, v, w](x, y, z) = [-u, -v, w](-x + Lx/2, -y, z + Lz/2):
+ * field <- (field + s1 field + s2 field + s1 s2 field) / 4, in place, on the
+ * device (canonical layout; Hermitian and Nyquist conventions preserved).
+ * Phi_dt commutes with the group, so invariant fields stay invariant. */
+sp_status sp_symmetrize(sp_plan* plan, double* field);
+/* on != 0: the Newton drivers project the state and each residual with
+ * sp_symmetrize, so that the search (and its Krylov spaces) stays in the
+ * invariant subspace, which excludes the continuous translations. */
+sp_status sp_plan_set_symmetry(sp_plan* plan, int32_t on);
+
 /* The hookstep subproblem alone, on the host (no plan, no device work): R is
  * the k x k upper-triangular Givens-rotated GMRES matrix (column-major, leading
  * dimension ld >= k, nonzero diagonal), g the k+1 rotated right-hand side.

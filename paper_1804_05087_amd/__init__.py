@@ -123,6 +123,16 @@ class Plan:
     def set_precision(self, precision: int):
         self._check(self.lib.sp_plan_set_precision(self.h, precision))
 
+    def symmetrize(self, a):
+        """In place: project a canonical field onto the shift-reflect
+        invariant subspace (EQ1's symmetry group)."""
+        self._check(self.lib.sp_symmetrize(self.h, self._field(a, "a")))
+        return a
+
+    def set_symmetry(self, on: bool = True):
+        """Confine the Newton drivers to the shift-reflect invariant subspace."""
+        self._check(self.lib.sp_plan_set_symmetry(self.h, 1 if on else 0))
+
     def set_advection(self, on: bool = True):
         """Laminar advection (U_lam . grad) u + (u . grad) U_lam in the
         implicit operator of every step (same roots, different Jacobian)."""

@@ -93,6 +93,8 @@ SIGNATURES = {
     "sp_newton_hookstep": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(sp_newton_opts),
                                      C.POINTER(sp_hook_opts), C.POINTER(sp_newton_report),
                                      C.POINTER(sp_hook_report)]),
+    "sp_symmetrize": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "sp_plan_set_symmetry": (C.c_int, [C.c_void_p, C.c_int32]),
     "sp_hook_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_double,
                                C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "sp_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),

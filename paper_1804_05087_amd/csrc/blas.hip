@@ -267,6 +267,52 @@ hipError_t launch_dcgs2_update(sp_plan* p, double2* V, int j, const double* a, c
   return hipGetLastError();
 }
 
+// In-place projection onto the fields invariant under the shift-reflect group
+// {1, s1, s2, s1 s2} of plane Couette flow,
+//   s1 [u, v, w](x, y, z) = [u, v, -w](x + Lx/2, y, -z),
+//   s2 [u, v, w](x, y, z) = [-u, -v, w](-x + Lx/2, -y, z + Lz/2),
+// P = (1 + s1 + s2 + s1 s2) / 4. On coefficients of mode (m_x, m_z, n) of
+// component c, with A = a(m_x) and B = a(-m_x):
+//   s1 a(m_x) = (-1)^m_x z_c conj(B),  s2 a(m_x) = r_c (-1)^(m_x + m_z + n) B,
+//   s1 s2 a(m_x) = z_c r_c (-1)^(m_z + n) conj(A),
+// z = (1, 1, -1), r = (-1, -1, 1). One thread owns the pair (m_x, -m_x) for one
+// (c, m_z, n) and writes both; the x Nyquist column stays as it is (zero).
+__global__ void k_symmetrize(double2* __restrict__ a, int nx, int ny, int nzh) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int hx = nx / 2;
+  const int total = 3 * hx * nzh * ny;  // i = 0 .. nx/2 - 1 (partner nx - i)
+  if (t >= total) return;
+  const int n = t % ny;
+  const int j = (t / ny) % nzh;
+  const int i = (t / (ny * nzh)) % hx;
+  const int c = t / (ny * nzh * hx);
+  const int in = (nx - i) % nx;
+  const size_t ia = (((size_t)c * nx + i) * nzh + j) * ny + n;
+  const size_t ib = (((size_t)c * nx + in) * nzh + j) * ny + n;
+  const double2 A = a[ia], B = a[ib];
+  const double z = (c == 2) ? -1.0 : 1.0;
+  const double r = (c == 2) ? 1.0 : -1.0;
+  const double sx = (i & 1) ? -1.0 : 1.0;        // (-1)^m_x (the same for -m_x)
+  const double szn = ((j + n) & 1) ? -1.0 : 1.0;  // (-1)^(m_z + n)
+  // P a(m_x)
+  const double2 pa = make_double2(0.25 * (A.x + sx * z * B.x + r * sx * szn * B.x + z * r * szn * A.x),
+                                  0.25 * (A.y - sx * z * B.y + r * sx * szn * B.y - z * r * szn * A.y));
+  // P a(-m_x): the same with A and B exchanged
+  const double2 pb = make_double2(0.25 * (B.x + sx * z * A.x + r * sx * szn * A.x + z * r * szn * B.x),
+                                  0.25 * (B.y - sx * z * A.y + r * sx * szn * A.y - z * r * szn * B.y));
+  a[ia] = pa;
+  if (in != i) a[ib] = pb;
+}
+
+hipError_t launch_symmetrize(sp_plan* p, double2* a) {
+  const int total = 3 * (p->d.nx / 2) * p->d.nzh * p->d.ny;
+  SP_PROF_BEGIN(p, KID_SCALE);
+  hipLaunchKernelGGL(k_symmetrize, dim3((total + 255) / 256), dim3(256), 0, p->stream, a,
+                     p->d.nx, p->d.ny, p->d.nzh);
+  SP_PROF_END(p, KID_SCALE);
+  return hipGetLastError();
+}
+
 hipError_t launch_hermitian(sp_plan* p, double2* a) {
   const int total = 3 * p->d.nx * p->d.ny;
   SP_PROF_BEGIN(p, KID_SCALE);

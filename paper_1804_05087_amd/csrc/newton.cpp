@@ -426,6 +426,19 @@ extern "C" sp_status sp_hook_step(const double* R, int32_t ld, const double* g, 
   return SP_OK;
 }
 
+extern "C" sp_status sp_symmetrize(sp_plan* p, double* field) {
+  if (!p) return SP_ERR_INVALID;
+  if (!field) return set_error(p, SP_ERR_INVALID, "null field");
+  SP_TRY_HIP(launch_symmetrize(p, (double2*)field), "symmetrize");
+  return SP_OK;
+}
+
+extern "C" sp_status sp_plan_set_symmetry(sp_plan* p, int32_t on) {
+  if (!p) return SP_ERR_INVALID;
+  p->symmetric = (on != 0);
+  return SP_OK;
+}
+
 extern "C" sp_status sp_newton_gmres(sp_plan* p, double* u_inout, const sp_newton_opts* o,
                                      sp_newton_report* rep) {
   if (!p) return SP_ERR_INVALID;
@@ -442,8 +455,10 @@ extern "C" sp_status sp_newton_gmres(sp_plan* p, double* u_inout, const sp_newto
   sp_status result = SP_ERR_NOT_CONVERGED;
   for (int it = 0; it <= o->max_newton; ++it) {
     double rn = 0.0;
+    if (p->symmetric) SP_TRY_HIP(launch_symmetrize(p, U), "symmetrize U");
     SP_TRY(residual_into(p, U, r));
     rep->total_actions += 1;
+    if (p->symmetric) SP_TRY_HIP(launch_symmetrize(p, r), "symmetrize r");
     SP_TRY(host_norm_of(p, r, &rn));
     rep->res_norm[it] = rn;
     if (rn < o->newton_tol) {
@@ -501,10 +516,15 @@ extern "C" sp_status sp_newton_hookstep(sp_plan* p, double* u_inout, const sp_ne
   const auto t0 = std::chrono::steady_clock::now();
   sp_status result = SP_ERR_NOT_CONVERGED;
   const char* why = "Newton did not reach newton_tol";
+  if (p->symmetric) SP_TRY_HIP(launch_symmetrize(p, U), "symmetrize U");
   SP_TRY(residual_into(p, U, r));
   rep->total_actions += 1;
   for (int it = 0; it <= o->max_newton; ++it) {
     double rn = 0.0;
+    if (p->symmetric) {  // keep the state and the Krylov space in the subspace
+      SP_TRY_HIP(launch_symmetrize(p, U), "symmetrize U");
+      SP_TRY_HIP(launch_symmetrize(p, r), "symmetrize r");
+    }
     SP_TRY(host_norm_of(p, r, &rn));
     rep->res_norm[it] = rn;
     if (rn < o->newton_tol) {

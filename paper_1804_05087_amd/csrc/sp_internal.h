@@ -109,6 +109,7 @@ struct sp_plan {
   int base_step = 0;  // trajectory index of the cached base state
   // laminar advection in the implicit operator: per-mode dense solution
   // operators [mode][3(N-1)][3 ny] (device) and an input copy for aliasing
+  bool symmetric = false;  // Newton drivers confined to the shift-reflect subspace
   bool advect = false;
   double2* d_adv = nullptr;
   double2* adv_x = nullptr;
@@ -169,6 +170,7 @@ hipError_t launch_dcgs2_update(sp_plan* p, double2* V, int j, const double* a, c
                               double inv_gamma, const double2* w, double2* unew);
 hipError_t launch_scale(sp_plan* p, const double2* y, double s, double2* x);
 hipError_t launch_hermitian(sp_plan* p, double2* a);
+hipError_t launch_symmetrize(sp_plan* p, double2* a);
 // element chunks of launch_multidot (1024 consecutive complex entries each); the
 // partial buffer passed to it holds nvec * multidot_blocks(p) doubles
 int multidot_blocks(const sp_plan* p);
