@@ -714,12 +714,14 @@ def main():
             energy=args.newton_energy)).to(dev)
         lam = torch.from_numpy(synth.laminar_field(w["nx"], w["ny"], w["nz"])).to(dev)
         finals = {}
-        for name, prec in (("fp64", SP_FP64), ("mixed", SP_MIXED)):
+        for name, prec, kf32 in (("fp64", SP_FP64, False), ("mixed", SP_MIXED, False),
+                                 ("mixed_krylov_fp32", SP_MIXED, True)):
             P.set_precision(prec)
             uu = u0.clone()
             torch.cuda.synchronize()
             rep = P.newton_gmres(uu, max_newton=args.newton_max, max_krylov=args.newton_krylov,
-                                 gmres_rtol=args.newton_rtol, newton_tol=1e-10)
+                                 gmres_rtol=args.newton_rtol, newton_tol=1e-10,
+                                 krylov_fp32=kf32)
             finals[name] = uu
             newton[name] = {
                 "converged": rep["converged"], "seconds": round(rep["seconds"], 4),
@@ -735,6 +737,8 @@ def main():
         newton["start"] = {"energy": args.newton_energy, "seed": 0, "max_krylov": args.newton_krylov,
                            "gmres_rtol": args.newton_rtol}
         newton["mixed_vs_fp64_final_L2"] = P.norm((finals["mixed"] - finals["fp64"]).contiguous())
+        newton["mixed_krylov_fp32_vs_fp64_final_L2"] = P.norm(
+            (finals["mixed_krylov_fp32"] - finals["fp64"]).contiguous())
         P.set_precision(SP_FP64)
         # the same solve with the laminar advection in the implicit operator
         # (Sec. 6's proposed remedy; same roots, fewer Krylov iterations)

@@ -194,6 +194,12 @@ typedef struct {
   double newton_tol;    /* stop Newton when the L2 norm of r < newton_tol        */
   int32_t jvp_mode;     /* 0: exact JVP; 1: finite difference [G(U+eps u)-G(U)]/eps */
   double fd_eps;        /* relative step of jvp_mode 1 (eps = fd_eps ||U||/||u||)  */
+  int32_t krylov_fp32;  /* 0: Krylov basis stored in FP64; 1: stored in FP32,
+                           halving the orthogonalisation's memory traffic (the
+                           dot products, GMRES scalars, residual and Newton
+                           update stay FP64; the basis vectors and the GMRES
+                           residual estimate are then accurate to about 1e-7
+                           relative, so gmres_rtol should be >= 1e-6)        */
 } sp_newton_opts;
 
 typedef struct {

@@ -240,10 +240,11 @@ class Plan:
 
     def newton_gmres(self, u, max_newton: int = 5, max_krylov: int = 40,
                      gmres_rtol: float = 1e-4, newton_tol: float = 1e-10, jvp_mode: int = 0,
-                     fd_eps: float = 1e-7):
-        """Newton-GMRES in place on u; returns the report as a dict."""
+                     fd_eps: float = 1e-7, krylov_fp32: bool = False):
+        """Newton-GMRES in place on u; returns the report as a dict.
+        krylov_fp32 stores the Krylov basis in FP32."""
         opts = _lib.sp_newton_opts(max_newton, max_krylov, gmres_rtol, newton_tol, jvp_mode,
-                                   fd_eps)
+                                   fd_eps, int(krylov_fp32))
         rep = _lib.sp_newton_report()
         st = self.lib.sp_newton_gmres(self.h, self._field(u, "u"), C.byref(opts), C.byref(rep))
         if st not in (0, _lib.SP_ERR_NOT_CONVERGED):
@@ -265,12 +266,12 @@ class Plan:
                         gmres_rtol: float = 1e-4, newton_tol: float = 1e-10,
                         jvp_mode: int = 0, fd_eps: float = 1e-7, max_trials: int = 10,
                         delta_init: float = 0.0, delta_min: float = 1e-12,
-                        delta_max: float = 1e300):
+                        delta_max: float = 1e300, krylov_fp32: bool = False):
         """Trust-region Newton-GMRES (hookstep) in place on u; returns the
         report of newton_gmres plus the per-step trials, delta, mu, step_norm
         and rho of the accepted steps."""
         opts = _lib.sp_newton_opts(max_newton, max_krylov, gmres_rtol, newton_tol, jvp_mode,
-                                   fd_eps)
+                                   fd_eps, int(krylov_fp32))
         hook = _lib.sp_hook_opts(max_trials, delta_init, delta_min, delta_max)
         rep = _lib.sp_newton_report()
         hrep = _lib.sp_hook_report()

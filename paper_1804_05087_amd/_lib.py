@@ -35,6 +35,7 @@ class sp_newton_opts(C.Structure):
         ("max_newton", C.c_int32), ("max_krylov", C.c_int32),
         ("gmres_rtol", C.c_double), ("newton_tol", C.c_double),
         ("jvp_mode", C.c_int32), ("fd_eps", C.c_double),
+        ("krylov_fp32", C.c_int32),
     ]
 
 

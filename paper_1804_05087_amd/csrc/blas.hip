@@ -15,13 +15,31 @@ namespace sp {
 // weighted entries of the w_r in registers (weights computed once), streams
 // the vectors eight at a time, and the sums are reduced with wave shuffles
 // and LDS.
+// The Krylov basis is stored in FP64 (double2) or, to halve the traffic of the
+// orthogonalisation, in FP32 (float2); every sum is accumulated in FP64.
+__device__ inline double2 ld_basis(const double2* V, size_t i) { return V[i]; }
+__device__ inline double2 ld_basis(const float2* V, size_t i) {
+  const float2 f = V[i];
+  return make_double2(f.x, f.y);
+}
+__device__ inline double2 st_basis(double2* V, size_t i, double x, double y) {
+  V[i] = make_double2(x, y);
+  return make_double2(x, y);
+}
+// returns the stored (rounded) value
+__device__ inline double2 st_basis(float2* V, size_t i, double x, double y) {
+  const float2 f = make_float2((float)x, (float)y);
+  V[i] = f;
+  return make_double2(f.x, f.y);
+}
+
 constexpr int kDotGroup = 8;
 constexpr int kDotEPT = 4;
 constexpr int kDotVecs = 32;
 
-template <int NR>
+template <int NR, typename T>
 __global__ void __launch_bounds__(256)
-    k_multidot(const double2* __restrict__ V, int nvec, const double2* __restrict__ w0,
+    k_multidot(const T* __restrict__ V, int nvec, const double2* __restrict__ w0,
                const double2* __restrict__ w1, double* __restrict__ partial, int n, int nx,
                int ny, int nzh) {
   __shared__ double red[4][kDotGroup * NR];
@@ -52,10 +70,10 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int q = 0; q < kDotGroup; ++q) {
       const int v = (v0 + q < vend) ? v0 + q : vend - 1;  // clamped; extra sums are dropped
-      const double2* Vv = V + (size_t)v * n;
+      const T* Vv = V + (size_t)v * n;
       double2 av[kDotEPT];
 #pragma unroll
-      for (int i = 0; i < kDotEPT; ++i) av[i] = Vv[tc[i]];
+      for (int i = 0; i < kDotEPT; ++i) av[i] = ld_basis(Vv, tc[i]);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         double s = 0.0;
@@ -100,8 +118,9 @@ __global__ void __launch_bounds__(256)
 
 // w = beta * w + alpha * sum_v h[v] V_v   (h in device memory). One entry per
 // thread; the vector loop is unrolled by eight so eight loads are in flight.
+template <typename T>
 __global__ void __launch_bounds__(256)
-    k_multiaxpy(const double2* __restrict__ V, int nvec, const double* __restrict__ h,
+    k_multiaxpy(const T* __restrict__ V, int nvec, const double* __restrict__ h,
                 double alpha, double beta, double2* __restrict__ w, int n) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= n) return;
@@ -110,7 +129,7 @@ __global__ void __launch_bounds__(256)
   for (; v + 8 <= nvec; v += 8) {
     double2 a[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) a[q] = V[(size_t)(v + q) * n + t];
+    for (int q = 0; q < 8; ++q) a[q] = ld_basis(V, (size_t)(v + q) * n + t);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const double c = h[v + q];
@@ -120,7 +139,7 @@ __global__ void __launch_bounds__(256)
   }
   for (; v < nvec; ++v) {
     const double c = h[v];
-    const double2 a = V[(size_t)v * n + t];
+    const double2 a = ld_basis(V, (size_t)v * n + t);
     rx += c * a.x;
     ry += c * a.y;
   }
@@ -131,10 +150,14 @@ __global__ void __launch_bounds__(256)
 // One pass of the delayed-reorthogonalisation Arnoldi step (newton.cpp):
 //   q    = (u - sum_{i<j} a_i V_i) * inv_gamma            (written over u = V_j)
 //   unew = w * inv_gamma - sum_{i<j} c_i V_i - c_j q
-// Each V_i is read once for both sums.
+// Each V_i is read once for both sums. q and unew are stored in the basis
+// precision and c_j multiplies the stored q; u64 (FP32 basis only, else NULL)
+// receives the stored unew widened to FP64, the input of the next Jacobian
+// action, so that the action and the basis see the same vector.
+template <typename T>
 __global__ void __launch_bounds__(256)
-    k_dcgs2_update(double2* V, int j, const double* __restrict__ a, const double* __restrict__ c,
-                   double inv_gamma, const double2* __restrict__ w, double2* __restrict__ unew,
+    k_dcgs2_update(T* V, int j, const double* __restrict__ a, const double* __restrict__ c,
+                   double inv_gamma, const double2* __restrict__ w, T* unew, double2* u64,
                    int n) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= n) return;
@@ -143,7 +166,7 @@ __global__ void __launch_bounds__(256)
   for (; i + 8 <= j; i += 8) {
     double2 v[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = V[(size_t)(i + q) * n + t];
+    for (int q = 0; q < 8; ++q) v[q] = ld_basis(V, (size_t)(i + q) * n + t);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const double ai = a[i + q], ci = c[i + q];
@@ -154,18 +177,29 @@ __global__ void __launch_bounds__(256)
     }
   }
   for (; i < j; ++i) {
-    const double2 v = V[(size_t)i * n + t];
+    const double2 v = ld_basis(V, (size_t)i * n + t);
     ax += a[i] * v.x;
     ay += a[i] * v.y;
     cx += c[i] * v.x;
     cy += c[i] * v.y;
   }
-  const double2 u = V[(size_t)j * n + t];
-  const double qx = (u.x - ax) * inv_gamma, qy = (u.y - ay) * inv_gamma;
-  V[(size_t)j * n + t] = make_double2(qx, qy);
+  const double2 u = ld_basis(V, (size_t)j * n + t);
+  const double2 q = st_basis(V, (size_t)j * n + t, (u.x - ax) * inv_gamma, (u.y - ay) * inv_gamma);
   const double2 wv = w[t];
   const double cj = c[j];
-  unew[t] = make_double2(wv.x * inv_gamma - cx - cj * qx, wv.y * inv_gamma - cy - cj * qy);
+  const double2 un =
+      st_basis(unew, t, wv.x * inv_gamma - cx - cj * q.x, wv.y * inv_gamma - cy - cj * q.y);
+  if (u64) u64[t] = un;
+}
+
+// dst = (float) src, then src <- (double) dst: the first vector of an FP32
+// basis and its FP64 copy for the Jacobian action.
+__global__ void __launch_bounds__(256)
+    k_round_basis(double2* src, float2* __restrict__ dst, int n) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  const double2 v = src[t];
+  src[t] = st_basis(dst, t, v.x, v.y);
 }
 
 // x = s * y
@@ -216,54 +250,84 @@ int multidot_blocks(const sp_plan* p) {
   return (n + 256 * kDotEPT - 1) / (256 * kDotEPT);  // element chunks
 }
 
-hipError_t launch_multidot(sp_plan* p, const double2* V, int nvec, const double2* w,
-                           double* partial, double* out, int* nb_out) {
+template <typename T>
+static hipError_t multidot_impl(sp_plan* p, const T* V, int nvec, const double2* w0,
+                                const double2* w1, int nr, double* partial, double* out) {
   const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
   const int nb = multidot_blocks(p);
   SP_PROF_BEGIN(p, KID_MULTIDOT);
   const dim3 grid(nb, (nvec + kDotVecs - 1) / kDotVecs);
-  hipLaunchKernelGGL(k_multidot<1>, grid, dim3(256), 0, p->stream, V, nvec, w, w, partial, n,
-                     p->d.nx, p->d.ny, p->d.nzh);
+  if (nr == 1)
+    hipLaunchKernelGGL((k_multidot<1, T>), grid, dim3(256), 0, p->stream, V, nvec, w0, w0,
+                       partial, n, p->d.nx, p->d.ny, p->d.nzh);
+  else
+    hipLaunchKernelGGL((k_multidot<2, T>), grid, dim3(256), 0, p->stream, V, nvec, w0, w1,
+                       partial, n, p->d.nx, p->d.ny, p->d.nzh);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_rows, dim3(nvec), dim3(256), 0, p->stream, partial, nb, out);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(nr * nvec), dim3(256), 0, p->stream, partial, nb, out);
   SP_PROF_END(p, KID_MULTIDOT);
-  if (nb_out) *nb_out = nb;
   return hipGetLastError();
+}
+
+hipError_t launch_multidot(sp_plan* p, const double2* V, int nvec, const double2* w,
+                           double* partial, double* out, int* nb_out) {
+  if (nb_out) *nb_out = multidot_blocks(p);
+  return multidot_impl(p, V, nvec, w, w, 1, partial, out);
 }
 
 hipError_t launch_multidot2(sp_plan* p, const double2* V, int nvec, const double2* w0,
                             const double2* w1, double* partial, double* out) {
-  const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
-  const int nb = multidot_blocks(p);
-  SP_PROF_BEGIN(p, KID_MULTIDOT);
-  const dim3 grid(nb, (nvec + kDotVecs - 1) / kDotVecs);
-  hipLaunchKernelGGL(k_multidot<2>, grid, dim3(256), 0, p->stream, V, nvec, w0, w1, partial, n,
-                     p->d.nx, p->d.ny, p->d.nzh);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_rows, dim3(2 * nvec), dim3(256), 0, p->stream, partial, nb, out);
-  SP_PROF_END(p, KID_MULTIDOT);
-  return hipGetLastError();
+  return multidot_impl(p, V, nvec, w0, w1, 2, partial, out);
+}
+hipError_t launch_multidot2(sp_plan* p, const float2* V, int nvec, const double2* w0,
+                            const double2* w1, double* partial, double* out) {
+  return multidot_impl(p, V, nvec, w0, w1, 2, partial, out);
 }
 
+template <typename T>
+static hipError_t multiaxpy_impl(sp_plan* p, const T* V, int nvec, const double* h, double alpha,
+                                 double beta, double2* w) {
+  const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
+  SP_PROF_BEGIN(p, KID_MULTIAXPY);
+  hipLaunchKernelGGL(k_multiaxpy<T>, dim3((n + 255) / 256), dim3(256), 0, p->stream, V, nvec, h,
+                     alpha, beta, w, n);
+  SP_PROF_END(p, KID_MULTIAXPY);
+  return hipGetLastError();
+}
 hipError_t launch_multiaxpy(sp_plan* p, const double2* V, int nvec, const double* h, double alpha,
                             double beta, double2* w) {
+  return multiaxpy_impl(p, V, nvec, h, alpha, beta, w);
+}
+hipError_t launch_multiaxpy(sp_plan* p, const float2* V, int nvec, const double* h, double alpha,
+                            double beta, double2* w) {
+  return multiaxpy_impl(p, V, nvec, h, alpha, beta, w);
+}
+
+template <typename T>
+static hipError_t dcgs2_impl(sp_plan* p, T* V, int j, const double* a, const double* c,
+                             double inv_gamma, const double2* w, T* unew, double2* u64) {
   const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
   SP_PROF_BEGIN(p, KID_MULTIAXPY);
-  hipLaunchKernelGGL(k_multiaxpy, dim3((n + 255) / 256), dim3(256), 0, p->stream, V, nvec, h, alpha,
-                     beta, w, n);
+  hipLaunchKernelGGL(k_dcgs2_update<T>, dim3((n + 255) / 256), dim3(256), 0, p->stream, V, j, a,
+                     c, inv_gamma, w, unew, u64, n);
   SP_PROF_END(p, KID_MULTIAXPY);
   return hipGetLastError();
 }
-
 hipError_t launch_dcgs2_update(sp_plan* p, double2* V, int j, const double* a, const double* c,
                               double inv_gamma, const double2* w, double2* unew) {
+  return dcgs2_impl(p, V, j, a, c, inv_gamma, w, unew, (double2*)nullptr);
+}
+hipError_t launch_dcgs2_update(sp_plan* p, float2* V, int j, const double* a, const double* c,
+                              double inv_gamma, const double2* w, float2* unew, double2* u64) {
+  return dcgs2_impl(p, V, j, a, c, inv_gamma, w, unew, u64);
+}
+
+hipError_t launch_round_basis(sp_plan* p, double2* src, float2* dst) {
   const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
-  SP_PROF_BEGIN(p, KID_MULTIAXPY);
-  hipLaunchKernelGGL(k_dcgs2_update, dim3((n + 255) / 256), dim3(256), 0, p->stream, V, j, a, c,
-                     inv_gamma, w, unew, n);
-  SP_PROF_END(p, KID_MULTIAXPY);
+  SP_PROF_BEGIN(p, KID_SCALE);
+  hipLaunchKernelGGL(k_round_basis, dim3((n + 255) / 256), dim3(256), 0, p->stream, src, dst, n);
+  SP_PROF_END(p, KID_SCALE);
   return hipGetLastError();
 }
 

@@ -2,8 +2,9 @@
 //
 // Newton: U <- U - du with J_r(U) du = r(U), r = (Phi_dt(U) - U)/dt.
 // GMRES: unrestarted, x0 = 0, Givens rotations and the least-squares solve on
-// the host. The residual, its norm and the orthogonalisation are FP64; the
-// Jacobian actions use the plan's precision.
+// the host. The residual, its norm, the GMRES scalars and every sum of the
+// orthogonalisation are FP64; the Jacobian actions use the plan's precision
+// and the basis is stored in FP64 or (krylov_fp32) FP32.
 //
 // Arnoldi orthogonalisation: classical Gram-Schmidt with the second
 // (re-orthogonalising) pass delayed by one iteration, so every iteration reads
@@ -54,6 +55,7 @@ size_t ws_bytes_for(const sp_plan* p, int K) {
   b += align256((size_t)(K + 1) * canon_bytes(p));         // Krylov basis
   b += align256(canon_bytes(p));                           // w
   b += align256(canon_bytes(p));                           // scratch field
+  b += align256(canon_bytes(p));                           // FP64 copy of u_j (FP32 basis)
   b += align256((size_t)2 * (K + 1) * multidot_blocks(p) * sizeof(double));  // partials
   b += 3 * align256((size_t)2 * (K + 2) * sizeof(double));  // dots, a|c, y
   return b;
@@ -63,6 +65,7 @@ struct Workspace {
   double2* V;
   double2* w;
   double2* s;
+  double2* u;
   double* partial;
   double* h1;
   double* h2;
@@ -77,6 +80,8 @@ Workspace carve(sp_plan* p, int K) {
   W.w = (double2*)c;
   c += align256(canon_bytes(p));
   W.s = (double2*)c;
+  c += align256(canon_bytes(p));
+  W.u = (double2*)c;
   c += align256(canon_bytes(p));
   W.partial = (double*)c;
   c += align256((size_t)2 * (K + 1) * multidot_blocks(p) * sizeof(double));
@@ -131,6 +136,8 @@ sp_status check_newton_opts(sp_plan* p, const sp_newton_opts* o) {
     return set_error(p, SP_ERR_INVALID, "tolerances must be >= 0");
   if (o->jvp_mode != 0 && o->jvp_mode != 1) return set_error(p, SP_ERR_INVALID, "bad jvp_mode");
   if (o->jvp_mode == 1 && !(o->fd_eps > 0)) return set_error(p, SP_ERR_INVALID, "fd_eps must be > 0");
+  if (o->krylov_fp32 != 0 && o->krylov_fp32 != 1)
+    return set_error(p, SP_ERR_INVALID, "krylov_fp32 must be 0 or 1");
   return SP_OK;
 }
 
@@ -167,10 +174,15 @@ struct Gmres {
   std::vector<double> H, R, cs, sn, g, hprev, a, b, Ha, cvec;
   int kd = 0;
   double beta = 0.0, relres = 1.0;
+  // FP32 basis: slot j of Vf holds q_j (u_j while iteration j runs); W.u holds
+  // u_j widened to FP64 for the Jacobian action
+  const bool f32;
+  float2* Vf;
 
   Gmres(sp_plan* p_, const sp_newton_opts* o_)
       : p(p_), o(o_), K(o_->max_krylov), W(carve(p_, o_->max_krylov)),
         canon(canon_bytes(p_)), nc(canon_bytes(p_) / sizeof(double2)),
+        f32(o_->krylov_fp32 != 0), Vf((float2*)W.V),
         H((size_t)(K + 1) * K), R((size_t)(K + 1) * K), cs(K), sn(K), g(K + 1), hprev(K + 1),
         a(K + 1), b(K + 1), Ha(K + 1), cvec(K + 1) {}
   ~Gmres() {
@@ -191,8 +203,14 @@ struct Gmres {
     double* d_dots = W.h1;             // 2 (K + 2) doubles
     double* d_ac = W.h2;               // 2 (K + 2) doubles
     // u_0 = r (unnormalised; gamma_0 = ||r|| comes out of the first reduction)
-    SP_TRY_HIP(hipMemcpyAsync(W.V, r, canon, hipMemcpyDeviceToDevice, p->stream), "copy r");
-    SP_TRY_HIP(launch_hermitian(p, W.V), "hermitian");
+    if (f32) {
+      SP_TRY_HIP(hipMemcpyAsync(W.u, r, canon, hipMemcpyDeviceToDevice, p->stream), "copy r");
+      SP_TRY_HIP(launch_hermitian(p, W.u), "hermitian");
+      SP_TRY_HIP(launch_round_basis(p, W.u, Vf), "round r");
+    } else {
+      SP_TRY_HIP(hipMemcpyAsync(W.V, r, canon, hipMemcpyDeviceToDevice, p->stream), "copy r");
+      SP_TRY_HIP(launch_hermitian(p, W.V), "hermitian");
+    }
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(R.begin(), R.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
@@ -200,7 +218,7 @@ struct Gmres {
     kd = 0;
     relres = 1.0;
     for (int j = 0; j <= K; ++j) {
-      double2* uj = W.V + (size_t)j * nc;
+      double2* uj = f32 ? W.u : W.V + (size_t)j * nc;
       const bool last = (j == K);  // only completes column K-1: no new direction
       if (!last) {
         if (o->jvp_mode == 0) {
@@ -219,8 +237,12 @@ struct Gmres {
         SP_TRY_HIP(launch_hermitian(p, W.w), "hermitian");
       }
       // dots of q_0..q_{j-1} and u_j with u_j and with w
-      SP_TRY_HIP(launch_multidot2(p, W.V, j + 1, uj, last ? uj : W.w, W.partial, d_dots),
-                 "multidot");
+      if (f32)
+        SP_TRY_HIP(launch_multidot2(p, Vf, j + 1, uj, last ? uj : W.w, W.partial, d_dots),
+                   "multidot");
+      else
+        SP_TRY_HIP(launch_multidot2(p, W.V, j + 1, uj, last ? uj : W.w, W.partial, d_dots),
+                   "multidot");
       SP_TRY_HIP(hipMemcpyAsync(hdots, d_dots, 2 * (j + 1) * sizeof(double),
                                 hipMemcpyDeviceToHost, p->stream),
                  "copy dots");
@@ -282,8 +304,13 @@ struct Gmres {
       SP_TRY_HIP(hipMemcpyAsync(d_ac, hac, 2 * (K + 2) * sizeof(double), hipMemcpyHostToDevice,
                                 p->stream),
                  "upload a, c");
-      SP_TRY_HIP(launch_dcgs2_update(p, W.V, j, d_ac, d_ac + (K + 2), ig, W.w, uj + nc),
-                 "dcgs2 update");
+      if (f32)
+        SP_TRY_HIP(launch_dcgs2_update(p, Vf, j, d_ac, d_ac + (K + 2), ig, W.w,
+                                       Vf + (size_t)(j + 1) * nc, W.u),
+                   "dcgs2 update");
+      else
+        SP_TRY_HIP(launch_dcgs2_update(p, W.V, j, d_ac, d_ac + (K + 2), ig, W.w, uj + nc),
+                   "dcgs2 update");
     }
     return SP_OK;
   }
@@ -301,7 +328,10 @@ struct Gmres {
   sp_status apply(const double* y, double2* target) {
     SP_TRY_HIP(hipMemcpyAsync(W.y, y, kd * sizeof(double), hipMemcpyHostToDevice, p->stream),
                "upload y");
-    SP_TRY_HIP(launch_multiaxpy(p, W.V, kd, W.y, -1.0, 1.0, target), "update");
+    if (f32)
+      SP_TRY_HIP(launch_multiaxpy(p, Vf, kd, W.y, -1.0, 1.0, target), "update");
+    else
+      SP_TRY_HIP(launch_multiaxpy(p, W.V, kd, W.y, -1.0, 1.0, target), "update");
     return SP_OK;
   }
 };

@@ -168,6 +168,16 @@ hipError_t launch_multiaxpy(sp_plan* p, const double2* V, int nvec, const double
 // V_j <- (V_j - sum_{i<j} a_i V_i) inv_gamma ; unew <- w inv_gamma - sum_{i<j} c_i V_i - c_j V_j
 hipError_t launch_dcgs2_update(sp_plan* p, double2* V, int j, const double* a, const double* c,
                               double inv_gamma, const double2* w, double2* unew);
+// The same on an FP32 basis (sums in FP64); the update also writes the stored
+// unew widened to FP64 into u64.
+hipError_t launch_multidot2(sp_plan* p, const float2* V, int nvec, const double2* w0,
+                            const double2* w1, double* partial, double* out);
+hipError_t launch_multiaxpy(sp_plan* p, const float2* V, int nvec, const double* h, double alpha,
+                            double beta, double2* w);
+hipError_t launch_dcgs2_update(sp_plan* p, float2* V, int j, const double* a, const double* c,
+                              double inv_gamma, const double2* w, float2* unew, double2* u64);
+// dst = (float) src, then src <- (double) dst
+hipError_t launch_round_basis(sp_plan* p, double2* src, float2* dst);
 hipError_t launch_scale(sp_plan* p, const double2* y, double s, double2* x);
 hipError_t launch_hermitian(sp_plan* p, double2* a);
 hipError_t launch_symmetrize(sp_plan* p, double2* a);
