@@ -168,7 +168,9 @@ sp_status sp_linearize(sp_plan* plan, const double* u);
 /* Jacobian-vector product about the cached base state: the exact
  * linearisation N_U(du) = du x Omega + U x curl(du) with homogeneous walls
  * (Sec. 2, after eq. factor2). SP_OP_PHI: J_Phi du; SP_OP_RESIDUAL:
- * (J_Phi du - du)/dt. out must not alias du. */
+ * (J_Phi du - du)/dt, written with the m_z = 0 plane exactly Hermitian (entry
+ * -m_x taken as the conjugate of entry m_x) and Nyquist entries zero, the form
+ * the packed vectors represent. out must not alias du. */
 sp_status sp_jvp_lin(sp_plan* plan, int32_t op, const double* du, double* out);
 /* sp_linearize(u) followed by sp_jvp_lin. */
 sp_status sp_jvp(sp_plan* plan, int32_t op, const double* u, const double* du, double* out);

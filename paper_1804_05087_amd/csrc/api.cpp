@@ -147,8 +147,7 @@ sp_status jvp_lin(sp_plan* p, int op, const double2* du, double2* out) {
     s = jvp_phi_step(p, du, dst);
     if (s) return s;
     if (op != SP_OP_PHI)
-      SP_TRY_HIP(launch_axpby(p, p->t2, p->d.inv_dt, du, -p->d.inv_dt, out, canon_count(p)),
-                 "axpby");
+      SP_TRY_HIP(launch_axpby_herm(p, p->t2, p->d.inv_dt, du, -p->d.inv_dt, out), "axpby");
     return SP_OK;
   }
   // chain rule along the trajectory: v_{k+1} = J_Phi(U_k) v_k
@@ -162,7 +161,7 @@ sp_status jvp_lin(sp_plan* p, int op, const double2* du, double2* out) {
     v = dst;
   }
   const double iT = p->d.inv_dt / n;
-  SP_TRY_HIP(launch_axpby(p, v, iT, du, -iT, out, canon_count(p)), "axpby");
+  SP_TRY_HIP(launch_axpby_herm(p, v, iT, du, -iT, out), "axpby");
   return SP_OK;
 }
 

@@ -33,8 +33,17 @@ __device__ inline double2 st_basis(float2* V, size_t i, double x, double y) {
   return make_double2(f.x, f.y);
 }
 
-constexpr int kDotGroup = 8;
-constexpr int kDotEPT = 4;
+// Launch shape per basis precision (measured at 48x65x48 with 24-200 vectors:
+// an FP32 basis streams fastest with four vectors per group and eight entries
+// per thread, an FP64 one with eight and four).
+template <typename T>
+struct DotShape {
+  static constexpr int group = 8, ept = 4;
+};
+template <>
+struct DotShape<float2> {
+  static constexpr int group = 4, ept = 8;
+};
 constexpr int kDotVecs = 32;
 
 template <int NR, typename T>
@@ -42,6 +51,8 @@ __global__ void __launch_bounds__(256)
     k_multidot(const T* __restrict__ V, int nvec, const double2* __restrict__ w0,
                const double2* __restrict__ w1, double* __restrict__ partial, int n, int nx,
                int ny, int nzh) {
+  constexpr int kDotGroup = DotShape<T>::group;
+  constexpr int kDotEPT = DotShape<T>::ept;
   __shared__ double red[4][kDotGroup * NR];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
@@ -245,16 +256,20 @@ static int nblocks_for(size_t n) {
   return (int)b;
 }
 
+// element chunks of the FP64 shape; the FP32 shape has fewer (ept is larger)
 int multidot_blocks(const sp_plan* p) {
   const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
-  return (n + 256 * kDotEPT - 1) / (256 * kDotEPT);  // element chunks
+  constexpr int e = DotShape<double2>::ept;
+  return (n + 256 * e - 1) / (256 * e);
 }
 
 template <typename T>
 static hipError_t multidot_impl(sp_plan* p, const T* V, int nvec, const double2* w0,
                                 const double2* w1, int nr, double* partial, double* out) {
   const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
-  const int nb = multidot_blocks(p);
+  constexpr int ept = DotShape<T>::ept;
+  static_assert(ept >= DotShape<double2>::ept, "the partial buffer holds multidot_blocks chunks");
+  const int nb = (n + 256 * ept - 1) / (256 * ept);
   SP_PROF_BEGIN(p, KID_MULTIDOT);
   const dim3 grid(nb, (nvec + kDotVecs - 1) / kDotVecs);
   if (nr == 1)
@@ -328,6 +343,45 @@ hipError_t launch_round_basis(sp_plan* p, double2* src, float2* dst) {
   SP_PROF_BEGIN(p, KID_SCALE);
   hipLaunchKernelGGL(k_round_basis, dim3((n + 255) / 256), dim3(256), 0, p->stream, src, dst, n);
   SP_PROF_END(p, KID_SCALE);
+  return hipGetLastError();
+}
+
+// out = a x + b y on a canonical field, written in the form the packed real
+// vector represents: the m_z = 0 plane exactly Hermitian (entry -m_x is the
+// conjugate of entry m_x, the (0, 0) mode real) and every Nyquist entry zero.
+// Entry -m_x of the m_z = 0 plane is computed from the inputs' entry m_x, so
+// out must not alias x or y.
+__global__ void k_axpby_herm(const double2* __restrict__ x, double a,
+                             const double2* __restrict__ y, double b, double2* __restrict__ out,
+                             int nx, int ny, int nzh) {
+  const int n_all = 3 * nx * nzh * ny;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_all; t += gridDim.x * blockDim.x) {
+    const int j = (t / ny) % nzh;
+    const int i = (t / (ny * nzh)) % nx;
+    if (i == nx / 2 || j == nzh - 1) {
+      out[t] = make_double2(0.0, 0.0);
+      continue;
+    }
+    const bool mirror = (j == 0 && i > nx / 2);
+    const int src = mirror ? t + (nx - 2 * i) * nzh * ny : t;  // entry (nx - i, 0, n)
+    const double2 X = x[src], Y = y[src];
+    double re = a * X.x + b * Y.x;
+    double im = a * X.y + b * Y.y;
+    if (j == 0 && i == 0) im = 0.0;
+    out[t] = make_double2(re, mirror ? -im : im);
+  }
+}
+
+hipError_t launch_axpby_herm(sp_plan* p, const double2* x, double a, const double2* y, double b,
+                             double2* out) {
+  const auto& d = p->d;
+  const int n = 3 * d.nx * d.nzh * d.ny;
+  int blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  SP_PROF_BEGIN(p, KID_AXPBY);
+  hipLaunchKernelGGL(k_axpby_herm, dim3(blocks), dim3(256), 0, p->stream, x, a, y, b, out, d.nx,
+                     d.ny, d.nzh);
+  SP_PROF_END(p, KID_AXPBY);
   return hipGetLastError();
 }
 

@@ -234,7 +234,8 @@ struct Gmres {
           SP_TRY_HIP(launch_axpby(p, W.w, 1.0 / eps, r, -1.0 / eps, W.w, nc), "axpby");
         }
         *actions += 1;
-        SP_TRY_HIP(launch_hermitian(p, W.w), "hermitian");
+        // the exact residual JVP already writes the Hermitian form
+        if (o->jvp_mode != 0) SP_TRY_HIP(launch_hermitian(p, W.w), "hermitian");
       }
       // dots of q_0..q_{j-1} and u_j with u_j and with w
       if (f32)

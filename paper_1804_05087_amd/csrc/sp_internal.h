@@ -151,6 +151,10 @@ hipError_t launch_stokes_solve(sp_plan* p, const double2* g, double2* out, int i
 // y-valued product fields p->nv -> Chebyshev analysis + xa * x -> solve, one kernel
 hipError_t launch_analysis_solve(sp_plan* p, const double2* x, double xa, double2* out,
                                  int inhomogeneous, bool fp32);
+// out = a x + b y with the m_z = 0 plane made exactly Hermitian and Nyquist
+// entries zero (out must not alias x or y)
+hipError_t launch_axpby_herm(sp_plan* p, const double2* x, double a, const double2* y, double b,
+                             double2* out);
 hipError_t launch_axpby(sp_plan* p, const double2* x, double a, const double2* y, double b,
                         double2* out, size_t n);
 hipError_t launch_norm_partial(sp_plan* p, const double2* a, double* partial, int* nblocks);
