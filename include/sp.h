@@ -189,6 +189,20 @@ sp_status sp_vjp(sp_plan* plan, int32_t op, const double* u, const double* w, do
 sp_status sp_pack(sp_plan* plan, const double* canonical, double* packed);
 sp_status sp_unpack(sp_plan* plan, const double* packed, double* canonical);
 
+/* Columns first .. first+count-1 of the dense Jacobian in the packed real
+ * basis, the matrix whose eigenvalues give the spectra of Sec. 5: column i is
+ * pack(J unpack(e_i)) with J the Jacobian action of sp_jvp_lin for op about
+ * the cached base state (sp_linearize first), written to J + (i - first) ld
+ * (device, float64; ld >= packed_n, the caller owns J; J may be NULL when
+ * count = 0, which does nothing). Each column is formed
+ * on the device (unit vector, unpack, Jacobian action, pack) without host
+ * synchronisation, so calls on several plans (each with its own stream)
+ * overlap. The first call allocates a packed and two canonical fields kept
+ * until sp_plan_destroy (SP_ERR_NOMEM if that fails). SP_ERR_INVALID for a bad
+ * op, a range outside [0, packed_n), ld < packed_n or no base state. */
+sp_status sp_jacobian_columns(sp_plan* plan, int32_t op, int64_t first, int64_t count, double* J,
+                              int64_t ld);
+
 typedef struct {
   int32_t max_newton;   /* Newton steps (<= 64)                                 */
   int32_t max_krylov;   /* GMRES iterations per Newton step (unrestarted)       */

@@ -199,6 +199,22 @@ class Plan:
                                     self._field(out, "out")))
         return out
 
+    def jacobian_columns(self, op: int = SP_OP_PHI, first: int = 0, count=None, out=None):
+        """Columns first .. first+count-1 of the dense Jacobian in the packed
+        real basis about the base state of linearize(), as the rows of a
+        (count, packed_n) float64 tensor (row c = column first + c), formed on
+        the device without host synchronisation."""
+        torch = _torch()
+        n = self.packed_n
+        count = n - first if count is None else count
+        if out is None:
+            out = torch.empty((count, n), dtype=torch.float64, device=self.device)
+        if (out.dtype != torch.float64 or out.dim() != 2 or tuple(out.shape) != (count, n)
+                or not out.is_contiguous() or out.device != self.device):
+            raise ValueError(f"out must be a contiguous float64 ({count}, {n}) tensor on {self.device}")
+        self._check(self.lib.sp_jacobian_columns(self.h, op, first, count, out.data_ptr(), n))
+        return out
+
     def pack(self, a, out=None):
         torch = _torch()
         out = torch.empty(self.packed_n, dtype=torch.float64, device=self.device) \

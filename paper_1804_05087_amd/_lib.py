@@ -88,6 +88,8 @@ SIGNATURES = {
     "sp_vjp_lin": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "sp_vjp": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "sp_pack": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sp_jacobian_columns": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p,
+                                      C.c_int64]),
     "sp_unpack": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "sp_newton_gmres": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(sp_newton_opts),
                                   C.POINTER(sp_newton_report)]),

@@ -307,6 +307,44 @@ extern "C" sp_status sp_unpack(sp_plan* p, const double* packed, double* canonic
   return SP_OK;
 }
 
+extern "C" sp_status sp_jacobian_columns(sp_plan* p, int32_t op, int64_t first, int64_t count,
+                                        double* J, int64_t ld) {
+  CHECK_PLAN();
+  if (count > 0) CHECK_PTR(J);
+  if (op != SP_OP_PHI && op != SP_OP_RESIDUAL) return set_error(p, SP_ERR_INVALID, "bad op");
+  const Dims& d = p->d;
+  const int64_t n = (int64_t)3 * d.ny * (d.nx - 1) * (2 * (d.nzh - 1) - 1);
+  if (first < 0 || count < 0 || first > n || count > n - first || ld < n)
+    return set_error(p, SP_ERR_INVALID, "columns out of range or ld < packed length");
+  if (!p->base_valid) return set_error(p, SP_ERR_INVALID, "no base state: call sp_linearize");
+  if (count == 0) return SP_OK;
+  if (!p->jc_e) {
+    const size_t cb = canon_count(p) * sizeof(double2);
+    if (hipMalloc((void**)&p->jc_e, (size_t)n * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&p->jc_in, cb) != hipSuccess ||
+        hipMalloc((void**)&p->jc_out, cb) != hipSuccess) {
+      (void)hipGetLastError();
+      if (p->jc_e) (void)hipFree(p->jc_e);
+      if (p->jc_in) (void)hipFree(p->jc_in);
+      if (p->jc_out) (void)hipFree(p->jc_out);
+      p->jc_e = nullptr;
+      p->jc_in = p->jc_out = nullptr;
+      return set_error(p, SP_ERR_NOMEM, "cannot allocate the Jacobian column buffers");
+    }
+    SP_TRY_HIP(launch_fill(p, p->jc_e, (size_t)n, 0.0), "zero unit vector");
+  }
+  for (int64_t c = 0; c < count; ++c) {
+    const size_t i = (size_t)(first + c);
+    SP_TRY_HIP(launch_set_entry(p, p->jc_e, i, 1.0), "unit vector");
+    SP_TRY_HIP(launch_unpack(p, p->jc_e, p->jc_in), "unpack");
+    SP_TRY_HIP(launch_set_entry(p, p->jc_e, i, 0.0), "unit vector");
+    sp_status s = jvp_lin(p, op, p->jc_in, p->jc_out);
+    if (s) return s;
+    SP_TRY_HIP(launch_pack(p, p->jc_out, J + (size_t)c * (size_t)ld), "pack");
+  }
+  return SP_OK;
+}
+
 extern "C" sp_status sp_profile_enable(sp_plan* p, int32_t on) {
   CHECK_PLAN();
   p->prof.on = (on != 0);

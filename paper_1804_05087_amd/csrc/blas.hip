@@ -422,6 +422,24 @@ __global__ void k_symmetrize(double2* __restrict__ a, int nx, int ny, int nzh) {
   if (in != i) a[ib] = pb;
 }
 
+__global__ void k_fill(double* __restrict__ a, size_t n, double v) {
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
+       t += (size_t)gridDim.x * blockDim.x)
+    a[t] = v;
+}
+
+hipError_t launch_fill(sp_plan* p, double* a, size_t n, double v) {
+  SP_PROF_BEGIN(p, KID_SCALE);
+  hipLaunchKernelGGL(k_fill, dim3(nblocks_for(n)), dim3(256), 0, p->stream, a, n, v);
+  SP_PROF_END(p, KID_SCALE);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_entry(sp_plan* p, double* a, size_t i, double v) {
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, p->stream, a + i, (size_t)1, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_symmetrize(sp_plan* p, double2* a) {
   const int total = 3 * (p->d.nx / 2) * p->d.nzh * p->d.ny;
   SP_PROF_BEGIN(p, KID_SCALE);

@@ -215,6 +215,9 @@ static void free_plan(sp_plan* p) {
   if (p->traj) (void)hipFree(p->traj);
   if (p->d_adv) (void)hipFree(p->d_adv);
   if (p->adv_x) (void)hipFree(p->adv_x);
+  if (p->jc_e) (void)hipFree(p->jc_e);
+  if (p->jc_in) (void)hipFree(p->jc_in);
+  if (p->jc_out) (void)hipFree(p->jc_out);
 }
 
 }  // namespace sp

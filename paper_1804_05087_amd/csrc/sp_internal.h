@@ -113,6 +113,10 @@ struct sp_plan {
   bool advect = false;
   double2* d_adv = nullptr;
   double2* adv_x = nullptr;
+  // dense Jacobian columns: a packed unit vector and its field in and out
+  double* jc_e = nullptr;
+  double2* jc_in = nullptr;
+  double2* jc_out = nullptr;
 
   sp::Profiler prof;
 
@@ -185,6 +189,9 @@ hipError_t launch_round_basis(sp_plan* p, double2* src, float2* dst);
 hipError_t launch_scale(sp_plan* p, const double2* y, double s, double2* x);
 hipError_t launch_hermitian(sp_plan* p, double2* a);
 hipError_t launch_symmetrize(sp_plan* p, double2* a);
+// a[i] = v for i in [0, n) (fill) or for the single index i (set)
+hipError_t launch_fill(sp_plan* p, double* a, size_t n, double v);
+hipError_t launch_set_entry(sp_plan* p, double* a, size_t i, double v);
 // element chunks of launch_multidot (1024 consecutive complex entries each); the
 // partial buffer passed to it holds nvec * multidot_blocks(p) doubles
 int multidot_blocks(const sp_plan* p);

@@ -32,22 +32,9 @@ def jacobian_dense(plan, u, op: int = SP_OP_RESIDUAL, scale_to_g: bool = True) -
     Jacobian action on the i-th unit vector. op = SP_OP_RESIDUAL gives the
     Jacobian of the plan's residual operator (times T if scale_to_g, i.e.
     the Jacobian of G = B - I); op = SP_OP_PHI gives that of one BEFE step."""
-    import torch
-    n = plan.packed_n
     plan.linearize(u)
-    e = torch.zeros(n, dtype=torch.float64, device=plan.device)
-    field = plan.empty()
-    out = plan.empty()
-    col = torch.empty(n, dtype=torch.float64, device=plan.device)
-    J = torch.empty((n, n), dtype=torch.float64, device=plan.device)
-    for i in range(n):
-        e[i] = 1.0
-        plan.unpack(e, out=field)
-        plan.jvp_lin(field, op, out=out)
-        plan.pack(out, out=col)
-        J[:, i] = col
-        e[i] = 0.0
-    J = J.cpu().numpy()
+    # rows of the device result are the columns of J
+    J = np.ascontiguousarray(plan.jacobian_columns(op).cpu().numpy().T)
     if op == SP_OP_RESIDUAL and scale_to_g:
         J *= plan.dt * getattr(plan, "nsteps", 1)
     return J

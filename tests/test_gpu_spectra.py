@@ -66,3 +66,51 @@ def test_stokes_eigenvalues_at_rest():
             err = np.min(np.abs(mu - m)) / abs(m)
             say("k2", round(k2, 3), "j", j, m, err)
             assert err < 1e-9
+
+
+@pytest.mark.parametrize("op", [SP_OP_PHI, SP_OP_RESIDUAL])
+def test_jacobian_columns_equal_single_actions(op):
+    """sp_jacobian_columns forms each column on the device from the same
+    kernels as unpack + sp_jvp_lin + pack, so a sub-range of columns equals
+    the one-at-a-time route bit for bit."""
+    import torch
+    from paper_1804_05087_amd import Plan
+    dims, re, dt = (12, 17, 12), 500.0, 1.0
+    say("jacobian columns 12x17x12 op", op)
+    P = Plan(*dims, *BOX, re, dt)
+    u = to_dev(synth.perturbation_field(*dims, *BOX, seed=2, energy=1e-2))
+    P.linearize(u)
+    n = P.packed_n
+    first, count = n // 3, 37
+    cols = P.jacobian_columns(op, first, count).cpu().numpy()
+    e = torch.zeros(n, dtype=torch.float64, device=P.device)
+    for c in range(count):
+        e.zero_()
+        e[first + c] = 1.0
+        ref = P.pack(P.jvp_lin(P.unpack(e), op)).cpu().numpy()
+        assert np.array_equal(cols[c], ref), c
+    # the last column of the basis and an empty range
+    last = P.jacobian_columns(op, n - 1, 1).cpu().numpy()
+    e.zero_()
+    e[n - 1] = 1.0
+    assert np.array_equal(last[0], P.pack(P.jvp_lin(P.unpack(e), op)).cpu().numpy())
+    assert P.jacobian_columns(op, n, 0).shape == (0, n)
+
+
+def test_jacobian_columns_rejects_bad_ranges():
+    import ctypes as C
+    import torch
+    from paper_1804_05087_amd import Plan, SPError
+    dims = (8, 9, 8)
+    P = Plan(*dims, *BOX, 400.0, 100.0)
+    n = P.packed_n
+    buf = torch.zeros((2, n), dtype=torch.float64, device=P.device)
+    with pytest.raises(SPError):  # no base state yet
+        P.jacobian_columns(SP_OP_PHI, 0, 2, out=buf)
+    P.linearize(to_dev(synth.perturbation_field(*dims, *BOX, seed=0)))
+    for first, count, ld in ((-1, 1, n), (n - 1, 2, n), (0, 1, n - 1)):
+        st = P.lib.sp_jacobian_columns(P.h, SP_OP_PHI, first, count, C.c_void_p(buf.data_ptr()), ld)
+        assert st != 0, (first, count, ld)
+    st = P.lib.sp_jacobian_columns(P.h, 7, 0, 1, C.c_void_p(buf.data_ptr()), n)
+    assert st != 0
+    assert torch.count_nonzero(buf).item() == 0
