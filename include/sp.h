@@ -112,12 +112,16 @@ sp_status sp_plan_set_steps(sp_plan* plan, int32_t nsteps);
  *   M u = -(U_lam . grad) u - (u . grad) U_lam,  U_lam = y e_x,
  * which has the same roots as the Stokes step. Per Fourier mode
  * M u = -(i k_x y u + v, i k_x y v, i k_x y w); the tau systems lose the parity
- * splitting, so the plan builds each mode's dense solution operator on the
- * host (O(modes N^3) work, threaded; seconds at 48x65x48) and keeps
+ * splitting, so the plan builds each mode's dense solution operator and keeps
  * 3 (N-1) x 3 (N+1) complex entries per mode on the device (0.74 GB at
- * 48x65x48); sp_plan_set_dt rebuilds them. The VJP is not provided for this
- * operator (SP_ERR_INVALID); sp_stokes_solve stays the Stokes solve. on = 0
- * restores the Stokes step (the operators stay allocated). Synchronises. */
+ * 48x65x48). on = 1 builds them on the device (one workgroup per mode: LU
+ * with partial pivoting and two refinement passes with double-double
+ * residuals; up to 4 GiB of temporary device memory); on = 2 builds them on
+ * the host instead (LU, long-double refinement, up to 16 threads; the
+ * reference construction, seconds at 48x65x48). sp_plan_set_dt rebuilds them
+ * the same way. The VJP is not provided for this operator (SP_ERR_INVALID);
+ * sp_stokes_solve stays the Stokes solve. on = 0 restores the Stokes step (the
+ * operators stay allocated); other values are SP_ERR_INVALID. Synchronises. */
 sp_status sp_plan_set_advection(sp_plan* plan, int32_t on);
 /* The per-mode computation of sp_plan_set_advection alone, on the host (no
  * plan, no device work): the solution operator of the advected tau system of

@@ -133,10 +133,12 @@ class Plan:
         """Confine the Newton drivers to the shift-reflect invariant subspace."""
         self._check(self.lib.sp_plan_set_symmetry(self.h, 1 if on else 0))
 
-    def set_advection(self, on: bool = True):
+    def set_advection(self, on: bool = True, host_build: bool = False):
         """Laminar advection (U_lam . grad) u + (u . grad) U_lam in the
-        implicit operator of every step (same roots, different Jacobian)."""
-        self._check(self.lib.sp_plan_set_advection(self.h, 1 if on else 0))
+        implicit operator of every step (same roots, different Jacobian).
+        The per-mode operators are built on the device, or on the host with
+        host_build (the reference construction)."""
+        self._check(self.lib.sp_plan_set_advection(self.h, (2 if host_build else 1) if on else 0))
         self.advect = bool(on)
 
     def set_steps(self, nsteps: int):

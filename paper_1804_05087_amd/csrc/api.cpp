@@ -260,6 +260,8 @@ extern "C" sp_status sp_plan_set_advection(sp_plan* p, int32_t on) {
     p->advect = false;
     return SP_OK;
   }
+  if (on != 1 && on != 2) return set_error(p, SP_ERR_INVALID, "advection must be 0, 1 or 2");
+  p->adv_host = (on == 2);
   s = build_advection(p);
   if (s) return s;
   p->advect = true;

@@ -111,6 +111,7 @@ struct sp_plan {
   // operators [mode][3(N-1)][3 ny] (device) and an input copy for aliasing
   bool symmetric = false;  // Newton drivers confined to the shift-reflect subspace
   bool advect = false;
+  bool adv_host = false;  // build the advected operators on the host (reference) or the device
   double2* d_adv = nullptr;
   double2* adv_x = nullptr;
   // dense Jacobian columns: a packed unit vector and its field in and out

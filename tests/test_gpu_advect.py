@@ -107,3 +107,38 @@ def test_invalid_arguments_are_rejected():
     for kw in (dict(max_trials=0), dict(delta_min=0.0), dict(delta_min=1.0, delta_max=0.5)):
         with pytest.raises(SPError):
             P.newton_hookstep(u.clone(), max_newton=1, max_krylov=5, **kw)
+
+
+@pytest.mark.parametrize("case", [((32, 33, 32), 400.0, 10.0), ((8, 97, 8), 1000.0, 100.0),
+                                  ((8, 129, 8), 400.0, 1.0), ((12, 21, 24), 1000.0, 1.0)])
+def test_device_build_equals_host_build(case):
+    """The advected operators built on the device (one workgroup per mode,
+    double-double refinement) against the host construction (long-double
+    refinement): both are refined to about one rounding of the exact
+    operator, so the steps and Jacobian actions they give agree to 1e-13.
+    ny = 97 and 129 have more right-hand sides (3 (N - 1) = 285, 381) than
+    the 256 threads of a workgroup."""
+    import torch
+    from paper_1804_05087_amd import Plan
+    dims, re, dt = case
+    say("advected device vs host build", dims, re, dt)
+    u = to_dev(synth.perturbation_field(*dims, *BOX, seed=2, energy=0.05))
+    du = to_dev(synth.random_admissible(*dims, *BOX, seed=3))
+    out = {}
+    for host in (False, True):
+        P = Plan(*dims, *BOX, re, dt)
+        P.set_advection(True, host_build=host)
+        out[host] = (to_np(P.befe_step(u)), to_np(P.jvp(u, du, SP_OP_RESIDUAL)))
+        torch.cuda.synchronize()
+    e_phi = rel(out[False][0], out[True][0])
+    e_jvp = rel(out[False][1], out[True][1])
+    say("phi", e_phi, "jvp", e_jvp)
+    assert e_phi < 1e-13 and e_jvp < 1e-13
+
+
+def test_advection_mode_value_rejected():
+    from paper_1804_05087_amd import Plan
+    dims = (8, 9, 8)
+    P = Plan(*dims, *BOX, 400.0, 100.0)
+    assert P.lib.sp_plan_set_advection(P.h, 3) != 0
+    assert P.lib.sp_plan_set_advection(P.h, -1) != 0
