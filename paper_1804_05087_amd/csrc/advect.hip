@@ -428,30 +428,65 @@ __device__ void adv_lu_solve_col(const double2* __restrict__ LU, const int* piv,
   }
 }
 
+// Row r of -e_c - A x_c accumulated in double-double over the non-zero
+// entries of row r only, which the tau matrix's structure fixes: in a
+// momentum row n of component comp its own block at m = n - 1, n, n + 1 and
+// m = n + 2, n + 4, ... (second derivative), the coupling entries (v and p
+// for u, the pressure gradient); all of its block in a no-slip row; u, w and
+// the odd-offset derivative of v in a continuity row. The entries come from
+// adv_entry, so A is never stored.
+__device__ double2 adv_residual_row(int N, double kx, double kz, double re, double diag, int r,
+                                    const double2* __restrict__ X, int C, int c) {
+  const int n1 = N + 1, V = n1, W = 2 * n1, P = 3 * n1, nm = 3 * (N - 1);
+  DD sr, si;
+  if (r == c) sr.hi = -1.0;
+  auto acc = [&](int q) {
+    const double2 a = adv_entry(N, kx, kz, re, diag, r, q);
+    const double2 x = X[(size_t)q * C + c];
+    sr.add_prod(-a.x, x.x);
+    sr.add_prod(a.y, x.y);
+    si.add_prod(-a.x, x.y);
+    si.add_prod(-a.y, x.x);
+  };
+  if (r < nm) {
+    const int comp = r / (N - 1), n = r - comp * (N - 1), off = comp * n1;
+    if (n >= 1) acc(off + n - 1);
+    acc(off + n);
+    acc(off + n + 1);
+    for (int m = n + 2; m <= N; m += 2) acc(off + m);
+    if (comp == 0) {
+      acc(V + n);
+      acc(P + n);
+    } else if (comp == 1) {
+      for (int m = n + 1; m <= N; m += 2) acc(P + m);
+    } else {
+      acc(P + n);
+    }
+  } else if (r < nm + 6) {
+    const int off = ((r - nm) >> 1) * n1;
+    for (int m = 0; m <= N; ++m) acc(off + m);
+  } else {
+    const int n = r - nm - 6;
+    acc(n);
+    for (int m = n + 1; m <= N; m += 2) acc(V + m);
+    acc(W + n);
+  }
+  return make_double2(sr.hi + sr.lo, si.hi + si.lo);
+}
+
 // Column c of the operator: solve A x = -e_c with the workgroup's factors,
 // refine twice with residuals accumulated in double-double, and write the
 // first R rows of x to column c of the mode's operator Sm (R x C, column-major).
-__device__ void adv_solve_refine(const double2* __restrict__ LU, const double2* __restrict__ A,
-                                 const int* piv, int n4, int C, int R, double2* __restrict__ X,
-                                 double2* __restrict__ Rw, int c, double2* __restrict__ Sm) {
+__device__ void adv_solve_refine(const double2* __restrict__ LU, const int* piv, int N, double kx,
+                                 double kz, double re, double diag, int C, int R,
+                                 double2* __restrict__ X, double2* __restrict__ Rw, int c,
+                                 double2* __restrict__ Sm) {
+  const int n4 = 4 * (N + 1);
   for (int r = 0; r < n4; ++r) X[(size_t)r * C + c] = make_double2(r == c ? -1.0 : 0.0, 0.0);
   adv_lu_solve_col(LU, piv, n4, C, X, c);
   for (int it = 0; it < 2; ++it) {
-    for (int r = 0; r < n4; ++r) {  // residual -e_c - A x_c in double-double
-      DD sr, si;
-      if (r == c) sr.hi = -1.0;
-      const double2* Ar = A + (size_t)r * n4;
-#pragma unroll 4
-      for (int q = 0; q < n4; ++q) {
-        const double2 a = Ar[q];
-        const double2 x = X[(size_t)q * C + c];
-        sr.add_prod(-a.x, x.x);
-        sr.add_prod(a.y, x.y);
-        si.add_prod(-a.x, x.y);
-        si.add_prod(-a.y, x.x);
-      }
-      Rw[(size_t)r * C + c] = make_double2(sr.hi + sr.lo, si.hi + si.lo);
-    }
+    for (int r = 0; r < n4; ++r)
+      Rw[(size_t)r * C + c] = adv_residual_row(N, kx, kz, re, diag, r, X, C, c);
     adv_lu_solve_col(LU, piv, n4, C, Rw, c);
     for (int r = 0; r < n4; ++r) {
       const double2 x = X[(size_t)r * C + c], d = Rw[(size_t)r * C + c];
@@ -469,7 +504,7 @@ constexpr int kAdvMaxN4 = 4 * 130;  // ny <= 129
 // right-hand sides (columns strided over the threads), refine twice with residuals
 // accumulated in double-double, and write the first 3 (N+1) rows of X as the
 // mode's operator in the layout of k_adv_apply. ws holds, per workgroup,
-// LU and A (n4 x n4) and X and the residual (n4 x C). status[b] = 1 if the
+// LU (n4 x n4) and X and the residual (n4 x C). status[b] = 1 if the
 // system is singular.
 __global__ void __launch_bounds__(256)
     k_adv_build(const int* __restrict__ modes, int N, int nx, int nzh, double alpha, double gamma,
@@ -487,14 +522,11 @@ __global__ void __launch_bounds__(256)
   const double kx = alpha * ((i < nx / 2) ? i : i - nx), kz = gamma * j;
   const double diag = (kx * kx + kz * kz) / re + inv_dt;
   double2* LU = ws + (size_t)blockIdx.x * ws_stride;
-  double2* A = LU + (size_t)n4 * n4;
-  double2* X = A + (size_t)n4 * n4;
+  double2* X = LU + (size_t)n4 * n4;
   double2* Rw = X + (size_t)n4 * C;
   for (int e = tid; e < n4 * n4; e += 256) {
     const int r = e / n4, c = e - r * n4;
-    const double2 v = adv_entry(N, kx, kz, re, diag, r, c);
-    A[e] = v;
-    LU[e] = v;
+    LU[e] = adv_entry(N, kx, kz, re, diag, r, c);
   }
   __syncthreads();
   bool singular = false;
@@ -565,8 +597,8 @@ __global__ void __launch_bounds__(256)
     return;
   }
   if (tid == 0) status[blockIdx.x] = 0;
-  for (int c = tid; c < C; c += 256) adv_solve_refine(LU, A, piv, n4, C, R, X, Rw, c,
-                                                      S + (size_t)mode * C * R);
+  for (int c = tid; c < C; c += 256)
+    adv_solve_refine(LU, piv, N, kx, kz, re, diag, C, R, X, Rw, c, S + (size_t)mode * C * R);
 }
 
 }  // namespace
@@ -601,7 +633,7 @@ static sp_status build_advection_device(sp_plan* p, const std::vector<int>& work
   s = hip_check(p, hipMemsetAsync(p->d_adv, 0, adv_bytes(p), p->stream), "clear operators");
   if (s) return s;
   if (work.empty()) return hip_check(p, hipStreamSynchronize(p->stream), "sync");
-  const size_t per_mode = (size_t)2 * n4 * n4 + (size_t)2 * n4 * C;  // double2 entries
+  const size_t per_mode = (size_t)n4 * n4 + (size_t)2 * n4 * C;  // double2 entries
   const size_t cap = ((size_t)4 << 30) / (per_mode * sizeof(double2));
   const int chunk = (int)std::max<size_t>(1, std::min<size_t>(cap, work.size()));
   double2* ws = nullptr;
