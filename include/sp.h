@@ -116,7 +116,7 @@ sp_status sp_plan_set_steps(sp_plan* plan, int32_t nsteps);
  * 3 (N-1) x 3 (N+1) complex entries per mode on the device (0.74 GB at
  * 48x65x48). on = 1 builds them on the device (one workgroup per mode: LU
  * with partial pivoting and two refinement passes with double-double
- * residuals; up to 4 GiB of temporary device memory); on = 2 builds them on
+ * residuals; up to 4 GiB of temporary device scratch); on = 2 builds them on
  * the host instead (LU, long-double refinement, up to 16 threads; the
  * reference construction, seconds at 48x65x48). sp_plan_set_dt rebuilds them
  * the same way. The VJP is not provided for this operator (SP_ERR_INVALID);

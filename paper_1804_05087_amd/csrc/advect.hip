@@ -623,7 +623,8 @@ static sp_status ensure_adv_buffers(sp_plan* p) {
 }
 
 // The operators of the modes in work built on the device (k_adv_build), in
-// chunks whose scratch stays below 4 GiB; synchronises.
+// chunks whose scratch stays below 4 GiB (freed before returning);
+// synchronises.
 static sp_status build_advection_device(sp_plan* p, const std::vector<int>& work) {
   const Dims& d = p->d;
   const int N = d.N, n4 = 4 * d.ny, C = 3 * (N - 1);
@@ -636,21 +637,17 @@ static sp_status build_advection_device(sp_plan* p, const std::vector<int>& work
   const size_t per_mode = (size_t)n4 * n4 + (size_t)2 * n4 * C;  // double2 entries
   const size_t cap = ((size_t)4 << 30) / (per_mode * sizeof(double2));
   const int chunk = (int)std::max<size_t>(1, std::min<size_t>(cap, work.size()));
-  double2* ws = nullptr;
-  int* d_modes = nullptr;
-  int* d_status = nullptr;
-  auto release = [&]() {
-    if (ws) (void)hipFree(ws);
-    if (d_modes) (void)hipFree(d_modes);
-    if (d_status) (void)hipFree(d_status);
-  };
-  if (hipMalloc((void**)&ws, (size_t)chunk * per_mode * sizeof(double2)) != hipSuccess ||
-      hipMalloc((void**)&d_modes, work.size() * sizeof(int)) != hipSuccess ||
-      hipMalloc((void**)&d_status, (size_t)chunk * sizeof(int)) != hipSuccess) {
+  // scratch for the build only: the chunk's factors and columns, then the mode
+  // list and status
+  const size_t ws_bytes = (size_t)chunk * per_mode * sizeof(double2);
+  void* scratch = nullptr;
+  if (hipMalloc(&scratch, ws_bytes + (work.size() + chunk) * sizeof(int)) != hipSuccess) {
     (void)hipGetLastError();
-    release();
     return set_error(p, SP_ERR_NOMEM, "cannot allocate the scratch of the advected build");
   }
+  double2* ws = reinterpret_cast<double2*>(scratch);
+  int* d_modes = reinterpret_cast<int*>(reinterpret_cast<char*>(scratch) + ws_bytes);
+  int* d_status = d_modes + work.size();
   s = hip_check(p, hipMemcpy(d_modes, work.data(), work.size() * sizeof(int), hipMemcpyHostToDevice),
                 "upload modes");
   std::vector<int> st(chunk);
@@ -668,7 +665,8 @@ static sp_status build_advection_device(sp_plan* p, const std::vector<int>& work
     for (int b = 0; s == SP_OK && b < cnt; ++b)
       if (st[b]) s = set_error(p, SP_ERR_INVALID, "singular advected tau system");
   }
-  release();
+  (void)hipStreamSynchronize(p->stream);  // no launch may still use the scratch
+  (void)hipFree(scratch);
   return s;
 }
 
@@ -676,7 +674,6 @@ sp_status build_advection(sp_plan* p) {
   const Dims& d = p->d;
   const int N = d.N, C = 3 * (N - 1), R = 3 * d.ny;
   const int nmodes = d.nx * d.nzh;
-  std::vector<cplx> S((size_t)nmodes * C * R, cplx(0.0, 0.0));
   std::vector<int> work;
   for (int m = 0; m < nmodes; ++m) {
     const int i = m / d.nzh, j = m - i * d.nzh;
@@ -684,6 +681,7 @@ sp_status build_advection(sp_plan* p) {
     work.push_back(m);
   }
   if (!p->adv_host) return build_advection_device(p, work);
+  std::vector<cplx> S((size_t)nmodes * C * R, cplx(0.0, 0.0));
   unsigned nt = std::thread::hardware_concurrency();
   nt = std::max(1u, std::min(nt == 0 ? 1u : nt, 16u));
   std::vector<int> ok(nt, 1);
