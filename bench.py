@@ -401,25 +401,28 @@ def spectra_report(dims=(12, 17, 12), re_find=400.0, re=500.0, seeds=(8, 1, 0, 2
     return out
 
 
-def advect_compare(seeds=range(5), dts=(10.0, 100.0), max_krylov=400, rtol=1e-3):
+def advect_compare(seeds=range(5), dts=(10.0, 100.0), max_krylov=400, rtol=1e-3,
+                   workload="couette_32x33x32_re400_dt100"):
     """The Stokes step against the step with the laminar advection in its
-    implicit operator (Sec. 6's proposed remedy) at 32x33x32, Re = 400:
+    implicit operator (Sec. 6's proposed remedy) on `workload` (32x33x32,
+    Re = 400 by default):
     GMRES iterations of the first Newton step to `rtol` (with the relative
     residual after at most `max_krylov`), and hookstep Newton solves to
     ||r|| < 1e-10 (GMRES to 1e-4), from the energy-1e-2 perturbation family;
     plus the cost of one step of each kind."""
     import torch
     from paper_1804_05087_amd import Plan, synth
-    w = WORKLOADS["couette_32x33x32_re400_dt100"]
+    w = WORKLOADS[workload]
     dev = torch.device("cuda", 0)
     dims = (w["nx"], w["ny"], w["nz"])
     box = (w["lx"], w["lz"])
     lam = torch.from_numpy(synth.laminar_field(*dims)).to(dev)
-    out = {"metric": "krylov_iterations_stokes_vs_advected", "workload": "couette_32x33x32_re400",
+    out = {"metric": "krylov_iterations_stokes_vs_advected", "workload": workload,
            "first_step_rtol": rtol, "max_krylov": max_krylov, "energy": 1e-2, "runs": {}}
     for dt in dts:
         for adv in (False, True):
             P = Plan(*dims, *box, w["re"], dt, device=dev)
+            torch.cuda.synchronize()
             t0 = time.perf_counter()
             if adv:
                 P.set_advection(True)
@@ -446,7 +449,7 @@ def advect_compare(seeds=range(5), dts=(10.0, 100.0), max_krylov=400, rtol=1e-3)
             ks = [r["K_first"] for r in rows]
             conv = [r for r in rows if r["converged"]]
             out["runs"][key] = {
-                "phi_us": round(1e6 * s / 200, 2), "build_seconds": round(build, 2),
+                "phi_us": round(1e6 * s / 200, 2), "build_seconds": round(build, 3),
                 "K_first_mean": sum(ks) / len(ks),
                 "relres_first_mean": sum(r["relres_first"] for r in rows) / len(rows),
                 "converged": len(conv),
@@ -566,6 +569,8 @@ def main():
     ap.add_argument("--spectra", action="store_true",
                     help="instead of the benchmark line, print spectra statistics of the "
                          "Stokes and time-integration Jacobians at 12x17x12")
+    ap.add_argument("--advect-workload", default="couette_32x33x32_re400_dt100",
+                    choices=sorted(WORKLOADS), help="workload of --advect-compare")
     ap.add_argument("--advect-compare", action="store_true",
                     help="instead of the benchmark line, compare Krylov counts of the Stokes "
                          "step and the step with laminar advection in its implicit operator")
@@ -588,7 +593,7 @@ def main():
         print(json.dumps(spectra_report()), flush=True)
         return
     if args.advect_compare:
-        print(json.dumps(advect_compare()), flush=True)
+        print(json.dumps(advect_compare(workload=args.advect_workload)), flush=True)
         return
     if args.symmetric_compare:
         print(json.dumps(symmetric_compare()), flush=True)
