@@ -754,6 +754,10 @@ def main():
         oa = PA.empty()
         sa, _ = time_loop(torch, lambda: PA.befe_step(u, oa), 200, 20)
         res["phi_fp64_advected_evals_per_s"] = 200 / sa
+        PA.set_precision(SP_MIXED)
+        sa, _ = time_loop(torch, lambda: PA.befe_step(u, oa), 200, 20)
+        res["phi_mixed_advected_evals_per_s"] = 200 / sa
+        PA.set_precision(SP_FP64)
         uu = u0.clone()
         torch.cuda.synchronize()
         rep = PA.newton_gmres(uu, max_newton=args.newton_max, max_krylov=args.newton_krylov,

@@ -114,7 +114,8 @@ sp_status sp_plan_set_steps(sp_plan* plan, int32_t nsteps);
  * M u = -(i k_x y u + v, i k_x y v, i k_x y w); the tau systems lose the parity
  * splitting, so the plan builds each mode's dense solution operator and keeps
  * 3 (N-1) x 3 (N+1) complex entries per mode on the device (0.74 GB at
- * 48x65x48). on = 1 builds them on the device (one workgroup per mode: LU
+ * 48x65x48), plus an FP32 copy (half that) that the mixed-precision steps and
+ * Jacobian actions read, with FP64 sums. on = 1 builds them on the device (one workgroup per mode: LU
  * with partial pivoting and two refinement passes with double-double
  * residuals; up to 4 GiB of temporary device scratch); on = 2 builds them on
  * the host instead (LU, long-double refinement, up to 16 threads; the

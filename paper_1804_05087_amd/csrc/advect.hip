@@ -261,9 +261,17 @@ namespace {
 // out_k = S~_k (g_k + i k_x Y x_k + (x_v, 0, 0)) on the used coefficients,
 // one block per mode; the mean mode and the Nyquist modes are skipped (their
 // output comes from the Stokes solve).
+__device__ inline double2 ld_op(const double2* S, size_t i) { return S[i]; }
+__device__ inline double2 ld_op(const float2* S, size_t i) {
+  const float2 f = S[i];
+  return make_double2(f.x, f.y);
+}
+
+// S~ in FP64, or its FP32 copy for the mixed-precision path (the sums stay FP64).
+template <typename TS>
 __global__ void __launch_bounds__(256)
     k_adv_apply(const double2* __restrict__ g, const double2* __restrict__ x,
-                const double2* __restrict__ S, double2* __restrict__ out, int nx, int ny,
+                const TS* __restrict__ S, double2* __restrict__ out, int nx, int ny,
                 int nzh, double alpha) {
   extern __shared__ unsigned char smem_raw[];
   double2* gl = reinterpret_cast<double2*>(smem_raw);
@@ -297,12 +305,12 @@ __global__ void __launch_bounds__(256)
     gl[t] = v;
   }
   __syncthreads();
-  const double2* Sm = S + (size_t)mode * C * R;
+  const TS* Sm = S + (size_t)mode * C * R;
   for (int r = threadIdx.x; r < R; r += blockDim.x) {
     double ar = 0.0, ai = 0.0;
 #pragma unroll 8
     for (int col = 0; col < C; ++col) {
-      const double2 s = Sm[(size_t)col * R + r];
+      const double2 s = ld_op(Sm, (size_t)col * R + r);
       const double2 b = gl[col];
       ar += s.x * b.x - s.y * b.y;
       ai += s.x * b.y + s.y * b.x;
@@ -603,12 +611,34 @@ __global__ void __launch_bounds__(256)
 
 }  // namespace
 
-// Allocates the operator and scratch fields of the advected step if needed.
+__global__ void k_narrow(const double2* __restrict__ a, float2* __restrict__ b, size_t n) {
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
+       t += (size_t)gridDim.x * blockDim.x)
+    b[t] = make_float2((float)a[t].x, (float)a[t].y);
+}
+
+// The FP32 copy of the operators used by the mixed-precision path.
+static sp_status narrow_adv(sp_plan* p) {
+  const size_t n = adv_bytes(p) / sizeof(double2);
+  hipLaunchKernelGGL(k_narrow, dim3(4096), dim3(256), 0, p->stream, p->d_adv, p->f_adv, n);
+  sp_status s = hip_check(p, hipGetLastError(), "narrow operators");
+  if (s) return s;
+  return hip_check(p, hipStreamSynchronize(p->stream), "sync");
+}
+
+// Allocates the operators (FP64 and the FP32 copy) and the scratch field of
+// the advected step if needed.
 static sp_status ensure_adv_buffers(sp_plan* p) {
   const Dims& d = p->d;
   if (!p->d_adv) {
     if (hipMalloc((void**)&p->d_adv, adv_bytes(p)) != hipSuccess) {
       p->d_adv = nullptr;
+      return set_error(p, SP_ERR_NOMEM, "cannot allocate the advected solve operators");
+    }
+  }
+  if (!p->f_adv) {
+    if (hipMalloc((void**)&p->f_adv, adv_bytes(p) / 2) != hipSuccess) {
+      p->f_adv = nullptr;
       return set_error(p, SP_ERR_NOMEM, "cannot allocate the advected solve operators");
     }
   }
@@ -667,7 +697,8 @@ static sp_status build_advection_device(sp_plan* p, const std::vector<int>& work
   }
   (void)hipStreamSynchronize(p->stream);  // no launch may still use the scratch
   (void)hipFree(scratch);
-  return s;
+  if (s) return s;
+  return narrow_adv(p);
 }
 
 sp_status build_advection(sp_plan* p) {
@@ -702,16 +733,23 @@ sp_status build_advection(sp_plan* p) {
     if (!v) return set_error(p, SP_ERR_INVALID, "singular advected tau system");
   sp_status s = ensure_adv_buffers(p);
   if (s) return s;
-  return hip_check(p, hipMemcpy(p->d_adv, S.data(), adv_bytes(p), hipMemcpyHostToDevice),
-                   "upload advected operators");
+  s = hip_check(p, hipMemcpy(p->d_adv, S.data(), adv_bytes(p), hipMemcpyHostToDevice),
+                "upload advected operators");
+  if (s) return s;
+  return narrow_adv(p);
 }
 
-hipError_t launch_adv_apply(sp_plan* p, const double2* g, const double2* x, double2* out) {
+hipError_t launch_adv_apply(sp_plan* p, const double2* g, const double2* x, double2* out,
+                            bool fp32) {
   const Dims& d = p->d;
   const size_t sh = (size_t)3 * (d.N - 1) * sizeof(double2);
   SP_PROF_BEGIN(p, KID_ADV);
-  hipLaunchKernelGGL(k_adv_apply, dim3(d.nx * d.nzh), dim3(256), sh, p->stream, g, x, p->d_adv,
-                     out, d.nx, d.ny, d.nzh, d.alpha);
+  if (fp32)
+    hipLaunchKernelGGL(k_adv_apply<float2>, dim3(d.nx * d.nzh), dim3(256), sh, p->stream, g, x,
+                       p->f_adv, out, d.nx, d.ny, d.nzh, d.alpha);
+  else
+    hipLaunchKernelGGL(k_adv_apply<double2>, dim3(d.nx * d.nzh), dim3(256), sh, p->stream, g, x,
+                       p->d_adv, out, d.nx, d.ny, d.nzh, d.alpha);
   SP_PROF_END(p, KID_ADV);
   return hipGetLastError();
 }

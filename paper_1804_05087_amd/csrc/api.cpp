@@ -56,7 +56,7 @@ sp_status befe_into(sp_plan* p, const double2* u, double2* out, bool fp32) {
   if (p->advect) {
     SP_TRY_HIP(launch_analysis_rhs(p, u, p->d.inv_dt, p->g, fp32), "analysis_rhs");
     SP_TRY_HIP(launch_stokes_solve(p, p->g, out, 1), "stokes_solve (mean mode)");
-    SP_TRY_HIP(launch_adv_apply(p, p->g, u, out), "advected solve");
+    SP_TRY_HIP(launch_adv_apply(p, p->g, u, out, fp32), "advected solve");
     return SP_OK;
   }
   SP_TRY_HIP(launch_analysis_solve(p, u, p->d.inv_dt, out, 1, fp32), "analysis+solve");
@@ -130,7 +130,7 @@ static sp_status jvp_phi_step(sp_plan* p, const double2* du, double2* out) {
   if (p->advect) {
     SP_TRY_HIP(launch_analysis_rhs(p, du, p->d.inv_dt, p->g, fp32), "analysis_rhs");
     SP_TRY_HIP(launch_stokes_solve(p, p->g, out, 0), "stokes_solve (mean mode)");
-    SP_TRY_HIP(launch_adv_apply(p, p->g, du, out), "advected solve");
+    SP_TRY_HIP(launch_adv_apply(p, p->g, du, out, fp32), "advected solve");
     return SP_OK;
   }
   SP_TRY_HIP(launch_analysis_solve(p, du, p->d.inv_dt, out, 0, fp32), "analysis+solve");

@@ -214,6 +214,7 @@ static void free_plan(sp_plan* p) {
   if (p->ws && p->ws_owned) (void)hipFree(p->ws);
   if (p->traj) (void)hipFree(p->traj);
   if (p->d_adv) (void)hipFree(p->d_adv);
+  if (p->f_adv) (void)hipFree(p->f_adv);
   if (p->adv_x) (void)hipFree(p->adv_x);
   if (p->jc_e) (void)hipFree(p->jc_e);
   if (p->jc_in) (void)hipFree(p->jc_in);

@@ -113,6 +113,7 @@ struct sp_plan {
   bool advect = false;
   bool adv_host = false;  // build the advected operators on the host (reference) or the device
   double2* d_adv = nullptr;
+  float2* f_adv = nullptr;  // FP32 copy of d_adv for the mixed-precision path
   double2* adv_x = nullptr;
   // dense Jacobian columns: a packed unit vector and its field in and out
   double* jc_e = nullptr;
@@ -204,7 +205,9 @@ sp_status residual_into(sp_plan* p, const double2* u, double2* r);
 sp_status linearize(sp_plan* p, const double2* u);
 sp_status base_at(sp_plan* p, int k);
 sp_status build_advection(sp_plan* p);
-hipError_t launch_adv_apply(sp_plan* p, const double2* g, const double2* x, double2* out);
+// fp32: use the FP32 copy of the operators (the mixed-precision path)
+hipError_t launch_adv_apply(sp_plan* p, const double2* g, const double2* x, double2* out,
+                            bool fp32);
 sp_status jvp_lin(sp_plan* p, int op, const double2* du, double2* out);
 sp_status vjp_lin(sp_plan* p, int op, const double2* w, double2* out);
 
