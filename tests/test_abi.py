@@ -54,6 +54,12 @@ def test_plan_create_validates_on_host(lib, override, status):
 def test_null_arguments(lib):
     assert lib.sp_plan_create(None, None, None) == -1
     assert lib.sp_befe_step(None, None, None) == -1
+    # every entry point that takes a plan rejects a null one before any device call
+    assert lib.sp_jacobian_columns(None, 0, 0, 1, None, 1) == -1
+    assert lib.sp_symmetrize(None, None) == -1
+    assert lib.sp_plan_set_symmetry(None, 1) == -1
+    assert lib.sp_plan_set_advection(None, 1) == -1
+    assert lib.sp_plan_set_steps(None, 2) == -1
     assert lib.sp_status_string(-5) == b"not converged"
 
 
