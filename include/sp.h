@@ -105,6 +105,22 @@ sp_status sp_plan_set_precision(sp_plan* plan, int32_t precision);
  * not provided (SP_ERR_INVALID). n in [1, 100000]; n > 1 allocates the
  * trajectory, n canonical fields (SP_ERR_NOMEM if that fails). Synchronises. */
 sp_status sp_plan_set_steps(sp_plan* plan, int32_t nsteps);
+/* Integrator of the residual operator of sp_plan_set_steps (Sec. 2: G^int
+ * allows any scheme). scheme = 0 (the default): BEFE steps of the plan's dt.
+ * scheme = 1: SBDF2 (second-order semi-implicit backward differences with the
+ * nonlinear term extrapolated as 2 N_k - N_{k-1}) with time step 3 dt / 2, so
+ * that each step is one solve of the plan's (I - dt L):
+ *   u_{k+1} = (I - dt L)^{-1} [ (4 u_k - u_{k-1}) / 3 + dt (2 N(u_k) - N(u_{k-1})) ],
+ * started with u_{-1} = u_0 = U (the first step is then a BEFE step of dt, and
+ * the equilibria stay the roots). The residual becomes (u_n - U) / T with
+ * T = n 3 dt / 2, its Jacobian actions the chain rule of these steps along the
+ * trajectory (du_{-1} = du_0 = du). SBDF2 needs FP64 actions and the Stokes
+ * implicit operator (SP_ERR_INVALID from the residual, linearisation and
+ * Jacobian calls otherwise); sp_befe_step and SP_OP_PHI actions stay one BEFE
+ * step. The first switch to 1 allocates two canonical fields and one y-valued
+ * nonlinear term (SP_ERR_NOMEM if that fails). Invalidates the base state.
+ * Synchronises. */
+sp_status sp_plan_set_scheme(sp_plan* plan, int32_t scheme);
 /* Laminar advection in the implicit operator (the remedy proposed in Sec. 6):
  * with on != 0 every BEFE step of the plan (sp_befe_step, sp_residual, the
  * Jacobian actions and the Newton drivers) becomes

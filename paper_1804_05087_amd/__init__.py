@@ -76,6 +76,7 @@ class Plan:
         self.shape = (3, nx, nz // 2 + 1, ny)
         self.packed_n = 3 * ny * (nx - 1) * (nz - 1)
         self.nsteps = 1
+        self.scheme = 0
         self._ws = None
 
     # ------------------------------------------------------------------ helpers
@@ -140,6 +141,12 @@ class Plan:
         host_build (the reference construction)."""
         self._check(self.lib.sp_plan_set_advection(self.h, (2 if host_build else 1) if on else 0))
         self.advect = bool(on)
+
+    def set_scheme(self, scheme: int):
+        """Integrator of the residual operator: 0 = BEFE steps of dt, 1 =
+        SBDF2 with implicit step dt (time step 1.5 dt); see set_steps."""
+        self._check(self.lib.sp_plan_set_scheme(self.h, int(scheme)))
+        self.scheme = int(scheme)
 
     def set_steps(self, nsteps: int):
         """Residual operator of nsteps BEFE steps of dt: 1 = Stokes operator

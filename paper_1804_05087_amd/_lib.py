@@ -71,6 +71,7 @@ SIGNATURES = {
     "sp_plan_set_dt": (C.c_int, [C.c_void_p, C.c_double]),
     "sp_plan_set_precision": (C.c_int, [C.c_void_p, C.c_int32]),
     "sp_plan_set_steps": (C.c_int, [C.c_void_p, C.c_int32]),
+    "sp_plan_set_scheme": (C.c_int, [C.c_void_p, C.c_int32]),
     "sp_plan_set_advection": (C.c_int, [C.c_void_p, C.c_int32]),
     "sp_advected_mode_operator": (C.c_int, [C.c_int32, C.c_double, C.c_double, C.c_double,
                                             C.c_double, C.c_void_p]),

@@ -65,8 +65,71 @@ sp_status befe_into(sp_plan* p, const double2* u, double2* out, bool fp32) {
 
 // r = (Phi_dt^n(u) - u) / (n dt) with n = p->nsteps (n = 1: the Stokes
 // operator); the intermediate states ping-pong between t1 and t2.
+static sp_status check_scheme(sp_plan* p) {
+  if (p->scheme == 1 && (p->precision == SP_MIXED || p->advect))
+    return set_error(p, SP_ERR_INVALID,
+                     "the SBDF2 operator needs FP64 actions and the Stokes implicit operator");
+  return SP_OK;
+}
+
+static size_t nv_count(const sp_plan* p) {
+  return (size_t)3 * p->d.ny * p->d.nzm * p->d.nx;
+}
+
+// One SBDF2 step (scheme 1) with implicit step tau = the plan's dt:
+//   out = (I - tau L)^{-1} [ (4 uk - ukm1) / 3 + tau (2 N_k - N_{k-1}) ],
+// mode 0: the step (N the nonlinear term, the walls' velocities); mode 1: its
+// linearisation about the cached base (N the linearised product, homogeneous
+// walls). N_{k-1} is carried in y-values in nv_prev; first: N_{k-1} = N_k.
+static sp_status sbdf2_step(sp_plan* p, const double2* uk, const double2* ukm1, double2* out,
+                            int mode, bool first) {
+  sp_status s = nonlinear_to_nv(p, uk, mode, false);
+  if (s) return s;
+  const size_t m = nv_count(p);
+  double2* nv = reinterpret_cast<double2*>(p->nv);
+  if (first)
+    SP_TRY_HIP(hipMemcpyAsync(p->nv_prev, nv, m * sizeof(double2), hipMemcpyDeviceToDevice,
+                              p->stream),
+               "copy N");
+  SP_TRY_HIP(launch_sbdf2_combine(p, nv, p->nv_prev, m), "combine N");
+  SP_TRY_HIP(launch_axpby(p, uk, 4.0 / 3.0, ukm1, -1.0 / 3.0, p->sb_x, canon_count(p)),
+             "combine u");
+  SP_TRY_HIP(launch_analysis_solve(p, p->sb_x, p->d.inv_dt, out, mode == 0 ? 1 : 0, false),
+             "analysis+solve");
+  return SP_OK;
+}
+
+// the one of t1, t2, sb_u that is neither a nor b
+static double2* third_buffer(sp_plan* p, const double2* a, const double2* b) {
+  double2* c[3] = {p->t1, p->t2, p->sb_u};
+  for (double2* x : c)
+    if (x != a && x != b) return x;
+  return nullptr;
+}
+
+// 1 / T of the residual operator: T = n dt (BEFE) or n 3 dt / 2 (SBDF2)
+static double inv_horizon(const sp_plan* p) {
+  return p->d.inv_dt / (p->nsteps * (p->scheme == 1 ? 1.5 : 1.0));
+}
+
 sp_status residual_into(sp_plan* p, const double2* u, double2* r) {
   const int n = p->nsteps;
+  if (p->scheme == 1) {
+    sp_status s = check_scheme(p);
+    if (s) return s;
+    const double2* prev = u;
+    const double2* cur = u;
+    for (int k = 0; k < n; ++k) {
+      double2* nxt = third_buffer(p, prev, cur);
+      s = sbdf2_step(p, cur, prev, nxt, 0, k == 0);
+      if (s) return s;
+      prev = cur;
+      cur = nxt;
+    }
+    const double iT = inv_horizon(p);
+    SP_TRY_HIP(launch_axpby(p, cur, iT, u, -iT, r, canon_count(p)), "axpby");
+    return SP_OK;
+  }
   const double2* x = u;
   for (int k = 0; k < n; ++k) {
     double2* dst = (k & 1) ? p->t2 : p->t1;
@@ -93,7 +156,9 @@ static sp_status cache_base(sp_plan* p, const double2* u) {
 sp_status linearize(sp_plan* p, const double2* u) {
   p->base_valid = false;
   p->traj_valid = false;
-  sp_status s = cache_base(p, u);
+  sp_status s = check_scheme(p);
+  if (s) return s;
+  s = cache_base(p, u);
   if (s) return s;
   p->base_valid = true;
   p->base_step = 0;
@@ -103,7 +168,11 @@ sp_status linearize(sp_plan* p, const double2* u) {
                               p->stream),
                "copy U_0");
     for (int k = 0; k + 1 < p->nsteps; ++k) {
-      s = befe_into(p, p->traj + (size_t)k * nc, p->traj + (size_t)(k + 1) * nc, false);
+      double2* cur = p->traj + (size_t)k * nc;
+      if (p->scheme == 1)
+        s = sbdf2_step(p, cur, p->traj + (size_t)(k > 0 ? k - 1 : 0) * nc, cur + nc, 0, k == 0);
+      else
+        s = befe_into(p, cur, cur + nc, false);
       if (s) return s;
     }
     p->traj_valid = true;
@@ -139,6 +208,25 @@ static sp_status jvp_phi_step(sp_plan* p, const double2* du, double2* out) {
 
 sp_status jvp_lin(sp_plan* p, int op, const double2* du, double2* out) {
   if (!p->base_valid) return set_error(p, SP_ERR_INVALID, "no base state: call sp_linearize");
+  if (op != SP_OP_PHI && p->scheme == 1) {
+    // chain rule of the SBDF2 steps along the trajectory, with du_{-1} = du_0 = du
+    sp_status s = check_scheme(p);
+    if (s) return s;
+    const double2* prev = du;
+    const double2* cur = du;
+    for (int k = 0; k < p->nsteps; ++k) {
+      s = base_at(p, k);
+      if (s) return s;
+      double2* nxt = third_buffer(p, prev, cur);
+      s = sbdf2_step(p, cur, prev, nxt, 1, k == 0);
+      if (s) return s;
+      prev = cur;
+      cur = nxt;
+    }
+    const double iT = inv_horizon(p);
+    SP_TRY_HIP(launch_axpby_herm(p, cur, iT, du, -iT, out), "axpby");
+    return SP_OK;
+  }
   const int n = (op == SP_OP_PHI) ? 1 : p->nsteps;
   if (n == 1) {
     sp_status s = base_at(p, 0);
@@ -247,6 +335,30 @@ extern "C" sp_status sp_plan_set_steps(sp_plan* p, int32_t nsteps) {
     }
   }
   p->nsteps = nsteps;
+  return SP_OK;
+}
+
+extern "C" sp_status sp_plan_set_scheme(sp_plan* p, int32_t scheme) {
+  CHECK_PLAN();
+  if (scheme != 0 && scheme != 1) return set_error(p, SP_ERR_INVALID, "scheme must be 0 or 1");
+  sp_status s = hip_check(p, hipStreamSynchronize(p->stream), "sync");
+  if (s) return s;
+  if (scheme == 1 && !p->sb_u) {
+    const size_t cb = canon_count(p) * sizeof(double2);
+    if (hipMalloc((void**)&p->sb_u, cb) != hipSuccess ||
+        hipMalloc((void**)&p->sb_x, cb) != hipSuccess ||
+        hipMalloc((void**)&p->nv_prev, nv_count(p) * sizeof(double2)) != hipSuccess) {
+      (void)hipGetLastError();
+      if (p->sb_u) (void)hipFree(p->sb_u);
+      if (p->sb_x) (void)hipFree(p->sb_x);
+      if (p->nv_prev) (void)hipFree(p->nv_prev);
+      p->sb_u = p->sb_x = p->nv_prev = nullptr;
+      return set_error(p, SP_ERR_NOMEM, "cannot allocate the SBDF2 scratch");
+    }
+  }
+  p->scheme = scheme;
+  p->base_valid = false;
+  p->traj_valid = false;
   return SP_OK;
 }
 

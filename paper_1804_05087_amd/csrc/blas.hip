@@ -435,6 +435,22 @@ hipError_t launch_fill(sp_plan* p, double* a, size_t n, double v) {
   return hipGetLastError();
 }
 
+__global__ void k_sbdf2_combine(double2* __restrict__ nv, double2* __restrict__ prev, size_t n) {
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
+       t += (size_t)gridDim.x * blockDim.x) {
+    const double2 a = nv[t], b = prev[t];
+    nv[t] = make_double2(2.0 * a.x - b.x, 2.0 * a.y - b.y);
+    prev[t] = a;
+  }
+}
+
+hipError_t launch_sbdf2_combine(sp_plan* p, double2* nv, double2* prev, size_t n) {
+  SP_PROF_BEGIN(p, KID_AXPBY);
+  hipLaunchKernelGGL(k_sbdf2_combine, dim3(nblocks_for(n)), dim3(256), 0, p->stream, nv, prev, n);
+  SP_PROF_END(p, KID_AXPBY);
+  return hipGetLastError();
+}
+
 hipError_t launch_set_entry(sp_plan* p, double* a, size_t i, double v) {
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, p->stream, a + i, (size_t)1, v);
   return hipGetLastError();

@@ -216,6 +216,9 @@ static void free_plan(sp_plan* p) {
   if (p->d_adv) (void)hipFree(p->d_adv);
   if (p->f_adv) (void)hipFree(p->f_adv);
   if (p->adv_x) (void)hipFree(p->adv_x);
+  if (p->sb_u) (void)hipFree(p->sb_u);
+  if (p->sb_x) (void)hipFree(p->sb_x);
+  if (p->nv_prev) (void)hipFree(p->nv_prev);
   if (p->jc_e) (void)hipFree(p->jc_e);
   if (p->jc_in) (void)hipFree(p->jc_in);
   if (p->jc_out) (void)hipFree(p->jc_out);

@@ -104,6 +104,12 @@ struct sp_plan {
   // > 1: time-integration operator, T = nsteps dt) and, for nsteps > 1, the
   // trajectory U_0 .. U_{nsteps-1} of the linearisation point (device)
   int nsteps = 1;
+  // integrator of the residual operator: 0 = BEFE steps of dt, 1 = SBDF2 with
+  // implicit step tau = dt (time step 3 dt / 2); scratch of the SBDF2 steps
+  int scheme = 0;
+  double2* sb_u = nullptr;
+  double2* sb_x = nullptr;
+  double2* nv_prev = nullptr;
   double2* traj = nullptr;
   bool traj_valid = false;
   int base_step = 0;  // trajectory index of the cached base state
@@ -193,6 +199,8 @@ hipError_t launch_hermitian(sp_plan* p, double2* a);
 hipError_t launch_symmetrize(sp_plan* p, double2* a);
 // a[i] = v for i in [0, n) (fill) or for the single index i (set)
 hipError_t launch_fill(sp_plan* p, double* a, size_t n, double v);
+// nv <- 2 nv - prev, prev <- nv (the SBDF2 extrapolation of the nonlinear term)
+hipError_t launch_sbdf2_combine(sp_plan* p, double2* nv, double2* prev, size_t n);
 hipError_t launch_set_entry(sp_plan* p, double* a, size_t i, double v);
 // element chunks of launch_multidot (1024 consecutive complex entries each); the
 // partial buffer passed to it holds nvec * multidot_blocks(p) doubles

@@ -36,7 +36,8 @@ def jacobian_dense(plan, u, op: int = SP_OP_RESIDUAL, scale_to_g: bool = True) -
     # rows of the device result are the columns of J
     J = np.ascontiguousarray(plan.jacobian_columns(op).cpu().numpy().T)
     if op == SP_OP_RESIDUAL and scale_to_g:
-        J *= plan.dt * getattr(plan, "nsteps", 1)
+        step = 1.5 if getattr(plan, "scheme", 0) == 1 else 1.0  # SBDF2: time step 1.5 dt
+        J *= plan.dt * getattr(plan, "nsteps", 1) * step
     return J
 
 

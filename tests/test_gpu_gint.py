@@ -67,3 +67,51 @@ def test_newton_hookstep_on_gint_matches_oracle():
         assert abs(a - b) <= 1e-8 * b
     for a, b in zip(rep["rho"], ref["rho"]):
         assert abs(a - b) <= 1e-6
+
+
+@pytest.mark.parametrize("dims,n,tau", [((8, 9, 8), 6, 0.125), ((16, 17, 16), 4, 0.2),
+                                        ((12, 21, 24), 3, 0.5)])
+def test_sbdf2_residual_and_jvp_parity(dims, n, tau):
+    """The SBDF2 integrator (scheme 1, implicit step tau = the plan's dt, time
+    step 1.5 tau) against the oracle's SBDF2 map and chain rule."""
+    from paper_1804_05087_amd import Plan
+    say("sbdf2", dims, n, tau)
+    g = Grid(*dims, *BOX)
+    B = Befe(g, 400.0, tau)
+    P = Plan(*dims, *BOX, 400.0, tau)
+    P.set_steps(n)
+    P.set_scheme(1)
+    u = synth.perturbation_field(*dims, *BOX, seed=1, energy=0.05)
+    du = synth.random_admissible(*dims, *BOX, seed=2)
+    r_ref = gint.sbdf2_residual(B, u, n)
+    r = to_np(P.residual(to_dev(u)))
+    say("residual", rel(r, r_ref))
+    assert rel(r, r_ref) < TOL
+    j_ref = gint.sbdf2_jvp(B, u, du, n)
+    j = to_np(P.jvp(to_dev(u), to_dev(du), SP_OP_RESIDUAL))
+    say("jvp", rel(j, j_ref))
+    assert rel(j, j_ref) < TOL
+    # a second action about the same base reuses the trajectory
+    j2 = to_np(P.jvp_lin(to_dev(du), SP_OP_RESIDUAL))
+    assert rel(j2, j_ref) < TOL
+    # one step of SBDF2 is a BEFE step of tau, residual scaled by 1 / 1.5
+    P.set_steps(1)
+    assert rel(to_np(P.residual(to_dev(u))), B.residual(u) / 1.5) < TOL
+    P.set_scheme(0)
+    assert rel(to_np(P.residual(to_dev(u))), B.residual(u)) < TOL
+
+
+def test_sbdf2_rejects_mixed_precision_and_bad_values():
+    from paper_1804_05087_amd import SP_MIXED, Plan
+    dims = (8, 9, 8)
+    P = Plan(*dims, *BOX, 400.0, 0.125)
+    P.set_steps(4)
+    with pytest.raises(SPError):
+        P.set_scheme(2)
+    P.set_scheme(1)
+    P.set_precision(SP_MIXED)
+    u = to_dev(synth.perturbation_field(*dims, *BOX, seed=1))
+    with pytest.raises(SPError):
+        P.residual(u)
+    with pytest.raises(SPError):
+        P.linearize(u)
