@@ -242,11 +242,13 @@ def _steps_to_reduction(hist, factor):
 
 def gint_compare(seeds=(8, 1, 0, 2, 3), re_find=400.0, re=380.0, t_stokes=100.0,
                  int_cases=((0.5, 1 / 32), (1.0, 1 / 32), (2.0, 1 / 32), (1.0, 1 / 64),
-                            (2.0, 1 / 64)),
+                            (2.0, 1 / 64), (0.5, 1 / 32, 1), (1.0, 1 / 32, 1),
+                            (2.0, 1 / 32, 1)),
                  max_krylov=1000, rtol=1e-4, max_newton=12):
     """The paper's comparison of the Stokes operator B_T - I (one BEFE step,
     T = 100) with the time-integration operator (B_dt)^{T/dt} - I (BEFE steps
-    of dt = 1/32 and 1/64) in plane Couette flow (Sec. 3.3): a non-laminar equilibrium is
+    of dt = 1/32 and 1/64, SBDF2 steps of 1/32) in plane Couette flow (Sec. 3.3): a
+    non-laminar equilibrium is
     found at Re = 400 with the Stokes operator from the perturbation family at
     32x33x32, Re is lowered to 380, and both operators' hookstep Newton solves
     start from it; the cost is counted in BEFE time steps."""
@@ -285,17 +287,22 @@ def gint_compare(seeds=(8, 1, 0, 2, 3), re_find=400.0, re=380.0, t_stokes=100.0,
         "total_krylov": rep["total_krylov"], "timesteps": _timesteps(rep, 1),
         "seconds": round(rep["seconds"], 3), "history": _history(rep, 1)}
     log("stokes", out["runs"][f"stokes_T{t_stokes:g}"])
-    for T, dt_int in int_cases:
-        PI = Plan(*dims, *box, re, dt_int, device=dev)
+    for case in int_cases:
+        T, dt_int = case[0], case[1]
+        scheme = case[2] if len(case) > 2 else 0
+        # SBDF2 (scheme 1): the plan's dt is the implicit step 2 dt_int / 3
+        PI = Plan(*dims, *box, re, dt_int * (2.0 / 3.0 if scheme else 1.0), device=dev)
         n = int(round(T / dt_int))
         PI.set_steps(n)
+        PI.set_scheme(scheme)
         uI = u_eq.clone()
         rep = PI.newton_hookstep(uI, max_newton=max_newton, max_krylov=max_krylov,
                                  gmres_rtol=rtol, newton_tol=1e-10)
-        key = f"int_T{T:g}_dt1/{round(1 / dt_int)}"
+        key = f"int{'_sbdf2' if scheme else ''}_T{T:g}_dt1/{round(1 / dt_int)}"
         finals[key] = uI
         out["runs"][key] = {
-            "nsteps": n, "dt": dt_int, "krylov": rep["krylov"],
+            "nsteps": n, "dt": dt_int, "scheme": "sbdf2" if scheme else "befe",
+            "krylov": rep["krylov"],
             "converged": rep["converged"], "newton_iters": rep["newton_iters"],
             "total_krylov": rep["total_krylov"], "timesteps": _timesteps(rep, n),
             "seconds": round(rep["seconds"], 3), "history": _history(rep, n),
@@ -461,7 +468,9 @@ def advect_compare(seeds=range(5), dts=(10.0, 100.0), max_krylov=400, rtol=1e-3,
 
 def symmetric_compare(seeds=range(10), energies=(1e-2, 5e-2), re_find=400.0, re=380.0,
                       t_stokes=100.0, int_cases=((1.0, 1 / 32), (2.0, 1 / 32), (1.0, 1 / 64),
-                                                 (2.0, 1 / 64), (1.0, 1 / 128)),
+                                                 (2.0, 1 / 64), (1.0, 1 / 128),
+                                                 (1.0, 1 / 32, 1), (2.0, 1 / 32, 1),
+                                                 (1.0, 1 / 64, 1)),
                       max_krylov=1000, rtol=1e-4):
     """The Stokes / time-integration comparison of gint_compare confined to the
     shift-reflect invariant subspace of EQ1's symmetry group (the paper's EQ1
@@ -512,21 +521,26 @@ def symmetric_compare(seeds=range(10), energies=(1e-2, 5e-2), re_find=400.0, re=
         "total_krylov": rep["total_krylov"], "timesteps": _timesteps(rep, 1),
         "seconds": round(rep["seconds"], 3), "history": _history(rep, 1)}
     log("symmetric stokes", runs[f"stokes_T{t_stokes:g}"])
-    for T, dt_int in int_cases:
-        PI = Plan(*dims, *box, re, dt_int, device=dev)
+    for case in int_cases:
+        T, dt_int = case[0], case[1]
+        scheme = case[2] if len(case) > 2 else 0
+        # SBDF2 (scheme 1): the plan's dt is the implicit step 2 dt_int / 3
+        PI = Plan(*dims, *box, re, dt_int * (2.0 / 3.0 if scheme else 1.0), device=dev)
         PI.set_symmetry(True)
         n = int(round(T / dt_int))
         PI.set_steps(n)
+        PI.set_scheme(scheme)
         uI = u_eq.clone()
         rep = PI.newton_hookstep(uI, max_newton=12, max_krylov=max_krylov, gmres_rtol=rtol,
                                  newton_tol=1e-10)
-        runs[f"int_T{T:g}_dt1/{round(1 / dt_int)}"] = {
-            "nsteps": n, "dt": dt_int, "krylov": rep["krylov"],
+        key = f"int{'_sbdf2' if scheme else ''}_T{T:g}_dt1/{round(1 / dt_int)}"
+        runs[key] = {
+            "nsteps": n, "dt": dt_int, "scheme": "sbdf2" if scheme else "befe", "krylov": rep["krylov"],
             "converged": rep["converged"], "newton_iters": rep["newton_iters"],
             "total_krylov": rep["total_krylov"], "timesteps": _timesteps(rep, n),
             "seconds": round(rep["seconds"], 3), "history": _history(rep, n),
             "dist_to_stokes_root_L2": P.norm((uI - uS).contiguous())}
-        log("symmetric int", T, dt_int, runs[f"int_T{T:g}_dt1/{round(1 / dt_int)}"])
+        log("symmetric int", T, dt_int, scheme, runs[key])
         del PI
     out["runs"] = runs
     out["root_dist_to_laminar_L2"] = P.norm((uS - lam).contiguous())
