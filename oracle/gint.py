@@ -96,15 +96,17 @@ def sbdf2_jvp(befe, u: np.ndarray, du: np.ndarray, n: int) -> np.ndarray:
 
 
 def newton_hook_gint(befe, U0_canonical: np.ndarray, n: int, tol: float, max_newton: int,
-                     kmax: int, rtol: float, **hook):
-    """Trust-region Newton-GMRES (krylov.newton_hook) on r^int, packed vectors."""
+                     kmax: int, rtol: float, sbdf2: bool = False, **hook):
+    """Trust-region Newton-GMRES (krylov.newton_hook) on r^int, packed vectors;
+    BEFE steps of befe.dt, or SBDF2 steps with implicit step befe.dt."""
     g = befe.g
+    res_f, jvp_f = (sbdf2_residual, sbdf2_jvp) if sbdf2 else (residual, jvp)
 
     def res(x):
-        return pack.pack(residual(befe, pack.unpack(x, g), n), g)
+        return pack.pack(res_f(befe, pack.unpack(x, g), n), g)
 
     def jv(x, dx):
-        return pack.pack(jvp(befe, pack.unpack(x, g), pack.unpack(dx, g), n), g)
+        return pack.pack(jvp_f(befe, pack.unpack(x, g), pack.unpack(dx, g), n), g)
 
     def norm(rx):
         return befe.norm_l2(pack.unpack(rx, g))

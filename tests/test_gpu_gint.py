@@ -47,16 +47,18 @@ def test_residual_and_jvp_parity(dims, n, dt):
     assert rel(r1, B.residual(u)) < TOL
 
 
-def test_newton_hookstep_on_gint_matches_oracle():
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_newton_hookstep_on_gint_matches_oracle(scheme):
     from paper_1804_05087_amd import Plan
     dims, n, dt = (8, 9, 8), 4, 0.25
-    say("gint newton", dims, n, dt)
+    say("gint newton", dims, n, dt, "scheme", scheme)
     g = Grid(*dims, *BOX)
     B = Befe(g, 400.0, dt)
     P = Plan(*dims, *BOX, 400.0, dt)
     P.set_steps(n)
+    P.set_scheme(scheme)
     u0 = synth.perturbation_field(*dims, *BOX, seed=0, energy=1e-2)
-    _, ref = gint.newton_hook_gint(B, u0, n, 1e-10, 3, 15, 1e-6)
+    _, ref = gint.newton_hook_gint(B, u0, n, 1e-10, 3, 15, 1e-6, sbdf2=bool(scheme))
     u = to_dev(u0)
     rep = P.newton_hookstep(u, max_newton=3, max_krylov=15, gmres_rtol=1e-6, newton_tol=1e-10)
     say("gpu", rep["res_norm"], rep["krylov"], rep["rho"])
