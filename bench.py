@@ -405,6 +405,13 @@ def spectra_report(dims=(12, 17, 12), re_find=400.0, re=500.0, seeds=(8, 1, 0, 2
         PI.set_steps(int(round(T / dt_int)))
         out["operators"][f"int_T{T:g}"] = s = one(PI, T, False)
         log("int", T, s)
+    # SBDF2 steps of dt_int (the plan's dt is the implicit step 2 dt_int / 3)
+    PS = Plan(*dims, *box, re, dt_int * 2.0 / 3.0, device=dev)
+    PS.set_scheme(1)
+    for T in int_T:
+        PS.set_steps(int(round(T / dt_int)))
+        out["operators"][f"int_sbdf2_T{T:g}"] = s = one(PS, T, False)
+        log("int sbdf2", T, s)
     return out
 
 
