@@ -114,3 +114,29 @@ def test_jacobian_columns_rejects_bad_ranges():
     st = P.lib.sp_jacobian_columns(P.h, 7, 0, 1, C.c_void_p(buf.data_ptr()), n)
     assert st != 0
     assert torch.count_nonzero(buf).item() == 0
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_jacobian_columns_of_the_multistep_operator_match_oracle(scheme):
+    """Dense-Jacobian columns of the time-integration operator (BEFE or SBDF2
+    steps, 3 of them) against the oracle's chain rule on the same unit
+    vectors, a sample of 24 columns spread over the packed basis."""
+    from oracle import gint
+    from paper_1804_05087_amd import Plan
+    dims, re, dt, n = (8, 9, 8), 400.0, 0.2, 3
+    say("multistep jacobian columns, scheme", scheme)
+    g = Grid(*dims, *BOX)
+    B = Befe(g, re, dt)
+    P = Plan(*dims, *BOX, re, dt)
+    P.set_steps(n)
+    P.set_scheme(scheme)
+    u = synth.perturbation_field(*dims, *BOX, seed=4, energy=0.05)
+    P.linearize(to_dev(u))
+    m = P.packed_n
+    jv = gint.sbdf2_jvp if scheme else gint.jvp
+    for first in np.linspace(0, m - 1, 24).astype(int):
+        col = P.jacobian_columns(SP_OP_RESIDUAL, int(first), 1).cpu().numpy()[0]
+        e = np.zeros(m)
+        e[first] = 1.0
+        ref = opack.pack(jv(B, u, opack.unpack(e, g), n), g)
+        assert rel(col, ref) < 1e-12, (first, rel(col, ref))
