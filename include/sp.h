@@ -210,6 +210,23 @@ sp_status sp_vjp(sp_plan* plan, int32_t op, const double* u, const double* w, do
 sp_status sp_pack(sp_plan* plan, const double* canonical, double* packed);
 sp_status sp_unpack(sp_plan* plan, const double* packed, double* canonical);
 
+/* Batched evaluations for throughput (independent states: seeds, sweeps,
+ * Jacobian columns): count canonical fields stored one after another in u
+ * (du) and out. sp_befe_step_batch: out_i = Phi_dt(u_i) as sp_befe_step;
+ * sp_jvp_lin_batch: out_i = the Jacobian action of sp_jvp_lin on du_i about
+ * the cached base state (SP_OP_RESIDUAL only for the one-step operator). Up to
+ * nstreams (1..8) members run concurrently, each with its own intermediates
+ * (about 10 canonical fields) and stream, allocated on first use and kept
+ * until sp_plan_destroy; the plan's stream waits for all members before the
+ * call returns its work, so results are ordered like those of single calls and
+ * equal to them bit for bit. SP_ERR_INVALID for count < 0, nstreams outside
+ * [1, 8], overlapping in and out, the advected operator, or (JVP) no base
+ * state or a multi-step residual operator. */
+sp_status sp_befe_step_batch(sp_plan* plan, int32_t count, int32_t nstreams, const double* u,
+                             double* out);
+sp_status sp_jvp_lin_batch(sp_plan* plan, int32_t op, int32_t count, int32_t nstreams,
+                           const double* du, double* out);
+
 /* Columns first .. first+count-1 of the dense Jacobian in the packed real
  * basis, the matrix whose eigenvalues give the spectra of Sec. 5: column i is
  * pack(J unpack(e_i)) with J the Jacobian action of sp_jvp_lin for op about

@@ -208,6 +208,31 @@ class Plan:
                                     self._field(out, "out")))
         return out
 
+    def _batch(self, t, name):
+        torch = _torch()
+        if (t.dtype != torch.complex128 or t.dim() != 5 or tuple(t.shape[1:]) != self.shape
+                or not t.is_contiguous() or t.device != self.device):
+            raise ValueError(f"{name} must be a contiguous complex128 (count, *{self.shape}) "
+                             f"tensor on {self.device}")
+        return C.c_void_p(t.data_ptr())
+
+    def befe_step_batch(self, u, out=None, streams: int = 4):
+        """Phi_dt of each of the count fields u[i] (a (count, *shape) tensor),
+        up to `streams` of them concurrently."""
+        torch = _torch()
+        out = torch.empty_like(u) if out is None else out
+        self._check(self.lib.sp_befe_step_batch(self.h, u.shape[0], streams,
+                                                self._batch(u, "u"), self._batch(out, "out")))
+        return out
+
+    def jvp_lin_batch(self, du, op: int = SP_OP_PHI, out=None, streams: int = 4):
+        """The Jacobian action about the base of linearize() on each du[i]."""
+        torch = _torch()
+        out = torch.empty_like(du) if out is None else out
+        self._check(self.lib.sp_jvp_lin_batch(self.h, op, du.shape[0], streams,
+                                              self._batch(du, "du"), self._batch(out, "out")))
+        return out
+
     def jacobian_columns(self, op: int = SP_OP_PHI, first: int = 0, count=None, out=None):
         """Columns first .. first+count-1 of the dense Jacobian in the packed
         real basis about the base state of linearize(), as the rows of a

@@ -91,6 +91,9 @@ SIGNATURES = {
     "sp_pack": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "sp_jacobian_columns": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p,
                                       C.c_int64]),
+    "sp_befe_step_batch": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
+    "sp_jvp_lin_batch": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                   C.c_void_p]),
     "sp_unpack": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "sp_newton_gmres": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(sp_newton_opts),
                                   C.POINTER(sp_newton_report)]),

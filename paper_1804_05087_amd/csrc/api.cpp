@@ -459,6 +459,144 @@ extern "C" sp_status sp_jacobian_columns(sp_plan* p, int32_t op, int64_t first, 
   return SP_OK;
 }
 
+// ---- batched calls ----------------------------------------------------------------
+// Member i of a batch runs the unchanged pipeline on buffer set i mod S and its
+// stream, S = nstreams: while a member's launches are issued the plan's
+// intermediate pointers and stream point at its set (kernels take pointers and
+// the stream at launch), so up to S members execute concurrently. The sets'
+// streams wait for the plan's stream before the batch, and the plan's stream
+// waits for them after it.
+static sp_status ensure_batch(sp_plan* p, int nstreams) {
+  if (!p->bstart && hipEventCreateWithFlags(&p->bstart, hipEventDisableTiming) != hipSuccess) {
+    p->bstart = nullptr;
+    return set_error(p, SP_ERR_HIP, "cannot create the batch event");
+  }
+  const Dims& d = p->d;
+  const size_t cz = sizeof(double2), canon = canon_count(p) * cz;
+  const size_t sizes[7] = {(size_t)6 * d.ny * d.nzm * d.nx * cz, (size_t)6 * d.ny * d.px * d.nzm * cz,
+                           (size_t)3 * d.ny * d.px * d.nzm * cz, (size_t)3 * d.ny * d.nzm * d.nx * cz,
+                           canon, canon, canon};
+  size_t total = 0;
+  for (size_t b : sizes) total += (b + 255) / 256 * 256;
+  while ((int)p->bsets.size() < nstreams) {
+    BatchSet b;
+    if (hipMalloc(&b.mem, total) != hipSuccess) {
+      (void)hipGetLastError();
+      return set_error(p, SP_ERR_NOMEM, "cannot allocate the intermediates of a batch member");
+    }
+    if (hipStreamCreateWithFlags(&b.s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      if (b.s) (void)hipStreamDestroy(b.s);
+      (void)hipFree(b.mem);
+      return set_error(p, SP_ERR_HIP, "cannot create the stream of a batch member");
+    }
+    void** dst[7] = {&b.yv, &b.xp, &b.np, &b.nv, (void**)&b.g, (void**)&b.t1, (void**)&b.t2};
+    size_t off = 0;
+    for (int k = 0; k < 7; ++k) {
+      *dst[k] = (char*)b.mem + off;
+      off += (sizes[k] + 255) / 256 * 256;
+    }
+    p->bsets.push_back(b);
+  }
+  return SP_OK;
+}
+
+// Points the plan at one buffer set for the launches issued in its scope.
+struct BatchView {
+  sp_plan* p;
+  void *yv, *xp, *np, *nv;
+  double2 *g, *t1, *t2;
+  hipStream_t s;
+  BatchView(sp_plan* p_, const BatchSet& b)
+      : p(p_), yv(p_->yv), xp(p_->xp), np(p_->np), nv(p_->nv), g(p_->g), t1(p_->t1), t2(p_->t2),
+        s(p_->stream) {
+    p->yv = b.yv;
+    p->xp = b.xp;
+    p->np = b.np;
+    p->nv = b.nv;
+    p->g = b.g;
+    p->t1 = b.t1;
+    p->t2 = b.t2;
+    p->stream = b.s;
+  }
+  ~BatchView() {
+    p->yv = yv;
+    p->xp = xp;
+    p->np = np;
+    p->nv = nv;
+    p->g = g;
+    p->t1 = t1;
+    p->t2 = t2;
+    p->stream = s;
+  }
+};
+
+template <typename F>
+static sp_status run_batch(sp_plan* p, int count, int nstreams, F member) {
+  if (count == 0) return SP_OK;
+  const int S = nstreams < count ? nstreams : count;
+  sp_status s = ensure_batch(p, S);
+  if (s) return s;
+  SP_TRY_HIP(hipEventRecord(p->bstart, p->stream), "record batch start");
+  for (int b = 0; b < S; ++b)
+    SP_TRY_HIP(hipStreamWaitEvent(p->bsets[b].s, p->bstart, 0), "batch wait");
+  for (int i = 0; i < count && s == SP_OK; ++i) {
+    BatchView v(p, p->bsets[i % S]);
+    s = member(i);
+  }
+  for (int b = 0; b < S; ++b) {  // join even after an error: no member is left running
+    SP_TRY_HIP(hipEventRecord(p->bsets[b].done, p->bsets[b].s), "record batch end");
+    SP_TRY_HIP(hipStreamWaitEvent(p->stream, p->bsets[b].done, 0), "batch join");
+  }
+  return s;
+}
+
+static sp_status check_batch_args(sp_plan* p, int32_t count, int32_t nstreams, const double* a,
+                                  const double* out) {
+  if (count < 0 || nstreams < 1 || nstreams > 8)
+    return set_error(p, SP_ERR_INVALID, "count must be >= 0 and nstreams in [1, 8]");
+  if (count > 0 && (!a || !out)) return set_error(p, SP_ERR_INVALID, "null pointer");
+  const size_t bytes = canon_count(p) * sizeof(double2) * (size_t)count;
+  const char *ab = (const char*)a, *ob = (const char*)out;
+  if (count > 0 && ab < ob + bytes && ob < ab + bytes)
+    return set_error(p, SP_ERR_INVALID, "out overlaps the input batch");
+  if (p->advect)
+    return set_error(p, SP_ERR_INVALID, "batched calls need the Stokes implicit operator");
+  return SP_OK;
+}
+
+extern "C" sp_status sp_befe_step_batch(sp_plan* p, int32_t count, int32_t nstreams,
+                                        const double* u, double* out) {
+  CHECK_PLAN();
+  sp_status s = check_batch_args(p, count, nstreams, u, out);
+  if (s) return s;
+  const size_t nc = canon_count(p);
+  const bool fp32 = (p->precision == SP_MIXED);
+  return run_batch(p, count, nstreams, [&](int i) {
+    return befe_into(p, (const double2*)u + i * nc, (double2*)out + i * nc, fp32);
+  });
+}
+
+extern "C" sp_status sp_jvp_lin_batch(sp_plan* p, int32_t op, int32_t count, int32_t nstreams,
+                                      const double* du, double* out) {
+  CHECK_PLAN();
+  if (op != SP_OP_PHI && op != SP_OP_RESIDUAL) return set_error(p, SP_ERR_INVALID, "bad op");
+  sp_status s = check_batch_args(p, count, nstreams, du, out);
+  if (s) return s;
+  if (!p->base_valid) return set_error(p, SP_ERR_INVALID, "no base state: call sp_linearize");
+  if (op == SP_OP_RESIDUAL && (p->nsteps > 1 || p->scheme != 0))
+    return set_error(p, SP_ERR_INVALID, "batched residual actions need the one-step operator");
+  if (p->base_step != 0) {
+    s = base_at(p, 0);
+    if (s) return s;
+  }
+  const size_t nc = canon_count(p);
+  return run_batch(p, count, nstreams, [&](int i) {
+    return jvp_lin(p, op, (const double2*)du + i * nc, (double2*)out + i * nc);
+  });
+}
+
 extern "C" sp_status sp_profile_enable(sp_plan* p, int32_t on) {
   CHECK_PLAN();
   p->prof.on = (on != 0);

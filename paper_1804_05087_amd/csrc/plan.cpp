@@ -211,6 +211,14 @@ static void free_plan(sp_plan* p) {
     if (q) (void)hipFree(q);
   if (p->h_partial) (void)hipHostFree(p->h_partial);
   p->prof.release();
+  for (auto& b : p->bsets) {
+    if (b.s) (void)hipStreamSynchronize(b.s);
+    if (b.mem) (void)hipFree(b.mem);
+    if (b.s) (void)hipStreamDestroy(b.s);
+    if (b.done) (void)hipEventDestroy(b.done);
+  }
+  p->bsets.clear();
+  if (p->bstart) (void)hipEventDestroy(p->bstart);
   if (p->ws && p->ws_owned) (void)hipFree(p->ws);
   if (p->traj) (void)hipFree(p->traj);
   if (p->d_adv) (void)hipFree(p->d_adv);

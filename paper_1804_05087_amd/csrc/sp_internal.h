@@ -49,6 +49,20 @@ struct Dims {
   double alpha, gamma, re, dt, inv_dt, wall_upper, wall_lower;
 };
 
+// Intermediates and stream of one member of a batched call (see api.cpp).
+struct BatchSet {
+  void* mem = nullptr;
+  void* yv = nullptr;
+  void* xp = nullptr;
+  void* np = nullptr;
+  void* nv = nullptr;
+  double2* g = nullptr;
+  double2* t1 = nullptr;
+  double2* t2 = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t done = nullptr;
+};
+
 }  // namespace sp
 
 struct sp_plan {
@@ -121,6 +135,9 @@ struct sp_plan {
   double2* d_adv = nullptr;
   float2* f_adv = nullptr;  // FP32 copy of d_adv for the mixed-precision path
   double2* adv_x = nullptr;
+  // batched calls: one buffer set and stream per concurrent member
+  std::vector<sp::BatchSet> bsets;
+  hipEvent_t bstart = nullptr;
   // dense Jacobian columns: a packed unit vector and its field in and out
   double* jc_e = nullptr;
   double2* jc_in = nullptr;
