@@ -234,9 +234,12 @@ sp_status sp_jvp_lin_batch(sp_plan* plan, int32_t op, int32_t count, int32_t nst
  * (device, float64; ld >= packed_n, the caller owns J; J may be NULL when
  * count = 0, which does nothing). Each column is formed
  * on the device (unit vector, unpack, Jacobian action, pack) without host
- * synchronisation, so calls on several plans (each with its own stream)
- * overlap. The first call allocates a packed and two canonical fields kept
- * until sp_plan_destroy (SP_ERR_NOMEM if that fails). SP_ERR_INVALID for a bad
+ * synchronisation. For the one-step operators (SP_OP_PHI, or SP_OP_RESIDUAL
+ * with one BEFE step, no laminar advection) and count >= 8 the columns are
+ * spread over 4 concurrent members as in sp_jvp_lin_batch, each with its own
+ * unit vector and fields; the multi-step chain forms them one after another.
+ * The plan's stream waits for all of them. Buffers are allocated on first use
+ * and kept until sp_plan_destroy (SP_ERR_NOMEM if that fails). SP_ERR_INVALID for a bad
  * op, a range outside [0, packed_n), ld < packed_n or no base state. */
 sp_status sp_jacobian_columns(sp_plan* plan, int32_t op, int64_t first, int64_t count, double* J,
                               int64_t ld);

@@ -421,44 +421,6 @@ extern "C" sp_status sp_unpack(sp_plan* p, const double* packed, double* canonic
   return SP_OK;
 }
 
-extern "C" sp_status sp_jacobian_columns(sp_plan* p, int32_t op, int64_t first, int64_t count,
-                                        double* J, int64_t ld) {
-  CHECK_PLAN();
-  if (count > 0) CHECK_PTR(J);
-  if (op != SP_OP_PHI && op != SP_OP_RESIDUAL) return set_error(p, SP_ERR_INVALID, "bad op");
-  const Dims& d = p->d;
-  const int64_t n = (int64_t)3 * d.ny * (d.nx - 1) * (2 * (d.nzh - 1) - 1);
-  if (first < 0 || count < 0 || first > n || count > n - first || ld < n)
-    return set_error(p, SP_ERR_INVALID, "columns out of range or ld < packed length");
-  if (!p->base_valid) return set_error(p, SP_ERR_INVALID, "no base state: call sp_linearize");
-  if (count == 0) return SP_OK;
-  if (!p->jc_e) {
-    const size_t cb = canon_count(p) * sizeof(double2);
-    if (hipMalloc((void**)&p->jc_e, (size_t)n * sizeof(double)) != hipSuccess ||
-        hipMalloc((void**)&p->jc_in, cb) != hipSuccess ||
-        hipMalloc((void**)&p->jc_out, cb) != hipSuccess) {
-      (void)hipGetLastError();
-      if (p->jc_e) (void)hipFree(p->jc_e);
-      if (p->jc_in) (void)hipFree(p->jc_in);
-      if (p->jc_out) (void)hipFree(p->jc_out);
-      p->jc_e = nullptr;
-      p->jc_in = p->jc_out = nullptr;
-      return set_error(p, SP_ERR_NOMEM, "cannot allocate the Jacobian column buffers");
-    }
-    SP_TRY_HIP(launch_fill(p, p->jc_e, (size_t)n, 0.0), "zero unit vector");
-  }
-  for (int64_t c = 0; c < count; ++c) {
-    const size_t i = (size_t)(first + c);
-    SP_TRY_HIP(launch_set_entry(p, p->jc_e, i, 1.0), "unit vector");
-    SP_TRY_HIP(launch_unpack(p, p->jc_e, p->jc_in), "unpack");
-    SP_TRY_HIP(launch_set_entry(p, p->jc_e, i, 0.0), "unit vector");
-    sp_status s = jvp_lin(p, op, p->jc_in, p->jc_out);
-    if (s) return s;
-    SP_TRY_HIP(launch_pack(p, p->jc_out, J + (size_t)c * (size_t)ld), "pack");
-  }
-  return SP_OK;
-}
-
 // ---- batched calls ----------------------------------------------------------------
 // Member i of a batch runs the unchanged pipeline on buffer set i mod S and its
 // stream, S = nstreams: while a member's launches are issued the plan's
@@ -550,6 +512,80 @@ static sp_status run_batch(sp_plan* p, int count, int nstreams, F member) {
     SP_TRY_HIP(hipStreamWaitEvent(p->stream, p->bsets[b].done, 0), "batch join");
   }
   return s;
+}
+
+extern "C" sp_status sp_jacobian_columns(sp_plan* p, int32_t op, int64_t first, int64_t count,
+                                        double* J, int64_t ld) {
+  CHECK_PLAN();
+  if (count > 0) CHECK_PTR(J);
+  if (op != SP_OP_PHI && op != SP_OP_RESIDUAL) return set_error(p, SP_ERR_INVALID, "bad op");
+  const Dims& d = p->d;
+  const int64_t n = (int64_t)3 * d.ny * (d.nx - 1) * (2 * (d.nzh - 1) - 1);
+  if (first < 0 || count < 0 || first > n || count > n - first || ld < n)
+    return set_error(p, SP_ERR_INVALID, "columns out of range or ld < packed length");
+  if (!p->base_valid) return set_error(p, SP_ERR_INVALID, "no base state: call sp_linearize");
+  if (count == 0) return SP_OK;
+  if (!p->jc_e) {
+    const size_t cb = canon_count(p) * sizeof(double2);
+    if (hipMalloc((void**)&p->jc_e, (size_t)n * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&p->jc_in, cb) != hipSuccess ||
+        hipMalloc((void**)&p->jc_out, cb) != hipSuccess) {
+      (void)hipGetLastError();
+      if (p->jc_e) (void)hipFree(p->jc_e);
+      if (p->jc_in) (void)hipFree(p->jc_in);
+      if (p->jc_out) (void)hipFree(p->jc_out);
+      p->jc_e = nullptr;
+      p->jc_in = p->jc_out = nullptr;
+      return set_error(p, SP_ERR_NOMEM, "cannot allocate the Jacobian column buffers");
+    }
+    SP_TRY_HIP(launch_fill(p, p->jc_e, (size_t)n, 0.0), "zero unit vector");
+  }
+  // one-step operators (whose base state the members only read) spread the
+  // columns over 4 streams with their own buffers; the multi-step chain
+  // re-caches the base per step, so it runs them one after another
+  const bool one_step = (op == SP_OP_PHI || (p->nsteps == 1 && p->scheme == 0)) && !p->advect;
+  if (one_step && count >= 8) {
+    if (p->base_step != 0) {
+      sp_status s = base_at(p, 0);
+      if (s) return s;
+    }
+    const int S = 4;
+    sp_status s = ensure_batch(p, S);
+    if (s) return s;
+    for (int b = 0; b < S; ++b) {
+      BatchSet& bs = p->bsets[b];
+      if (bs.e) continue;
+      const size_t cb = canon_count(p) * sizeof(double2);
+      if (hipMalloc((void**)&bs.e, (size_t)n * sizeof(double)) != hipSuccess ||
+          hipMalloc((void**)&bs.fin, cb) != hipSuccess ||
+          hipMalloc((void**)&bs.fout, cb) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(p, SP_ERR_NOMEM, "cannot allocate the Jacobian column buffers");
+      }
+      SP_TRY_HIP(launch_fill(p, bs.e, (size_t)n, 0.0), "zero unit vector");
+    }
+    return run_batch(p, (int)count, S, [&](int c) -> sp_status {
+      BatchSet& bs = p->bsets[c % S];
+      const size_t i = (size_t)(first + c);
+      SP_TRY_HIP(launch_set_entry(p, bs.e, i, 1.0), "unit vector");
+      SP_TRY_HIP(launch_unpack(p, bs.e, bs.fin), "unpack");
+      SP_TRY_HIP(launch_set_entry(p, bs.e, i, 0.0), "unit vector");
+      sp_status st = jvp_lin(p, op, bs.fin, bs.fout);
+      if (st) return st;
+      SP_TRY_HIP(launch_pack(p, bs.fout, J + (size_t)c * (size_t)ld), "pack");
+      return SP_OK;
+    });
+  }
+  for (int64_t c = 0; c < count; ++c) {
+    const size_t i = (size_t)(first + c);
+    SP_TRY_HIP(launch_set_entry(p, p->jc_e, i, 1.0), "unit vector");
+    SP_TRY_HIP(launch_unpack(p, p->jc_e, p->jc_in), "unpack");
+    SP_TRY_HIP(launch_set_entry(p, p->jc_e, i, 0.0), "unit vector");
+    sp_status s = jvp_lin(p, op, p->jc_in, p->jc_out);
+    if (s) return s;
+    SP_TRY_HIP(launch_pack(p, p->jc_out, J + (size_t)c * (size_t)ld), "pack");
+  }
+  return SP_OK;
 }
 
 static sp_status check_batch_args(sp_plan* p, int32_t count, int32_t nstreams, const double* a,

@@ -214,6 +214,9 @@ static void free_plan(sp_plan* p) {
   for (auto& b : p->bsets) {
     if (b.s) (void)hipStreamSynchronize(b.s);
     if (b.mem) (void)hipFree(b.mem);
+    if (b.e) (void)hipFree(b.e);
+    if (b.fin) (void)hipFree(b.fin);
+    if (b.fout) (void)hipFree(b.fout);
     if (b.s) (void)hipStreamDestroy(b.s);
     if (b.done) (void)hipEventDestroy(b.done);
   }

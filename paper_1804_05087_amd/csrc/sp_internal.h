@@ -61,6 +61,10 @@ struct BatchSet {
   double2* t2 = nullptr;
   hipStream_t s = nullptr;
   hipEvent_t done = nullptr;
+  // dense Jacobian columns: packed unit vector, its field and the action
+  double* e = nullptr;
+  double2* fin = nullptr;
+  double2* fout = nullptr;
 };
 
 }  // namespace sp
