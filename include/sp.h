@@ -215,7 +215,8 @@ sp_status sp_unpack(sp_plan* plan, const double* packed, double* canonical);
  * (du) and out. sp_befe_step_batch: out_i = Phi_dt(u_i) as sp_befe_step;
  * sp_jvp_lin_batch: out_i = the Jacobian action of sp_jvp_lin on du_i about
  * the cached base state (SP_OP_RESIDUAL only for the one-step operator). Up to
- * nstreams (1..8) members run concurrently, each with its own intermediates
+ * nstreams (1..8) members run concurrently (3 fill, with the plan's own
+ * stream, the 4 hardware queues a process gets by default), each with its own intermediates
  * (about 10 canonical fields) and stream, allocated on first use and kept
  * until sp_plan_destroy; the plan's stream waits for all members before the
  * call returns its work, so results are ordered like those of single calls and
@@ -236,7 +237,7 @@ sp_status sp_jvp_lin_batch(sp_plan* plan, int32_t op, int32_t count, int32_t nst
  * on the device (unit vector, unpack, Jacobian action, pack) without host
  * synchronisation. For the one-step operators (SP_OP_PHI, or SP_OP_RESIDUAL
  * with one BEFE step, no laminar advection) and count >= 8 the columns are
- * spread over 4 concurrent members as in sp_jvp_lin_batch, each with its own
+ * spread over 3 concurrent members as in sp_jvp_lin_batch, each with its own
  * unit vector and fields; the multi-step chain forms them one after another.
  * The plan's stream waits for all of them. Buffers are allocated on first use
  * and kept until sp_plan_destroy (SP_ERR_NOMEM if that fails). SP_ERR_INVALID for a bad

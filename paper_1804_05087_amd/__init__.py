@@ -216,16 +216,17 @@ class Plan:
                              f"tensor on {self.device}")
         return C.c_void_p(t.data_ptr())
 
-    def befe_step_batch(self, u, out=None, streams: int = 4):
+    def befe_step_batch(self, u, out=None, streams: int = 3):
         """Phi_dt of each of the count fields u[i] (a (count, *shape) tensor),
-        up to `streams` of them concurrently."""
+        up to `streams` of them concurrently (3 with the plan's own stream
+        fill the 4 hardware queues a process gets by default)."""
         torch = _torch()
         out = torch.empty_like(u) if out is None else out
         self._check(self.lib.sp_befe_step_batch(self.h, u.shape[0], streams,
                                                 self._batch(u, "u"), self._batch(out, "out")))
         return out
 
-    def jvp_lin_batch(self, du, op: int = SP_OP_PHI, out=None, streams: int = 4):
+    def jvp_lin_batch(self, du, op: int = SP_OP_PHI, out=None, streams: int = 3):
         """The Jacobian action about the base of linearize() on each du[i]."""
         torch = _torch()
         out = torch.empty_like(du) if out is None else out

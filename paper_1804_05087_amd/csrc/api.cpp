@@ -541,7 +541,7 @@ extern "C" sp_status sp_jacobian_columns(sp_plan* p, int32_t op, int64_t first, 
     SP_TRY_HIP(launch_fill(p, p->jc_e, (size_t)n, 0.0), "zero unit vector");
   }
   // one-step operators (whose base state the members only read) spread the
-  // columns over 4 streams with their own buffers; the multi-step chain
+  // columns over 3 streams with their own buffers; the multi-step chain
   // re-caches the base per step, so it runs them one after another
   const bool one_step = (op == SP_OP_PHI || (p->nsteps == 1 && p->scheme == 0)) && !p->advect;
   if (one_step && count >= 8) {
@@ -549,7 +549,7 @@ extern "C" sp_status sp_jacobian_columns(sp_plan* p, int32_t op, int64_t first, 
       sp_status s = base_at(p, 0);
       if (s) return s;
     }
-    const int S = 4;
+    const int S = 3;  // with the plan's stream: the 4 hardware queues of a process
     sp_status s = ensure_batch(p, S);
     if (s) return s;
     for (int b = 0; b < S; ++b) {
