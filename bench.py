@@ -707,6 +707,15 @@ def main():
     P.linearize(u)
     s, _ = time_loop(torch, lambda: P.jvp_lin(du, SP_OP_RESIDUAL, out), steps2, args.warmup)
     res["jvp_fp64_evals_per_s"] = steps2 / s
+    # the vector-Jacobian product (the transposed pipeline), FP64 and mixed
+    s, _ = time_loop(torch, lambda: P.vjp_lin(du, SP_OP_RESIDUAL, out), steps2, args.warmup)
+    res["vjp_fp64_evals_per_s"] = steps2 / s
+    P.set_precision(SP_MIXED)
+    P.linearize(u)
+    s, _ = time_loop(torch, lambda: P.vjp_lin(du, SP_OP_RESIDUAL, out), steps2, args.warmup)
+    res["vjp_mixed_evals_per_s"] = steps2 / s
+    P.set_precision(SP_FP64)
+    P.linearize(u)
     log("rates", res)
 
     # ---- per-kernel durations inside the FP64 Phi loop (HIP events, plan stream)
