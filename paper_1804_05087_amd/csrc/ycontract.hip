@@ -217,7 +217,10 @@ struct AdjSynthLoad {
 // for kz < nz/2 (x may be NULL); the z Nyquist rows kz = nz/2 get xa * x (or
 // zero) from the blocks past the first nqb column blocks. nterm[c] terms for
 // component c = the logical z block index.
-template <typename R, int KS, class Load>
+// ALLT: each wave computes every row tile from the A fragments it loaded
+// (grid y = 1) instead of one tile per block; for loaders that gather several
+// fields per element this removes the re-loads across the row tiles.
+template <typename R, int KS, class Load, bool ALLT = false>
 __global__ void __launch_bounds__(256)
     k_ycoef_mfma(Load load, int nterm0, int nterm1, int nterm2, YMat<R> M0, YMat<R> M1,
                  const double2* __restrict__ x, double xa, double2* __restrict__ out, int nx,
@@ -251,9 +254,7 @@ __global__ void __launch_bounds__(256)
   const int kza = qcl / nx;
   const int mxa = qcl - kza * nx;
   const int nt = ny >> 4;
-  const int t = bk.y;
-  const bool tile = t < nt;
-  const bool tail = (t == (int)gridDim.y - 1) && (16 * nt < ny);
+  const int ty = ALLT ? (nt > 0 ? nt : 1) : (int)gridDim.y;  // row tiles of the launch
   R a[2][KS];
 #pragma unroll
   for (int tm = 0; tm < 2; ++tm) {
@@ -264,6 +265,9 @@ __global__ void __launch_bounds__(256)
       a[tm][s] = v * (R)((qav && j < ny) ? 1 : 0);  // a mask, not a select: see k_ysynth_mfma
     }
   }
+  for (int t = ALLT ? 0 : bk.y; t < (ALLT ? ty : bk.y + 1); ++t) {
+  const bool tile = t < nt;
+  const bool tail = (t == ty - 1) && (16 * nt < ny);
   if (tile) {
     const int n = 16 * t + (lane & 15);
     typename MF::acc_t acc = {0, 0, 0, 0};
@@ -348,6 +352,7 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
+  }  // row tiles
 }
 
 // ----------------------------------- launchers -----------------------------------
@@ -479,6 +484,11 @@ hipError_t launch_adj_synth(sp_plan* p, const double2* x, double a, double2* out
   const int nq = d.nzm * d.nx;
   int nqb;
   const dim3 grid = ycoef_grid(d, &nqb);
+  // FP64: all row tiles per wave (grid y = 1), since the loader gathers up to
+  // three fields per element (measured: VJP 10.2 -> 11.5 k/s at 48x65x48);
+  // FP32 keeps one tile per block (its loads are cheap, its waves more useful)
+  dim3 grid1 = grid;
+  grid1.y = 1;
   SP_PROF_BEGIN(p, KID_ADJ_SYNTH);
   if (fp32) {
     const AdjSynthLoad<float> ld{(const float2*)p->yv, d.nx, d.ny, nq, (float)d.alpha,
@@ -493,7 +503,7 @@ hipError_t launch_adj_synth(sp_plan* p, const double2* x, double a, double2* out
     const AdjSynthLoad<double> ld{(const double2*)p->yv, d.nx, d.ny, nq, d.alpha, d.gamma};
     const YMat<double> m0 = ymat<double>(p, YM_T_T), m1 = ymat<double>(p, YM_TD_T);
 #define L64(KS)                                                                                \
-  hipLaunchKernelGGL((k_ycoef_mfma<double, KS, AdjSynthLoad<double>>), grid, dim3(256), 0,      \
+  hipLaunchKernelGGL((k_ycoef_mfma<double, KS, AdjSynthLoad<double>, true>), grid1, dim3(256), 0, \
                      p->stream, ld, 2, 1, 2, m0, m1, x, a, out, d.nx, d.ny, d.nzh, d.nzm, nqb)
     SP_KS_DISPATCH(d.ny, L64);
 #undef L64
