@@ -93,11 +93,13 @@ __global__ void __launch_bounds__(64)
   const double ik = mean ? 0.0 : 1.0 / k;
   const double lam = k2 + re * inv_dt;
   double2 wa[3], wb[3], wc[3];
+  // packed-Euclidean -> Parseval weights: the (0,0) mode counts twice
+  const double wscale = mean ? 2.0 : 1.0;
 #pragma unroll
   for (int t = 0; t < 3; ++t) {  // clamped loads, masked after (no per-load branches)
     const int n = tid + 64 * t;
     const int nc = n < n1 ? n : N;
-    const double keep = n < n1 ? 1.0 : 0.0;
+    const double keep = n < n1 ? wscale : 0.0;
     wa[t] = w[mo + nc];
     wb[t] = w[cs + mo + nc];
     wc[t] = w[2 * cs + mo + nc];
@@ -322,14 +324,19 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Scale the (0,0) mode of a canonical field in place.
-__global__ void k_mean_scale(double2* __restrict__ a, double s, int nx, int nzh, int ny) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 3 * ny) return;
-  const int c = t / ny;
-  const int n = t - c * ny;
-  const size_t o = ((size_t)c * nx * nzh) * ny + n;
-  a[o] = make_double2(a[o].x * s, a[o].y * s);
+// out <- a s out + b w, s = 1/2 on the (0,0) mode (Parseval -> packed-Euclidean
+// weights) and 1 elsewhere: the end of the VJP, with the residual's (. - w)/dt.
+__global__ void k_vjp_finish(double2* __restrict__ out, const double2* __restrict__ w, double a,
+                             double b, int nx, int nzh, int ny, size_t n) {
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
+       t += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)((t / ny) % nzh);
+    const int i = (int)((t / ((size_t)ny * nzh)) % nx);
+    const double s = (i == 0 && j == 0) ? 0.5 * a : a;
+    const double2 v = out[t];
+    const double2 x = (b != 0.0) ? w[t] : make_double2(0.0, 0.0);  // SP_OP_PHI: w unused
+    out[t] = make_double2(s * v.x + b * x.x, s * v.y + b * x.y);
+  }
 }
 
 // ----------------------------------- launchers -----------------------------------
@@ -392,14 +399,6 @@ hipError_t launch_adj_z_lds(sp_plan* p, bool fp32) {
   return hipGetLastError();
 }
 
-hipError_t launch_mean_scale(sp_plan* p, double2* a, double s) {
-  const Dims& d = p->d;
-  SP_PROF_BEGIN(p, KID_MEAN_SCALE);
-  hipLaunchKernelGGL(k_mean_scale, dim3((3 * d.ny + 255) / 256), dim3(256), 0, p->stream, a, s,
-                     d.nx, d.nzh, d.ny);
-  SP_PROF_END(p, KID_MEAN_SCALE);
-  return hipGetLastError();
-}
 
 #define SP_TRY_HIP(expr, what)                 \
   do {                                         \
@@ -420,19 +419,21 @@ sp_status vjp_lin(sp_plan* p, int op, const double2* w, double2* out) {
   const bool fp32 = (p->precision == SP_MIXED);
   const Dims& d = p->d;
   const size_t n = (size_t)3 * d.nx * d.nzh * d.ny;
-  // packed-Euclidean -> Parseval: the (0,0) mode counts twice relative to the rest
-  SP_TRY_HIP(hipMemcpyAsync(p->t1, w, n * sizeof(double2), hipMemcpyDeviceToDevice, p->stream),
-             "copy w");
-  SP_TRY_HIP(launch_mean_scale(p, p->t1, 2.0), "mean_scale");
-  SP_TRY_HIP(launch_stokes_solve_adj(p, p->t1, p->t2), "stokes_solve_adj");
+  // the adjoint solve weighs the (0,0) mode of w twice (packed-Euclidean ->
+  // Parseval), the finishing pass halves it back
+  SP_TRY_HIP(launch_stokes_solve_adj(p, w, p->t2), "stokes_solve_adj");
   SP_TRY_HIP(launch_synth_tab(p, p->t2, 1, p->nv, fp32), "analysis^T");
   SP_TRY_HIP(launch_fft_x_inv_gen(p, p->nv, p->xp, 3, 1, fp32), "pad+ifft_x");
   SP_TRY_HIP(launch_adj_z(p, fp32), "adj_z");
   SP_TRY_HIP(launch_fft_x_fwd_gen(p, p->xp, p->yv, 6, fp32), "fft_x+truncate");
   SP_TRY_HIP(launch_adj_synth(p, p->t2, d.inv_dt, out, fp32), "adj_synth");
-  SP_TRY_HIP(launch_mean_scale(p, out, 0.5), "mean_scale");
-  if (op == SP_OP_RESIDUAL)
-    SP_TRY_HIP(launch_axpby(p, out, d.inv_dt, w, -d.inv_dt, out, n), "axpby");
+  const bool res = (op == SP_OP_RESIDUAL);
+  SP_PROF_BEGIN(p, KID_MEAN_SCALE);
+  hipLaunchKernelGGL(k_vjp_finish, dim3(n < 4096 * 256 ? (n + 255) / 256 : 4096), dim3(256), 0,
+                     p->stream, out, w, res ? d.inv_dt : 1.0, res ? -d.inv_dt : 0.0, d.nx, d.nzh,
+                     d.ny, n);
+  SP_PROF_END(p, KID_MEAN_SCALE);
+  SP_TRY_HIP(hipGetLastError(), "vjp finish");
   return SP_OK;
 }
 
