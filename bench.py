@@ -601,7 +601,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
-              "(this build runs on a single MI355X; see DESIGN.md for how it would shard)",
+              "(the library runs on a single MI355X; sharding across GPUs is not implemented)",
               file=sys.stderr)
         sys.exit(2)
     if args.dt_sweep:

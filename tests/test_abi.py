@@ -128,3 +128,22 @@ def test_advected_mode_operator_matches_oracle(lib):
         err = np.abs(S - ref).max() / np.abs(ref).max()
         assert err < 1e-13, (N, kx, kz, err)
     assert lib.sp_advected_mode_operator(8, 0.0, 0.0, 400.0, 0.01, S.ctypes.data) == -1
+
+
+def test_missing_library_raises(monkeypatch, tmp_path):
+    """Without libsp.so the binding raises instead of falling back to the CPU."""
+    from paper_1804_05087_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libsp.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        _lib.load()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asking for more exits with status 2 before any work."""
+    import subprocess
+    import sys
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert res.returncode == 2
+    assert "one GPU only" in res.stderr
