@@ -565,6 +565,58 @@ def symmetric_compare(seeds=range(10), energies=(1e-2, 5e-2), re_find=400.0, re=
     return out
 
 
+def mixed_error(workload=DEFAULT, energy=1e-6, max_krylov=200, rtol=1e-4, max_newton=20):
+    """Per-Newton-step error of the mixed-precision solves against the FP64 one
+    at 48x65x48, Re 1000, dt 100 (same start as the benchmark's Newton solve).
+    Each solve advances one Newton step per call, so the iterate after every
+    step is kept; the FP64 path is the reference (its Jacobian actions agree
+    with the oracle to 1e-12 relative). Reported per step: ||r|| of each
+    solve and the volume-normalised L2 distance of each mixed iterate from
+    the FP64 iterate of the same step, absolute and relative to the FP64
+    Newton update of that step."""
+    import torch
+    from paper_1804_05087_amd import SP_FP64, SP_MIXED, Plan, synth
+    w = WORKLOADS[workload]
+    dev = torch.device("cuda", 0)
+    P = Plan(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], w["re"], w["dt"], device=dev)
+    u0 = torch.from_numpy(synth.perturbation_field(
+        w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], seed=0, energy=energy)).to(dev)
+    iterates, res = {}, {}
+    for name, prec, kf32 in (("fp64", SP_FP64, False), ("mixed", SP_MIXED, False),
+                             ("mixed_krylov_fp32", SP_MIXED, True)):
+        P.set_precision(prec)
+        uu = u0.clone()
+        its, rs = [u0.clone()], []
+        for _ in range(max_newton):
+            # one Newton step per call; the report also holds ||r|| after the step
+            rep = P.newton_gmres(uu, max_newton=1, max_krylov=max_krylov, gmres_rtol=rtol,
+                                 newton_tol=1e-10, krylov_fp32=kf32)
+            if not rs:
+                rs.append(rep["res_norm"][0])
+            if rep["newton_iters"] == 1:
+                its.append(uu.clone())
+                rs.append(rep["res_norm"][-1])
+            if rep["converged"] or rep["newton_iters"] == 0:
+                break
+        iterates[name], res[name] = its, rs
+        log("mixed-error", name, "steps", len(its) - 1, "final ||r||", rs[-1])
+    P.set_precision(SP_FP64)
+    ref = iterates["fp64"]
+    out = {"metric": "mixed_vs_fp64_newton_error", "workload": workload,
+           "start": {"energy": energy, "seed": 0, "max_krylov": max_krylov, "gmres_rtol": rtol},
+           "res_norm": {k: [float(f"{x:.3e}") for x in v] for k, v in res.items()}}
+    for name in ("mixed", "mixed_krylov_fp32"):
+        rows = []
+        for k in range(1, min(len(ref), len(iterates[name]))):
+            d = P.norm((iterates[name][k] - ref[k]).contiguous())
+            step = P.norm((ref[k] - ref[k - 1]).contiguous())
+            rows.append({"step": k, "dist_L2": float(f"{d:.3e}"),
+                         "fp64_update_L2": float(f"{step:.3e}"),
+                         "dist_over_update": float(f"{d / step:.3e}") if step > 0 else None})
+        out[name] = rows
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -580,6 +632,9 @@ def main():
     ap.add_argument("--newton-energy", type=float, default=1e-6,
                     help="perturbation energy of the Newton start (E = 1e-2 does not "
                          "converge without a hookstep)")
+    ap.add_argument("--mixed-error", action="store_true",
+                    help="instead of the benchmark line, print the per-Newton-step distance of "
+                         "the mixed-precision iterates from the FP64 ones at 48x65x48")
     ap.add_argument("--dt-sweep", action="store_true",
                     help="instead of the benchmark line, print the Krylov-count sweep over "
                          "dt in {1, 10, 100} and seeds 0-9 at 32x33x32, Re 400")
@@ -604,6 +659,9 @@ def main():
               "(the library runs on a single MI355X; sharding across GPUs is not implemented)",
               file=sys.stderr)
         sys.exit(2)
+    if args.mixed_error:
+        print(json.dumps(mixed_error()), flush=True)
+        return
     if args.dt_sweep:
         print(json.dumps(dt_sweep()), flush=True)
         return
