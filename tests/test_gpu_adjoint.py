@@ -151,3 +151,50 @@ def test_autograd_gradient_vs_central_differences(torch_mod):
         worst = max(worst, abs(fd - an) / (abs(an) + 1e-30))
         assert abs(fd - an) <= 1e-6 * abs(an) + 1e-9 * loss.item(), (fd, an)
     say("autograd worst rel FD mismatch", worst)
+
+
+def test_autograd_gradient_mixed_precision(torch_mod):
+    """The FP32 variant of the adjoint workload: the gradient of
+    L(x) = 1/2 ||Phi(x) - x||^2 through PhiFunction on a mixed-precision plan
+    (FP32 transforms, products and y-contractions; FP64 solves) against the FP64
+    plan's gradient and against central differences of the FP64 loss (h = 1e-6,
+    20 seeded directions). FP32 rounding (unit 6e-8) amplified by the transform
+    and solve chain bounds the gap at ~1e-6 of the gradient's norm."""
+    torch = torch_mod
+    from paper_1804_05087_amd import SP_MIXED, Plan, PhiFunction
+    dims = (32, 33, 32)
+    say("autograd mixed 32x33x32")
+    g, B, P = _setup(dims, 400.0, 100.0)
+    PM = Plan(*dims, *BOX, 400.0, 100.0, precision=SP_MIXED)
+    u = to_dev(synth.perturbation_field(*dims, *BOX, seed=0))
+    x0 = P.pack(u).clone()
+
+    def grad_of(plan):
+        x = x0.clone().requires_grad_(True)
+        loss = 0.5 * torch.sum((PhiFunction.apply(x, plan) - x) ** 2)
+        loss.backward()
+        return x.grad.detach(), loss.item()
+
+    g64, loss64 = grad_of(P)
+    g32, loss32 = grad_of(PM)
+    gn = torch.linalg.norm(g64).item()
+    e_grad = torch.linalg.norm(g32 - g64).item() / gn
+    say("mixed gradient: rel error vs FP64", e_grad, "loss rel diff", abs(loss32 - loss64) / loss64)
+    assert e_grad < 2e-5
+    assert abs(loss32 - loss64) <= 2e-5 * loss64
+
+    def L(xx):
+        with torch.no_grad():
+            return 0.5 * torch.sum((PhiFunction.apply(xx, P) - xx) ** 2).item()
+
+    gen = torch.Generator(device="cpu").manual_seed(1)
+    h = 1e-6
+    worst = 0.0
+    for _ in range(20):
+        d = torch.randn(P.packed_n, generator=gen, dtype=torch.float64).to(P.device)
+        d /= torch.linalg.norm(d)
+        fd = (L(x0 + h * d) - L(x0 - h * d)) / (2 * h)
+        an = torch.dot(g32, d).item()
+        worst = max(worst, abs(fd - an) / gn)
+        assert abs(fd - an) <= 2e-5 * gn, (fd, an, gn)
+    say("mixed gradient: worst FD mismatch / ||grad||", worst)
