@@ -617,6 +617,67 @@ def mixed_error(workload=DEFAULT, energy=1e-6, max_krylov=200, rtol=1e-4, max_ne
     return out
 
 
+def large_newton(workload="couette_96x97x96_re2000_dt100", max_newton=30, max_krylov=200,
+                 rtol=1e-3):
+    """Trust-region (hookstep) Newton-GMRES to ||r|| < 1e-10 on the large grid
+    (96x97x96, Re 2000, 4pi x 2 x 2pi box) from the streak + roll start, with FP64
+    Jacobian actions, mixed ones, mixed ones with an FP32 Krylov basis, and FP64
+    actions of the step with the laminar advection in its implicit operator.
+    Reported per solve: convergence, Newton steps, Krylov iterations, seconds,
+    the residual history and the distance of the end state from laminar flow
+    and from the FP64 solve's end state."""
+    import torch
+    from paper_1804_05087_amd import SP_FP64, SP_MIXED, Plan, synth
+    w = WORKLOADS[workload]
+    dev = torch.device("cuda", 0)
+    P = Plan(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], w["re"], w["dt"], device=dev)
+    u0 = torch.from_numpy(synth.streak_roll_field(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"],
+                                                  seed=0)).to(dev)
+    lam = torch.from_numpy(synth.laminar_field(w["nx"], w["ny"], w["nz"])).to(dev)
+    out = {"metric": "large_grid_newton", "workload": workload, "newton": "hookstep",
+           "max_krylov": max_krylov, "gmres_rtol": rtol, "newton_tol": 1e-10}
+    finals = {}
+    for name, prec, kf32 in (("fp64", SP_FP64, False), ("mixed", SP_MIXED, False),
+                             ("mixed_krylov_fp32", SP_MIXED, True)):
+        P.set_precision(prec)
+        uu = u0.clone()
+        torch.cuda.synchronize()
+        rep = P.newton_hookstep(uu, max_newton=max_newton, max_krylov=max_krylov,
+                                gmres_rtol=rtol, newton_tol=1e-10, krylov_fp32=kf32)
+        finals[name] = uu
+        out[name] = {"converged": rep["converged"], "newton_iters": rep["newton_iters"],
+                     "total_krylov": rep["total_krylov"], "actions": rep["total_actions"],
+                     "seconds": round(rep["seconds"], 3),
+                     "res_history": [float(f"{x:.3e}") for x in rep["res_norm"]],
+                     "krylov": rep["krylov"],
+                     "dist_to_laminar_L2": float(f"{P.norm((uu - lam).contiguous()):.4e}")}
+        if name != "fp64":
+            out[name]["vs_fp64_final_L2"] = float(
+                f"{P.norm((uu - finals['fp64']).contiguous()):.3e}")
+        log("large newton", name, out[name])
+    P.set_precision(SP_FP64)
+    del P
+    # the same solve with the laminar advection in the implicit operator
+    PA = Plan(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], w["re"], w["dt"], device=dev)
+    tb = time.perf_counter()
+    PA.set_advection(True)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - tb
+    uu = u0.clone()
+    rep = PA.newton_hookstep(uu, max_newton=max_newton, max_krylov=max_krylov,
+                             gmres_rtol=rtol, newton_tol=1e-10)
+    out["fp64_advected"] = {"converged": rep["converged"], "newton_iters": rep["newton_iters"],
+                            "total_krylov": rep["total_krylov"], "actions": rep["total_actions"],
+                            "seconds": round(rep["seconds"], 3),
+                            "operator_build_seconds": round(build_s, 3),
+                            "res_history": [float(f"{x:.3e}") for x in rep["res_norm"]],
+                            "krylov": rep["krylov"],
+                            "dist_to_laminar_L2": float(
+                                f"{PA.norm((uu - lam).contiguous()):.4e}")}
+    log("large newton", "fp64_advected", out["fp64_advected"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -632,6 +693,9 @@ def main():
     ap.add_argument("--newton-energy", type=float, default=1e-6,
                     help="perturbation energy of the Newton start (E = 1e-2 does not "
                          "converge without a hookstep)")
+    ap.add_argument("--large-newton", action="store_true",
+                    help="instead of the benchmark line, run hookstep Newton to 1e-10 at "
+                         "96x97x96, Re 2000, from the streak + roll start (FP64 and mixed)")
     ap.add_argument("--mixed-error", action="store_true",
                     help="instead of the benchmark line, print the per-Newton-step distance of "
                          "the mixed-precision iterates from the FP64 ones at 48x65x48")
@@ -659,6 +723,9 @@ def main():
               "(the library runs on a single MI355X; sharding across GPUs is not implemented)",
               file=sys.stderr)
         sys.exit(2)
+    if args.large_newton:
+        print(json.dumps(large_newton()), flush=True)
+        return
     if args.mixed_error:
         print(json.dumps(mixed_error()), flush=True)
         return
