@@ -1,0 +1,43 @@
+"""The compulsory bytes per launch that the benchmark divides by each kernel's
+duration (its roofline position), rebuilt here from the shapes of the arrays
+each kernel reads and writes at 48x65x48 (FP64): canonical fields are
+complex128 [3][nx][nz/2+1][ny], y-valued spectral fields complex [ny][nz/2][nx],
+x-physical fields complex [ny][3nx/2][nz/2], the solve's mode record
+10(N+1)+12 doubles per mode (rounded up to even) and the Chebyshev weights."""
+import math
+
+import numpy as np
+
+
+def _nbytes(shape, itemsize):
+    return int(np.prod(shape)) * itemsize
+
+
+def test_algorithmic_bytes_48x65x48():
+    import bench
+    w = bench.WORKLOADS["couette_48x65x48_re1000_dt100"]
+    nx, ny, nz = w["nx"], w["ny"], w["nz"]
+    ab = bench.algorithmic_bytes(w)
+    canon = _nbytes((3, nx, nz // 2 + 1, ny), 16)
+    yv = _nbytes((ny, nz // 2, nx), 16)
+    xp = _nbytes((ny, 3 * nx // 2, nz // 2), 16)
+    record = 10 * ny + 12
+    record += record % 2
+    modes = nx * (nz // 2 + 1)
+    assert ab["k_synth_y"] == _nbytes((3, nx, nz // 2, ny), 16) + 5 * yv
+    assert ab["k_fft_x_inv"] == 5 * yv + 6 * xp
+    assert ab["k_z_product"] == 9 * xp
+    assert ab["k_fft_x_fwd"] == 3 * xp + 3 * yv
+    assert ab["k_stokes_solve"] == 3 * yv + 2 * canon + modes * record * 8 + 3 * ny * 8
+    # the figures quoted with the benchmark's roofline line
+    assert ab["k_stokes_solve"] == 17_439_000
+    assert ab["k_synth_y"] == 9_584_640
+    assert math.isclose(ab["k_fft_x_inv"] / 1e6, 16.77, abs_tol=0.005)
+
+
+def test_mixed_path_halves_transform_bytes():
+    import bench
+    w = bench.WORKLOADS["couette_48x65x48_re1000_dt100"]
+    ab64, ab32 = bench.algorithmic_bytes(w), bench.algorithmic_bytes(w, fp32=True)
+    for k in ("k_fft_x_inv", "k_z_product", "k_fft_x_fwd"):
+        assert 2 * ab32[k] == ab64[k]
