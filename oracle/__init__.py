@@ -25,7 +25,9 @@ Modules:
   befe      -- N(u), Phi, residual, norms, JVP, VJP
   krylov    -- GMRES (modified Gram-Schmidt, Givens) and Newton
   pack      -- canonical complex layout <-> packed real vector
-  dense     -- dense Jacobians and their spectra (tiny grids)
+  gint      -- the multi-step time-integration operator (BEFE or SBDF2 steps)
+  advect    -- the implicit operator with the laminar advection added
+  symmetry  -- the shift-reflect projector of plane Couette flow
 
 Every function is pinned by a CPU test against something other than itself
 (closed forms, analytic Stokes eigenvalues, brute-force products, library

@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package header).
 
-Sec. 6 proposes, as the most promising remedy for the large Krylov counts at
+Sec. 3.6 proposes, as the most promising remedy for the large Krylov counts at
 high Re, moving the linearisation of the advection about the laminar flow,
 (U_lam . grad) u + (u . grad) U_lam, from N into L. With U_lam = y e_x this
 linear operator is, per Fourier mode (k_x = alpha m_x),

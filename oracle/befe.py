@@ -36,7 +36,8 @@ solve; the large-dt limit -L^{-1}(L+N) (eq. largedt); divergence and wall
 values; the brute-force dealiased product; exactness of the central
 difference for the quadratic map (eq. finitediff); translation and
 reflection symmetries; adjoint dot-product identities and the dense
-Jacobian transpose.
+Jacobian transpose; the sign of N against the convective form -(u.grad)u
+plus a gradient, and the curl of single-mode fields in closed form.
 """
 from __future__ import annotations
 

@@ -8,7 +8,7 @@ the initial guess and the tolerance open; the readings used here are x0 = 0,
 modified Gram-Schmidt, Givens rotations, stop when the least-squares residual
 falls to rtol * ||b|| or after kmax iterations.
 
-Hookstep (Sec. 3.1: the codes constrain the Newton step to a trusted region
+Hookstep (Sec. 3.2: the codes constrain the Newton step to a trusted region
 of validity of the linearisation, the hookstep of Viswanath 2007): the step
 is Q y with y minimising the GMRES model ||beta e_1 - Hbar y|| subject to
 ||y|| <= delta, written through the SVD Hbar = W diag(s) Z^T as

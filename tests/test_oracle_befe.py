@@ -12,7 +12,11 @@ fixes, not against itself:
 * translations in x and z, the reflection z -> -z and the rotation
   (x, y) -> (-x, -y) commute with Phi (symmetries of plane Couette flow);
 * the VJP satisfies <w, J v> = <J^T w, v> and equals the transpose of the
-  dense Jacobian assembled column by column from JVPs.
+  dense Jacobian assembled column by column from JVPs;
+* the orientation of N: on a band-limited field N(u) = -(u.grad)u +
+  grad(|u|^2/2) pointwise (Sec. 2, eq. DE: N is the advective term), and the
+  curl of single-mode fields equals its hand-differentiated closed form, both
+  from a series evaluation that shares nothing with the oracle's curl.
 """
 import math
 
@@ -155,3 +159,106 @@ def test_dense_jacobian_transpose_and_structure():
     s = np.linalg.svd(J, compute_uv=False)
     rank = int(np.sum(s > 1e-10 * s[0]))
     assert rank == m
+
+
+# ---- orientation of the advective term (Sec. 2, eq. DE: N holds the advective
+# terms, (U.grad)U on the right-hand side with a minus sign; Sec. 3.2: formed
+# pseudospectrally). These checks use a pointwise series evaluation of their
+# own (explicit exponentials in x, z and numpy's chebval/chebder in y), so they
+# share nothing with Befe.curl, Befe.dy or the oracle's transforms.
+
+def _series(a, g, x, y, z, dx=0, dz=0):
+    """Pointwise value of the canonical spectral field a[..., i, m_z, n] at the
+    physical points (x, y, z), differentiated dx times in x and dz times in z."""
+    from numpy.polynomial import chebyshev as C
+    kx = g.kx()
+    kz = g.kz()
+    out = np.zeros(a.shape[:-3] + (len(x),))
+    for i in range(g.nx):
+        for j in range(g.nzh):
+            coef = a[..., i, j, :]
+            if not np.any(coef):
+                continue
+            fac = (1j * kx[i]) ** dx * (1j * kz[j]) ** dz
+            ty = C.chebval(y, np.moveaxis(coef, -1, 0))  # [..., npts]
+            e = fac * ty * np.exp(1j * (kx[i] * x + kz[j] * z))
+            out += e.real if j == 0 else 2.0 * e.real
+    return out
+
+
+def _dy_coeffs(a):
+    """Coefficients of d/dy by numpy's chebder (independent of cheb.derivative)."""
+    from numpy.polynomial import chebyshev as C
+    d = C.chebder(np.moveaxis(a, -1, 0))
+    d = np.concatenate([d, np.zeros((1,) + d.shape[1:], dtype=d.dtype)], axis=0)
+    return np.moveaxis(d, 0, -1)
+
+
+def _band_limited(g, mmax, nmax, seed):
+    """Real field with |m_x|, m_z <= mmax and Chebyshev degree <= nmax."""
+    rng = np.random.default_rng(seed)
+    a = g.zeros()
+    mx = g.mx()
+    for i in range(g.nx):
+        for j in range(min(mmax, g.nzh - 2) + 1):
+            if abs(mx[i]) > mmax:
+                continue
+            a[:, i, j, :nmax + 1] = (rng.standard_normal((3, nmax + 1))
+                                     + 1j * rng.standard_normal((3, nmax + 1)))
+    for i in range(1, g.nx // 2):  # Hermitian m_z = 0 plane, real (0,0) mode
+        a[:, g.nx - i, 0, :] = np.conj(a[:, i, 0, :])
+    a[:, 0, 0, :] = a[:, 0, 0, :].real
+    return a
+
+
+def test_nonlinear_orientation_against_convective_form():
+    """N(u) = -(u.grad)u + grad(|u|^2/2) pointwise, on a band-limited field whose
+    products are resolved exactly (Fourier |m| <= 3 of 8 retained, degree 8 of
+    N = 24), so the dealiased pseudospectral N must equal the convective form
+    up to the gradient the pressure absorbs. Flipping the sign of the curl (or
+    the order of the cross product) makes the residual about 2|N|."""
+    g = Grid(16, 25, 16, *BOX)
+    B = Befe(g, 400.0, 100.0)
+    a = _band_limited(g, 3, 8, seed=11)
+    rng = np.random.default_rng(12)
+    npts = 64
+    x = rng.uniform(0, g.lx, npts)
+    y = rng.uniform(-1, 1, npts)
+    z = rng.uniform(0, g.lz, npts)
+    u = _series(a, g, x, y, z)                              # [3, npts]
+    grad = np.stack([_series(a, g, x, y, z, dx=1),          # grad[k][c] = d_k u_c
+                     _series(_dy_coeffs(a), g, x, y, z),
+                     _series(a, g, x, y, z, dz=1)])
+    convective = np.einsum("kp,kcp->cp", u, grad)           # (u.grad) u
+    half_grad_sq = np.einsum("cp,kcp->kp", u, grad)         # grad(|u|^2 / 2)
+    N = _series(B.nonlinear(a), g, x, y, z)
+    err = np.abs(N + convective - half_grad_sq).max()
+    assert err <= 1e-12 * np.abs(convective).max()
+    assert np.abs(N).max() > 0.1 * np.abs(convective).max()
+
+
+def test_curl_of_single_modes_closed_form():
+    """omega = curl u of single-mode fields against the hand-differentiated
+    closed forms: u = (0, 0, cos(alpha x) T_2(y)) has omega =
+    (4 y cos(alpha x), alpha sin(alpha x) T_2(y), 0); u = (0, sin(gamma z) T_3(y),
+    0) has omega = (-gamma cos(gamma z) T_3(y), 0, 0)."""
+    g = Grid(8, 9, 8, *BOX)
+    B = Befe(g, 400.0, 100.0)
+    al, ga = g.alpha, g.gamma
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0, g.lx, 16)
+    y = rng.uniform(-1, 1, 16)
+    z = rng.uniform(0, g.lz, 16)
+    a = g.zeros()
+    a[2, 1, 0, 2] = 0.5
+    a[2, g.nx - 1, 0, 2] = 0.5
+    om = _series(B.curl(a), g, x, y, z)
+    T2 = 2 * y * y - 1
+    expect = np.stack([4 * y * np.cos(al * x), al * np.sin(al * x) * T2, 0 * x])
+    assert np.abs(om - expect).max() <= 1e-13
+    b = g.zeros()
+    b[1, 0, 1, 3] = -0.5j  # sin(gamma z) = 2 Re(-i/2 e^{i gamma z})
+    T3 = 4 * y ** 3 - 3 * y
+    om = _series(B.curl(b), g, x, y, z)
+    expect = np.stack([-ga * np.cos(ga * z) * T3, 0 * x, 0 * x])
+    assert np.abs(om - expect).max() <= 1e-13
