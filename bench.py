@@ -343,7 +343,7 @@ def _truncate(u, dims):
 
 def spectra_report(dims=(12, 17, 12), re_find=400.0, re=500.0, seeds=(8, 1, 0, 2, 3),
                    stokes_T=(1e-4, 0.1, 100.0), int_T=(1.0, 10.0), dt_int=0.03125):
-    """Spectra of the Newton operators' Jacobians (Sec. 5) on a small grid of
+    """Spectra of the Newton operators' Jacobians (Sec. 3.5) on a small grid of
     the Couette box, restricted to admissible fields. The base state is a
     non-laminar equilibrium: found by the Stokes solver at 32x33x32, Re = 400
     from the perturbation family, truncated to the small grid, re-converged
@@ -418,7 +418,7 @@ def spectra_report(dims=(12, 17, 12), re_find=400.0, re=500.0, seeds=(8, 1, 0, 2
 def advect_compare(seeds=range(5), dts=(10.0, 100.0), max_krylov=400, rtol=1e-3,
                    workload="couette_32x33x32_re400_dt100"):
     """The Stokes step against the step with the laminar advection in its
-    implicit operator (Sec. 6's proposed remedy) on `workload` (32x33x32,
+    implicit operator (Sec. 3.6's proposed remedy) on `workload` (32x33x32,
     Re = 400 by default):
     GMRES iterations of the first Newton step to `rtol` (with the relative
     residual after at most `max_krylov`), and hookstep Newton solves to
@@ -914,7 +914,7 @@ def main():
             (finals["mixed_krylov_fp32"] - finals["fp64"]).contiguous())
         P.set_precision(SP_FP64)
         # the same solve with the laminar advection in the implicit operator
-        # (Sec. 6's proposed remedy; same roots, fewer Krylov iterations)
+        # (Sec. 3.6's proposed remedy; same roots, fewer Krylov iterations)
         PA = Plan(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], w["re"], w["dt"], device=dev)
         tb = time.perf_counter()
         PA.set_advection(True)

@@ -121,7 +121,7 @@ sp_status sp_plan_set_steps(sp_plan* plan, int32_t nsteps);
  * nonlinear term (SP_ERR_NOMEM if that fails). Invalidates the base state.
  * Synchronises. */
 sp_status sp_plan_set_scheme(sp_plan* plan, int32_t scheme);
-/* Laminar advection in the implicit operator (the remedy proposed in Sec. 6):
+/* Laminar advection in the implicit operator (the remedy proposed in Sec. 3.6):
  * with on != 0 every BEFE step of the plan (sp_befe_step, sp_residual, the
  * Jacobian actions and the Newton drivers) becomes
  *   (I - dt (L + M)) Phi~(U) = U + dt (N(U) - M U),
@@ -229,7 +229,7 @@ sp_status sp_jvp_lin_batch(sp_plan* plan, int32_t op, int32_t count, int32_t nst
                            const double* du, double* out);
 
 /* Columns first .. first+count-1 of the dense Jacobian in the packed real
- * basis, the matrix whose eigenvalues give the spectra of Sec. 5: column i is
+ * basis, the matrix whose eigenvalues give the spectra of Sec. 3.5: column i is
  * pack(J unpack(e_i)) with J the Jacobian action of sp_jvp_lin for op about
  * the cached base state (sp_linearize first), written to J + (i - first) ld
  * (device, float64; ld >= packed_n, the caller owns J; J may be NULL when
@@ -291,7 +291,7 @@ typedef struct {
   double rho[64];        /* actual / predicted decrease of ||r||^2                 */
 } sp_hook_report;
 
-/* Newton-GMRES with the hookstep (Sec. 3.1: the step is kept inside a trusted
+/* Newton-GMRES with the hookstep (Sec. 3.2: the step is kept inside a trusted
  * region of validity of the linearisation, after Viswanath 2007). Each Newton
  * iteration runs GMRES as sp_newton_gmres does, then takes du = Q y with y
  * minimising the GMRES model ||beta e_1 - Hbar y|| subject to ||y|| <= delta

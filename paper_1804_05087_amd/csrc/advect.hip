@@ -1,5 +1,5 @@
 // The BEFE step with the laminar advection moved into the implicit operator
-// (paper Sec. 6, the proposed remedy for the Krylov counts at high Re):
+// (paper Sec. 3.6, the proposed remedy for the Krylov counts at high Re):
 //
 //   (I - dt (L + M)) Phi~(U) = U + dt (N(U) - M U),
 //   M u = -( i k_x y u + v, i k_x y v, i k_x y w )    per Fourier mode,

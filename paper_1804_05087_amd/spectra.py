@@ -1,4 +1,4 @@
-"""Spectra of the Newton operators' Jacobians (paper Sec. 5).
+"""Spectra of the Newton operators' Jacobians (paper Sec. 3.5).
 
 The distribution of the eigenvalues of G_U decides how fast GMRES converges
 on eq. biglin. The paper forms the full Jacobian of G^Stokes_T = B_T - I or

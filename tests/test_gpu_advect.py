@@ -1,5 +1,5 @@
 """GPU parity of the BEFE step with the laminar advection in the implicit
-operator (Sec. 6's proposed remedy) against the oracle's dense per-mode
+operator (Sec. 3.6's proposed remedy) against the oracle's dense per-mode
 solves: Phi~, its Jacobian action, the multi-step operator built on it, and
 the aliasing and error contracts."""
 import math

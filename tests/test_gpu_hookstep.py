@@ -1,4 +1,4 @@
-"""GPU parity of the trust-region Newton-GMRES (hookstep, Sec. 3.1) against the
+"""GPU parity of the trust-region Newton-GMRES (hookstep, Sec. 3.2) against the
 oracle's newton_hook: same residual history, trials, radii, multipliers, step
 lengths and ratios. The cases are chosen with every ratio at least 0.019 away
 from the thresholds 0.01 / 0.25 / 0.75, so rounding cannot flip a decision."""

@@ -1,4 +1,4 @@
-"""The spectra tool on the GPU (Sec. 5): the dense Jacobian assembled from the
+"""The spectra tool on the GPU (Sec. 3.5): the dense Jacobian assembled from the
 library's Jacobian actions equals the oracle's, J_Phi has rank at most the
 dimension of the admissible subspace (so G_U has the eigenvalue -1 on the
 rest), and about U = 0 the BEFE step's eigenvalues give back the analytic

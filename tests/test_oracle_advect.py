@@ -1,5 +1,5 @@
 """Pins of the oracle's BEFE step with laminar advection in the implicit
-operator (the remedy proposed in Sec. 6)."""
+operator (the remedy proposed in Sec. 3.6)."""
 import math
 
 import numpy as np

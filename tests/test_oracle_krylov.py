@@ -63,7 +63,7 @@ def test_newton_quadratic_convergence():
 
 
 # ---------------------------------------------------------------- hookstep
-# The constrained step min ||b - Hbar y|| over ||y|| <= delta (Sec. 3.1, the
+# The constrained step min ||b - Hbar y|| over ||y|| <= delta (Sec. 3.2, the
 # hookstep of Viswanath 2007) is pinned by what fixes it mathematically: the
 # unconstrained least-squares solution when it fits, otherwise a point of the
 # sphere ||y|| = delta satisfying the Lagrange condition with mu > 0, and no

@@ -1,4 +1,4 @@
-"""Host helpers of the spectra tool against the paper's 1-D model (Sec. 5,
+"""Host helpers of the spectra tool against the paper's 1-D model (Sec. 3.5,
 eq. model): advection-diffusion u_t = u_xx / Re - U u_x on a periodic line,
 eigenvalues lambda_k = -k^2/Re - i k U. BEFE with the diffusion implicit and
 the advection explicit gives B_T - I with eigenvalues
