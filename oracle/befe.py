@@ -119,19 +119,9 @@ class Befe:
 
     # ---- adjoint ---------------------------------------------------------------------------
     def solve_adjoint(self, w):
-        """Adjoint of the homogeneous solve S_0 in the Parseval inner product."""
-        g = self.g
-        out = g.zeros()
-        for (i, j) in self.solver.modes:
-            if i == 0 and j == 0:
-                S = self.solver.mean_operator()
-                out[0, 0, 0] = S.T @ w[0, 0, 0].real
-                out[2, 0, 0] = S.T @ w[2, 0, 0].real
-                continue
-            S = self.solver.mode_operator(i, j)
-            x = S.conj().T @ w[:, i, j, :].reshape(-1)
-            out[:, i, j, :] = x.reshape(3, g.ny)
-        return out
+        """Adjoint of the homogeneous solve S_0 in the Parseval inner product
+        (per mode the conjugate transpose, oracle.stokes)."""
+        return self.solver.solve_adjoint(w)
 
     def curl_adjoint(self, a):
         ax, ay, az = a[0], a[1], a[2]

@@ -123,6 +123,20 @@ def _refined_solve(A: np.ndarray, lu, b: np.ndarray, steps: int = 2) -> np.ndarr
     return x
 
 
+def _refined_solve_adjoint(A: np.ndarray, lu, b: np.ndarray, steps: int = 2) -> np.ndarray:
+    """x with A^H x = b, from the LU factors of A, refined like _refined_solve."""
+    cplx = np.iscomplexobj(A)
+    x = sla.lu_solve(lu, b, trans=2 if cplx else 1)
+    AH = A.conj().T.astype(np.clongdouble if cplx else np.longdouble)
+    for _ in range(steps):
+        xe = x.astype(AH.dtype)
+        r = b.astype(AH.dtype) - AH @ xe
+        dx = sla.lu_solve(lu, r.astype(np.complex128 if cplx else np.float64),
+                          trans=2 if cplx else 1)
+        x = (xe + dx.astype(AH.dtype)).astype(x.dtype)
+    return x
+
+
 class StokesSolver:
     """Per-mode dense factorisations of the implicit BEFE operator.
 
@@ -179,6 +193,34 @@ class StokesSolver:
         N = self.g.N
         x = _refined_solve(A, lu, mode_rhs(N, gfield[:, i, j, :]))
         return x[3 * N + 3:]
+
+    def solve_adjoint(self, w: np.ndarray) -> np.ndarray:
+        """Conjugate transpose of the homogeneous solve g -> phi, mode by mode.
+
+        For a mode k != 0 the solve is S = P A^{-1} E, with E placing -g_c(n),
+        n <= N-2, on the momentum rows and P keeping the velocity unknowns, so
+        S^H w = E^H A^{-H} P^H w: one solve with A^H (the same LU factors) per
+        mode. The (0,0) mode is real: S^T w = -(A^{-T} w) on n <= N-2.
+        Pinned against the conjugate transpose of the explicit operators
+        (mode_operator, mean_operator) in tests/test_oracle_stokes.py.
+        """
+        g = self.g
+        N = g.N
+        n1 = N + 1
+        out = g.zeros()
+        for (i, j) in self.modes:
+            A, lu = self._fact[(i, j)]
+            if i == 0 and j == 0:
+                for c in (0, 2):
+                    y = _refined_solve_adjoint(A, lu, np.ascontiguousarray(w[c, 0, 0].real))
+                    out[c, 0, 0, :N - 1] = -y[:N - 1]
+                continue
+            b = np.zeros(4 * n1, dtype=np.complex128)
+            b[:3 * n1] = w[:, i, j, :].reshape(-1)
+            y = _refined_solve_adjoint(A, lu, b)
+            for c in range(3):
+                out[c, i, j, :N - 1] = -y[c * (N - 1):(c + 1) * (N - 1)]
+        return out
 
     def mode_operator(self, i: int, j: int) -> np.ndarray:
         """Dense 3(N+1) x 3(N+1) complex map g -> phi for one mode (k != 0).

@@ -179,3 +179,25 @@ def test_solutions_are_divergence_free_and_no_slip():
     t[0, 0, 0] -= 1.0
     b[0, 0, 0] += 1.0
     assert np.abs(t).max() < 1e-14 and np.abs(b).max() < 1e-14
+
+
+def test_adjoint_solve_equals_conjugate_transpose_of_explicit_operator():
+    """solve_adjoint (one solve with A^H per mode) against the definition of the
+    adjoint: the conjugate transpose of the explicit map g -> phi assembled
+    column by column from forward solves (mode_operator, mean_operator)."""
+    import math
+    g = Grid(6, 13, 8, 2 * math.pi / 1.14, 2 * math.pi / 2.5)
+    S = StokesSolver(g, 400.0, 10.0)
+    rng = np.random.default_rng(7)
+    w = rng.standard_normal(g.shape) + 1j * rng.standard_normal(g.shape)
+    got = S.solve_adjoint(w)
+    for (i, j) in S.modes:
+        if (i, j) == (0, 0):
+            M = S.mean_operator()
+            for c in (0, 2):
+                ref = M.T @ w[c, 0, 0].real
+                assert np.abs(got[c, 0, 0] - ref).max() <= 1e-14 * np.abs(ref).max()
+            assert not np.any(got[1, 0, 0])
+            continue
+        ref = (S.mode_operator(i, j).conj().T @ w[:, i, j, :].reshape(-1)).reshape(3, g.ny)
+        assert np.abs(got[:, i, j] - ref).max() <= 1e-14 * np.abs(ref).max(), (i, j)
