@@ -1,6 +1,7 @@
 """Build the HIP library libsp.so for gfx950 in-tree.
 
-Compiles every source under csrc/ with hipcc into paper_1804_05087_amd/libsp.so.
+Compiles every source under csrc/ with hipcc (one process per file, objects in
+_build/) and links paper_1804_05087_amd/libsp.so.
 Usage: python -m paper_1804_05087_amd.build  (or build() from Python).
 """
 from __future__ import annotations
@@ -34,16 +35,36 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build the library)")
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *FLAGS, "-I", os.path.join(HERE, "..", "include"), "-o", tmp, *srcs]
+def _compile(src: str, obj: str, verbose: bool) -> None:
+    cmd = [hipcc(), *FLAGS, "-c", "-I", os.path.join(HERE, "..", "include"), "-o", obj, src]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libsp.so")
+        raise RuntimeError(f"hipcc failed compiling {os.path.basename(src)}")
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compiles every source (one hipcc process per file, in parallel) and links
+    libsp.so; every call recompiles."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    objs = [os.path.join(objdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    jobs = jobs or min(len(srcs), os.cpu_count() or 1, 16)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for f in [ex.submit(_compile, s, o, verbose) for s, o in zip(srcs, objs)]:
+            f.result()
+    tmp = LIB + ".tmp"
+    cmd = [hipcc(), *[f for f in FLAGS if f != "-c"], "-o", tmp, *objs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed linking libsp.so")
     os.replace(tmp, LIB)
     return LIB
 

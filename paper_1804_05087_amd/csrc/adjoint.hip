@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(64)
   // mode record and weights (contiguous in LDS: hw = rec + stride) in one round
   // trip: all loads are issued before the first LDS store
   {
-    constexpr int RPL = (416 * E + 63) / 64;  // (13 ny + 12) / 64 for ny <= 32 E - 1
+    constexpr int RPL = solve_record_loads(E);
     const double* src = modedata + (size_t)mode * stride;
     const int tot = stride + 3 * n1;
     double rv[RPL];
@@ -341,7 +341,6 @@ __global__ void k_vjp_finish(double2* __restrict__ out, const double2* __restric
 
 // ----------------------------------- launchers -----------------------------------
 
-int solve_lanes_per_chain(int ny);
 
 hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out) {
   const Dims& d = p->d;

@@ -186,6 +186,14 @@ sp_status build_mode_data(sp_plan* p) {
   s = hip_check(p, hipMemcpy(p->d_hw, hw.data(), hw.size() * sizeof(double), hipMemcpyHostToDevice),
                 "upload hw");
   if (s) return s;
+  {
+    // the solve kernels stage record + weights with solve_record_loads(E)
+    // doubles per lane (E = elements per lane and parity chain, at most 5)
+    int E = solve_lanes_per_chain(p->d.ny);
+    if (E > 5) E = 5;
+    if (stride + 3 * p->d.ny > 64 * solve_record_loads(E))
+      return set_error(p, SP_ERR_SHAPE, "mode record does not fit the solve kernels' loads");
+  }
   p->mode_stride = stride;
   return SP_OK;
 }

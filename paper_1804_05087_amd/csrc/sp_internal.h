@@ -29,6 +29,12 @@ struct ModeLayout {
   __host__ __device__ int stride() const { return ((10 * n1 + 12) + 1) / 2 * 2; }
 };
 
+// Doubles each of the 64 lanes of the per-mode solve kernels loads to stage one
+// mode record and the three weight rows (stride + 3 ny = 13 ny + 12 values),
+// for E elements per lane and parity chain: enough up to ny = 32 E, the
+// largest (even) ny with E elements per lane.
+__host__ __device__ constexpr int solve_record_loads(int E) { return (416 * E + 12 + 63) / 64; }
+
 struct FFTPlan1D {
   int P = 0;
   int nrad = 0;
@@ -161,6 +167,8 @@ namespace sp {
 sp_status set_error(sp_plan* p, sp_status s, const std::string& msg);
 sp_status hip_check(sp_plan* p, hipError_t e, const char* what);
 sp_status build_mode_data(sp_plan* p);
+// elements per lane of a 16-lane row covering one parity chain (kernels.hip)
+int solve_lanes_per_chain(int ny);
 
 // kernel launchers (kernels.hip); all enqueue on p->stream
 hipError_t launch_synth_y(sp_plan* p, const double2* u, bool fp32);
