@@ -197,3 +197,19 @@ def random_spectral(nx: int, ny: int, nz: int, seed: int, scale: float = 1.0) ->
     shape = (3, nx, nz // 2 + 1, ny)
     a = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) * scale
     return hermitian_project(a)
+
+
+def regrid(a: np.ndarray, nx: int, ny: int, nz: int) -> np.ndarray:
+    """The canonical field a on another grid: Fourier modes and Chebyshev
+    coefficients present on both grids are copied, the others are zero
+    (spectral interpolation by zero padding, or truncation). The result has
+    zero Nyquist entries and keeps a's Hermitian m_z = 0 plane."""
+    a = np.asarray(a)
+    _, ax, azh, ay = a.shape
+    out = np.zeros((3, nx, nz // 2 + 1, ny), dtype=np.complex128)
+    hx = min(ax, nx) // 2          # |m_x| < hx on both grids
+    hz = min(azh - 1, nz // 2)     # m_z < hz on both grids
+    n = min(ay, ny)
+    for m in range(-(hx - 1), hx):
+        out[:, m % nx, :hz, :n] = a[:, m % ax, :hz, :n]
+    return hermitian_project(out)

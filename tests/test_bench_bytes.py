@@ -2,8 +2,11 @@
 duration (its roofline position), rebuilt here from the shapes of the arrays
 each kernel reads and writes at 48x65x48 (FP64): canonical fields are
 complex128 [3][nx][nz/2+1][ny], y-valued spectral fields complex [ny][nz/2][nx],
-x-physical fields complex [ny][3nx/2][nz/2], the solve's mode record
-10(N+1)+12 doubles per mode (rounded up to even) and the Chebyshev weights."""
+x-physical fields complex [ny][3nx/2][nz/2]. The solve is charged the phase
+traffic 9 S (S = one spectral field [nx][nz/2+1][ny] complex128): it reads the
+three product fields and u and writes Phi; its mode records (10(N+1)+12
+doubles per mode, rounded up to even, for every mode outside the Nyquist row
+and column) and the Chebyshev weights are reported apart."""
 import math
 
 import numpy as np
@@ -28,9 +31,15 @@ def test_algorithmic_bytes_48x65x48():
     assert ab["k_fft_x_inv"] == 5 * yv + 6 * xp
     assert ab["k_z_product"] == 9 * xp
     assert ab["k_fft_x_fwd"] == 3 * xp + 3 * yv
-    assert ab["k_stokes_solve"] == 3 * yv + 2 * canon + modes * record * 8 + 3 * ny * 8
+    S = _nbytes((nx, nz // 2 + 1, ny), 16)
+    assert ab["k_stokes_solve"] == 9 * S
+    assert 9 * S == 3 * canon
+    nonnyq = (nx - 1) * (nz // 2)
+    assert bench.solve_modes(w) == nonnyq == 1128
+    assert bench.record_bytes(w) == nonnyq * record * 8 + 3 * ny * 8
     # the figures quoted with the benchmark's roofline line
-    assert ab["k_stokes_solve"] == 17_439_000
+    assert ab["k_stokes_solve"] == 11_232_000
+    assert bench.record_bytes(w) == 5_975_448
     assert ab["k_synth_y"] == 9_584_640
     assert math.isclose(ab["k_fft_x_inv"] / 1e6, 16.77, abs_tol=0.005)
 
