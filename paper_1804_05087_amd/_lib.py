@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libsp.so")
 
 SP_OK = 0
 SP_ERR_NOT_CONVERGED = -5
+SP_ERR_NONFINITE = -6
 SP_FP64 = 0
 SP_MIXED = 1
 SP_OP_PHI = 0

@@ -28,6 +28,7 @@
 #include <cstring>
 #include <vector>
 
+#include "host_math.h"
 #include "sp_internal.h"
 
 using namespace sp;
@@ -343,119 +344,7 @@ double norm2(const double* v, int n) {
   return std::sqrt(s);
 }
 
-// The damped least-squares solution y(mu) = argmin ||R y - g||^2 + mu ||y||^2
-// for the k x k upper-triangular R (column-major, leading dimension ld): the
-// rows sqrt(mu) e_i are rotated into R with Givens rotations (no normal
-// equations, so the conditioning stays that of R), giving S upper triangular
-// with S^T S = R^T R + mu I and z = the rotated right-hand side; y = S^{-1} z
-// and q = S^{-T} y (for the Newton correction of mu). S row-major k x k.
-void damped_solve(const double* R, int ld, const double* g, int k, double mu,
-                  std::vector<double>& S, std::vector<double>& e, double* z, double* y,
-                  double* q) {
-  for (int i = 0; i < k; ++i) {
-    for (int j = 0; j < i; ++j) S[(size_t)i * k + j] = 0.0;
-    for (int j = i; j < k; ++j) S[(size_t)i * k + j] = R[(size_t)j * ld + i];
-    z[i] = g[i];
-  }
-  const double sm = std::sqrt(mu);
-  for (int i = 0; i < k; ++i) {
-    std::fill(e.begin() + i, e.begin() + k, 0.0);
-    e[i] = sm;
-    double t = 0.0;  // right-hand side of the extra row
-    for (int j = i; j < k; ++j) {
-      if (e[j] == 0.0) continue;
-      double* Sj = &S[(size_t)j * k];
-      const double r = std::hypot(Sj[j], e[j]);
-      const double c = Sj[j] / r, s = e[j] / r;
-      Sj[j] = r;
-      for (int l = j + 1; l < k; ++l) {
-        const double a = Sj[l], b = e[l];
-        Sj[l] = c * a + s * b;
-        e[l] = -s * a + c * b;
-      }
-      const double zj = z[j];
-      z[j] = c * zj + s * t;
-      t = -s * zj + c * t;
-    }
-  }
-  for (int i = k - 1; i >= 0; --i) {
-    double s2 = z[i];
-    const double* Si = &S[(size_t)i * k];
-    for (int j = i + 1; j < k; ++j) s2 -= Si[j] * y[j];
-    y[i] = s2 / Si[i];
-  }
-  for (int i = 0; i < k; ++i) {
-    double s2 = y[i];
-    for (int j = 0; j < i; ++j) s2 -= S[(size_t)j * k + i] * q[j];
-    q[i] = s2 / S[(size_t)i * k + i];
-  }
-}
-
-// The hookstep: y minimising ||g[0..k-1] - R y|| over ||y|| <= delta, given the
-// unconstrained minimiser yN. mu from Newton's method on 1/||y(mu)|| = 1/delta
-// (Hebden; More & Sorensen), which increases monotonically from mu = 0 when
-// ||yN|| > delta. Returns mu; y holds the step.
-double hook_solve(const double* R, int ld, const double* g, int k, const double* yN,
-                  double delta, double* y) {
-  const double nN = norm2(yN, k);
-  if (nN <= delta) {
-    std::copy(yN, yN + k, y);
-    return 0.0;
-  }
-  std::vector<double> S((size_t)k * k), e(k), z(k), q(k);
-  // mu = 0: S = R, y = yN, q = R^{-T} yN
-  for (int i = 0; i < k; ++i) {
-    double s2 = yN[i];
-    for (int j = 0; j < i; ++j) s2 -= R[(size_t)i * ld + j] * q[j];
-    q[i] = s2 / R[(size_t)i * ld + i];
-  }
-  double mu = 0.0, ny = nN, nq = norm2(q.data(), k);
-  std::copy(yN, yN + k, y);
-  double lo = 0.0, hi = HUGE_VAL;
-  for (int it = 0; it < 100; ++it) {
-    if (std::fabs(ny - delta) <= 1e-13 * delta) break;
-    if (ny > delta) lo = mu; else hi = mu;
-    double mn = mu + (ny / nq) * (ny / nq) * (ny - delta) / delta;
-    if (!(mn > lo && mn < hi)) mn = std::isfinite(hi) ? 0.5 * (lo + hi) : 2.0 * lo + 1e-300;
-    if (mn == mu) break;
-    mu = mn;
-    damped_solve(R, ld, g, k, mu, S, e, z.data(), y, q.data());
-    ny = norm2(y, k);
-    nq = norm2(q.data(), k);
-  }
-  return mu;
-}
-
-// ||g[0..k-1] - R y||^2 + g[k]^2: the GMRES model's squared residual at y
-double model_res2(const double* R, int ld, const double* g, int k, const double* y) {
-  double s = g[k] * g[k];
-  for (int i = 0; i < k; ++i) {
-    double t = g[i];
-    for (int j = i; j < k; ++j) t -= R[(size_t)j * ld + i] * y[j];
-    s += t * t;
-  }
-  return s;
-}
-
 }  // namespace
-
-extern "C" sp_status sp_hook_step(const double* R, int32_t ld, const double* g, int32_t k,
-                                  double delta, double* y, double* mu, double* model_res) {
-  if (!R || !g || !y || !mu || !model_res || k < 1 || ld < k || !(delta > 0))
-    return SP_ERR_INVALID;
-  for (int i = 0; i < k; ++i)
-    if (!(R[(size_t)i * ld + i] != 0.0) || !std::isfinite(R[(size_t)i * ld + i]))
-      return SP_ERR_INVALID;
-  std::vector<double> yN(k);
-  for (int i = k - 1; i >= 0; --i) {
-    double s2 = g[i];
-    for (int j = i + 1; j < k; ++j) s2 -= R[(size_t)j * ld + i] * yN[j];
-    yN[i] = s2 / R[(size_t)i * ld + i];
-  }
-  *mu = hook_solve(R, ld, g, k, yN.data(), delta, y);
-  *model_res = std::sqrt(model_res2(R, ld, g, k, y));
-  return SP_OK;
-}
 
 extern "C" sp_status sp_symmetrize(sp_plan* p, double* field) {
   if (!p) return SP_ERR_INVALID;

@@ -1,0 +1,29 @@
+"""The library's host-only numerics (host_math.cpp: the hookstep subproblem
+and the advected per-mode operators) built with g++ under AddressSanitizer and
+UndefinedBehaviorSanitizer and run on valid and invalid arguments (CPU only;
+no device code is involved)."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1804_05087_amd", "csrc")
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_host_math_under_asan_ubsan(tmp_path):
+    exe = tmp_path / "host_sanitize"
+    cmd = ["g++", "-std=c++17", "-g", "-O1", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-I", os.path.join(ROOT, "include"),
+           os.path.join(ROOT, "tests", "host_sanitize_driver.cpp"),
+           os.path.join(CSRC, "host_math.cpp"), "-o", str(exe)]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    res = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=300)
+    assert res.returncode == 0, res.stdout + res.stderr
+    assert "all checks passed" in res.stdout
+    assert "runtime error" not in res.stderr and "AddressSanitizer" not in res.stderr
