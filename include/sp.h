@@ -174,6 +174,20 @@ sp_status sp_stokes_solve(sp_plan* plan, const double* g, double* out, int32_t i
  * alias u. */
 sp_status sp_befe_step(sp_plan* plan, const double* u, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): Phi_dt(u)
+ * exactly as sp_befe_step computes it (same kernels, same result), with the
+ * intermediates of the transforms in a fixed array of the library's own device
+ * memory instead of the plan's scratch. The array holds 32 MiB per device and
+ * stays allocated until the process ends; its address is looked up while the
+ * first plan on a device is created, and this call allocates nothing.
+ * SP_ERR_SHAPE if the grid's intermediates exceed 32 MiB (48x65x48 needs
+ * 27 MB), SP_ERR_INVALID for the advected step (sp_plan_set_advection) or NULL
+ * pointers, SP_ERR_HIP if the array's address could not be obtained. Every call
+ * on one device uses the same array: calls that overlap on one device (other
+ * streams or plans) race, and the caller must order them. out may alias u. */
+sp_status sp_befe_step_noalloc(sp_plan* plan, const double* u, double* out);
+
 /* r = (Phi_dt(u) - u)/dt, FP64. If host_norm != NULL, synchronises and stores
  * the volume-normalised L2 norm sqrt((1/V) int |r|^2 dV) there (returns
  * SP_ERR_NONFINITE if it is NaN/Inf). r_out must not alias u. */

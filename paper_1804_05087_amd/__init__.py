@@ -171,6 +171,14 @@ class Plan:
         self._check(self.lib.sp_befe_step(self.h, self._field(u, "u"), self._field(out, "out")))
         return out
 
+    def befe_step_noalloc(self, u, out):
+        """Phi_dt(u) into out with the intermediates in the library's fixed
+        per-device scratch (sp_befe_step_noalloc): no device allocation; calls
+        that overlap on one device race."""
+        self._check(self.lib.sp_befe_step_noalloc(self.h, self._field(u, "u"),
+                                                  self._field(out, "out")))
+        return out
+
     def residual(self, u, out=None, norm: bool = False):
         out = self.empty() if out is None else out
         nrm = C.c_double(0.0)

@@ -82,6 +82,7 @@ SIGNATURES = {
     "sp_nonlinear": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "sp_stokes_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "sp_befe_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sp_befe_step_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "sp_residual": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "sp_norm": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "sp_linearize": (C.c_int, [C.c_void_p, C.c_void_p]),

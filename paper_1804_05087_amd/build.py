@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsp.so")
-SOURCES = ["plan.cpp", "api.cpp", "newton.cpp", "host_math.cpp", "kernels.hip", "adjoint.hip", "ycontract.hip", "zline.hip", "xline.hip", "blas.hip", "advect.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "newton.cpp", "host_math.cpp", "kernels.hip", "adjoint.hip", "ycontract.hip", "zline.hip", "xline.hip", "blas.hip", "advect.hip", "noalloc.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

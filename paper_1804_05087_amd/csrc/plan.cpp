@@ -273,6 +273,17 @@ extern "C" sp_status sp_plan_create(const sp_params* prm, void* hip_stream, sp_p
   p->prm = q;
   p->stream = (hipStream_t)hip_stream;
   p->precision = q.precision;
+  {
+    // the device the plan works on: the library's per-device set-up runs here
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+      (void)hipGetLastError();
+      delete p;
+      return SP_ERR_HIP;
+    }
+    p->device = dev;
+    noalloc_setup(dev);
+  }
   Dims& d = p->d;
   d.nx = q.nx;
   d.ny = q.ny;

@@ -79,6 +79,7 @@ struct sp_plan {
   sp_params prm;
   sp::Dims d;
   hipStream_t stream = nullptr;
+  int device = -1;  // current device when the plan was created
   int precision = SP_FP64;
   std::string last_error;
 
@@ -162,6 +163,12 @@ struct sp_plan {
 };
 
 namespace sp {
+
+// scratch-free Phi (noalloc.hip): per-device set-up of the file-scope scratch
+// array (called by sp_plan_create with the plan's device current) and the
+// bytes of intermediates one evaluation on grid d needs there
+void noalloc_setup(int device);
+size_t noalloc_bytes_needed(const Dims& d);
 
 // host helpers (plan.cpp)
 sp_status set_error(sp_plan* p, sp_status s, const std::string& msg);

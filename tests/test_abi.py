@@ -54,6 +54,7 @@ def test_plan_create_validates_on_host(lib, override, status):
 def test_null_arguments(lib):
     assert lib.sp_plan_create(None, None, None) == -1
     assert lib.sp_befe_step(None, None, None) == -1
+    assert lib.sp_befe_step_noalloc(None, None, None) == -1
     # every entry point that takes a plan rejects a null one before any device call
     assert lib.sp_jacobian_columns(None, 0, 0, 1, None, 1) == -1
     assert lib.sp_symmetrize(None, None) == -1
