@@ -282,8 +282,11 @@ __global__ void __launch_bounds__(256)
 // halves in y (Tinv[n][N-j] = (-1)^n Tinv[n][j]), so each lane forms its
 // coefficients n from N/2+1 terms; tinv is the folded half transposed,
 // th[j][n] = Tinv[n][j], so the lanes' loads are contiguous.
+// Two-wave blocks are held to at most 168 VGPRs (3 waves per SIMD), so that
+// every mode's block is resident at once at 48x65x48 (2 x 1128 waves).
 template <int E, int AN>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(AN != 0 ? 128 : 64)
+    __attribute__((amdgpu_waves_per_eu(AN != 0 ? 3 : 1)))
     k_stokes_solve(const double2* __restrict__ g, double2* __restrict__ out,
                    const double* __restrict__ modedata, const double* __restrict__ hw_g,
                    int stride, int nx, int ny, int nzh, double alpha, double gamma, double re,
@@ -308,7 +311,9 @@ __global__ void __launch_bounds__(64)
   const int jh = (ny - 1) / 2 + 1;  // folded column length (AN != 0)
   const int jh8 = (jh + 7) & ~7;    // padded with zeros to whole groups of 8
   cd* colE = Dm + n1;               // [3][jh8] even halves f_j + f_{N-j}
-  cd* colO = colE + 3 * jh8;        // [3][jh8] odd halves  f_j - f_{N-j}
+  // odd halves f_j - f_{N-j} ([3][jh8]), 64 bytes past the even ones so that
+  // the two addresses an analysis load broadcasts fall in different banks
+  cd* colO = colE + 3 * jh8 + 4;
 
   // logical order: x mode fastest, so the modes whose product-field entries
   // share a cache line (consecutive m_x at one m_z) run on one XCD
@@ -316,13 +321,20 @@ __global__ void __launch_bounds__(64)
   const int j = lo / nx;
   const int i = lo - j * nx;
   const int mode = i * nzh + j;
-  const int tid = threadIdx.x;
+  // With the fused analysis (AN != 0) a mode has two waves: wave 1 loads half of
+  // the record and sums half of the analysis' terms, hands its partial sums to
+  // wave 0, and from then on only takes part in the barriers (a wave-uniform
+  // branch skips its work); wave 0 does everything else.
+  constexpr int NW = (AN != 0) ? 2 : 1;
+  const int tid = threadIdx.x & 63;
+  const bool shadow = (threadIdx.x >> 6) != 0;
   const int row = tid >> 4;
   const int l = tid & 15;
   const size_t cs = (size_t)nx * nzh * ny;  // component stride
   const size_t mo = ((size_t)i * nzh + j) * ny;
   const bool nyq = (i == nx / 2) || (j == nzh - 1);
   if (nyq) {
+    if (shadow) return;  // uniform per block: both waves leave
     for (int n = tid; n < n1; n += 64) {
       out[mo + n] = make_double2(0.0, 0.0);
       out[cs + mo + n] = make_double2(0.0, 0.0);
@@ -369,14 +381,17 @@ __global__ void __launch_bounds__(64)
   // f_jj and f_{N-jj}; issued before the record loads so both overlap
   using RA = typename std::conditional<AN == 2, float, double>::type;
   using CA = typename V2<RA>::T;
-  CA fa[2][3], fb[2][3];
+  // folded column entries per lane: jj = tid + 64 q, q < QF; jh <= 64 up to
+  // ny = 128 (E <= 4), so only E = 5 needs a second set
+  constexpr int QF = (E >= 5) ? 2 : 1;
+  CA fa[QF][3], fb[QF][3];
   if constexpr (AN != 0) {
     const CA* nv = reinterpret_cast<const CA*>(nv_raw);
     const int nzm = nzh - 1;
     const size_t cstride = (size_t)ny * nzm * nx;
     const size_t base = (size_t)j * nx + i;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < QF; ++q) {
       const int jj = tid + 64 * q;
       const int jc = jj < jh ? jj : jh - 1;
 #pragma unroll
@@ -389,22 +404,22 @@ __global__ void __launch_bounds__(64)
   // mode record and weights (contiguous in LDS: hw = rec + stride) in one round
   // trip: all loads are issued before the first LDS store
   {
-    constexpr int RPL = solve_record_loads(E);
+    constexpr int RPL = (solve_record_loads(E) + NW - 1) / NW;
     const double* src = modedata + (size_t)mode * stride;
     const int tot = stride + 3 * n1;
     double rv[RPL];
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
-      const int t = tid + 64 * q;
+      const int t = threadIdx.x + 64 * NW * q;
       const int tc = t < tot ? t : tot - 1;
       rv[q] = (tc < stride) ? src[tc] : hw_g[tc - stride];
     }
     if constexpr (AN != 0) {
       // even / odd halves, zero padded to jh8 entries
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < QF; ++q) {
         const int jj = tid + 64 * q;
-        if (jj < jh8) {
+        if (jj < jh8 && !shadow) {
           const double in = jj < jh ? 1.0 : 0.0;
           const double same = (jj == N - jj) ? 0.0 : 1.0;  // middle point counted once
 #pragma unroll
@@ -418,7 +433,7 @@ __global__ void __launch_bounds__(64)
     }
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
-      const int t = tid + 64 * q;
+      const int t = threadIdx.x + 64 * NW * q;
       if (t < tot) rec[t] = rv[q];
     }
   }
@@ -428,6 +443,12 @@ __global__ void __launch_bounds__(64)
     const R* Ti = reinterpret_cast<const R*>(tinv_raw);
     __syncthreads();
     const int tmax = (N - 2) / 64 + 1;  // passes over n <= N-2 (uniform)
+    // groups of 8 folded terms: wave 0 sums [0, gsplit), wave 1 [gsplit, ng)
+    const int ng = jh8 / 8;
+    const int gsplit = (NW == 2) ? (ng + 1) / 2 : ng;
+    const int gbeg = shadow ? gsplit : 0;
+    const int gend = shadow ? ng : gsplit;
+    R* part = reinterpret_cast<R*>(colO + 3 * jh8);  // [6][64] partial sums of wave 1
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       if (t >= tmax) {
@@ -440,27 +461,57 @@ __global__ void __launch_bounds__(64)
       const R* col = Ti + nc;  // th[j][n]: consecutive n across lanes
       R a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0;
       {
-        for (int j0 = 0; j0 < jh8; j0 += 8) {  // branch-free: padded entries are zero
-          R tv[8];
+        // the table entries of the next group of 8 are loaded while this group
+        // is summed (indexes clamped into the table, so the last prefetch is a
+        // harmless re-read)
+        R tv[8], tn[8];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) tv[q] = col[(size_t)(j0 + q < jh ? j0 + q : jh - 1) * ny];
-          cd e0[8], e1[8], e2[8];
+        for (int q = 0; q < 8; ++q)
+          tv[q] = col[(size_t)(8 * gbeg + q < jh ? 8 * gbeg + q : jh - 1) * ny];
+        for (int j0 = 8 * gbeg; j0 < 8 * gend; j0 += 8) {  // padded entries are zero
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            e0[q] = src[j0 + q];
-            e1[q] = src[jh8 + j0 + q];
-            e2[q] = src[2 * jh8 + j0 + q];
+          for (int q = 0; q < 8; ++q)
+            tn[q] = col[(size_t)(j0 + 8 + q < jh ? j0 + 8 + q : jh - 1) * ny];
+#pragma unroll
+          for (int h = 0; h < 8; h += 4) {  // two halves of 4 terms (register pressure)
+            cd e0[4], e1[4], e2[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              e0[q] = src[j0 + h + q];
+              e1[q] = src[jh8 + j0 + h + q];
+              e2[q] = src[2 * jh8 + j0 + h + q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              a0r += tv[h + q] * (R)e0[q].re;
+              a0i += tv[h + q] * (R)e0[q].im;
+              a1r += tv[h + q] * (R)e1[q].re;
+              a1i += tv[h + q] * (R)e1[q].im;
+              a2r += tv[h + q] * (R)e2[q].re;
+              a2i += tv[h + q] * (R)e2[q].im;
+            }
           }
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            a0r += tv[q] * (R)e0[q].re;
-            a0i += tv[q] * (R)e0[q].im;
-            a1r += tv[q] * (R)e1[q].re;
-            a1i += tv[q] * (R)e1[q].im;
-            a2r += tv[q] * (R)e2[q].re;
-            a2i += tv[q] * (R)e2[q].im;
-          }
+          for (int q = 0; q < 8; ++q) tv[q] = tn[q];
         }
+      }
+      if constexpr (NW == 2) {
+        if (shadow) {
+          part[tid] = a0r;
+          part[64 + tid] = a0i;
+          part[128 + tid] = a1r;
+          part[192 + tid] = a1i;
+          part[256 + tid] = a2r;
+          part[320 + tid] = a2i;
+        }
+        __syncthreads();
+        a0r += part[tid];
+        a0i += part[64 + tid];
+        a1r += part[128 + tid];
+        a1i += part[192 + tid];
+        a2r += part[256 + tid];
+        a2i += part[320 + tid];
+        __syncthreads();  // the next pass rewrites part
       }
       const double keep = n <= N - 2 ? 1.0 : 0.0;
       const double2 x0 = ga[t], x1 = gb[t], x2 = gc[t];
@@ -469,20 +520,23 @@ __global__ void __launch_bounds__(64)
       gc[t] = make_double2(((double)a2r + xa * x2.x) * keep, ((double)a2i + xa * x2.y) * keep);
     }
   }
+  const bool work = !shadow;  // wave-uniform: wave 1 only meets the barriers below
+  if (work) {
 #pragma unroll
-  for (int t = 0; t < 3; ++t) {
-    const int n = tid + 64 * t;
-    if (n < n1) {
-      const cd fu(re * ga[t].x, re * ga[t].y);
-      const cd fv(re * gb[t].x, re * gb[t].y);
-      const cd fw(re * gc[t].x, re * gc[t].y);
-      if (mean) {
-        Rv[n] = -fu;  // (0,0): u and w solve Dirichlet Helmholtz problems
-        Rp[n] = -fw;
-      } else {
-        Fpar[n] = (fu * kx + fw * kz) * ik;
-        Rp[n] = -((fu * kz - fw * kx) * ik);  // -F_perp
-        Fv[n] = fv;
+    for (int t = 0; t < 3; ++t) {
+      const int n = tid + 64 * t;
+      if (n < n1) {
+        const cd fu(re * ga[t].x, re * ga[t].y);
+        const cd fv(re * gb[t].x, re * gb[t].y);
+        const cd fw(re * gc[t].x, re * gc[t].y);
+        if (mean) {
+          Rv[n] = -fu;  // (0,0): u and w solve Dirichlet Helmholtz problems
+          Rp[n] = -fw;
+        } else {
+          Fpar[n] = (fu * kx + fw * kz) * ik;
+          Rp[n] = -((fu * kz - fw * kx) * ik);  // -F_perp
+          Fv[n] = fv;
+        }
       }
     }
   }
@@ -494,42 +548,49 @@ __global__ void __launch_bounds__(64)
   const int pv = row & 1;  // v parity (rows 0, 1), u_perp / w parity (rows 2, 3)
   const int po = 1 - pv;
   if (mean) {
-    cd bu(0.0);
-    if (inhomogeneous && vrow) bu = cd(pv == 0 ? 0.5 * (wu + wl) : 0.5 * (wu - wl));
-    wsweep<E>(helm, hw, N, pv, vrow ? Rv : Rp, bu, vrow ? P : U, l);
+    if (work) {
+      cd bu(0.0);
+      if (inhomogeneous && vrow) bu = cd(pv == 0 ? 0.5 * (wu + wl) : 0.5 * (wu - wl));
+      wsweep<E>(helm, hw, N, pv, vrow ? Rv : Rp, bu, vrow ? P : U, l);
+    }
   } else {
-    wderiv<E>(N, pv, vrow ? Fv : Rp, vrow ? A : Dm, l);
+    if (work) wderiv<E>(N, pv, vrow ? Fv : Rp, vrow ? A : Dm, l);
     __syncthreads();
-    if (vrow) SP_ROW_PAR(po, divF[n] = mul_i(Fpar[n] * k) + A[n];)
+    if (work && vrow) SP_ROW_PAR(po, divF[n] = mul_i(Fpar[n] * k) + A[n];)
     __syncthreads();
     // P = Pois(div F) on rows 0, 1; U = Helm(-F_perp) on rows 2, 3
-    wsweep<E>(SweepView(rec + (vrow ? L.pois() : L.helm()), n1), hw, N, vrow ? po : pv, vrow ? divF : Rp, cd(0.0),
-              vrow ? P : U, l);
+    if (work)
+      wsweep<E>(SweepView(rec + (vrow ? L.pois() : L.helm()), n1), hw, N, vrow ? po : pv,
+                vrow ? divF : Rp, cd(0.0), vrow ? P : U, l);
     __syncthreads();
-    wderiv<E>(N, po, vrow ? P : Rp, vrow ? A : Dm, l);
+    if (work) wderiv<E>(N, po, vrow ? P : Rp, vrow ? A : Dm, l);
     __syncthreads();
-    if (vrow) SP_ROW_PAR(pv, Rv[n] = A[n] - Fv[n];)
+    if (work && vrow) SP_ROW_PAR(pv, Rv[n] = A[n] - Fv[n];)
     __syncthreads();
-    wsweep<E>(helm, hw, N, pv, vrow ? Rv : Rp, cd(0.0), vrow ? V : Dm, l);
+    if (work) wsweep<E>(helm, hw, N, pv, vrow ? Rv : Rp, cd(0.0), vrow ? V : Dm, l);
     __syncthreads();
     // influence correction: (c_delta, c_b) = -Minv (D v(1), tau definition)
-    cd la(0.0);
-    SP_ROW_PAR(pv, la = la + V[n] * ((double)n * n);)
-    la = row_sum(la);
-    const int m = (N % 2 == pv) ? N : N - 1;
-    cd lb = V[m] * lam;
-    if (m == N - 1) lb = lb + P[N] * (2.0 * N);
-    const double* Mi = rec + L.minv() + 4 * pv;
-    const cd ca = -(la * Mi[0] + lb * Mi[1]);
-    const cd cb = -(la * Mi[2] + lb * Mi[3]);
+    cd ca(0.0), cb(0.0);
+    if (work) {
+      cd la(0.0);
+      SP_ROW_PAR(pv, la = la + V[n] * ((double)n * n);)
+      la = row_sum(la);
+      const int m = (N % 2 == pv) ? N : N - 1;
+      cd lb = V[m] * lam;
+      if (m == N - 1) lb = lb + P[N] * (2.0 * N);
+      const double* Mi = rec + L.minv() + 4 * pv;
+      ca = -(la * Mi[0] + lb * Mi[1]);
+      cb = -(la * Mi[2] + lb * Mi[3]);
+    }
     const double* vdel = rec + L.vdel();
     const double* vb = rec + L.vb();
     __syncthreads();
-    if (vrow) SP_ROW_PAR(pv, V[n] = V[n] + ca * vdel[n] + cb * vb[n];)
+    if (work && vrow) SP_ROW_PAR(pv, V[n] = V[n] + ca * vdel[n] + cb * vb[n];)
     __syncthreads();
-    wderiv<E>(N, pv, vrow ? V : Rp, vrow ? A : Dm, l);
+    if (work) wderiv<E>(N, pv, vrow ? V : Rp, vrow ? A : Dm, l);
   }
   __syncthreads();
+  if (!work) return;
   for (int n = tid; n < n1; n += 64) {
     cd uo, vo, wo;
     if (mean) {
@@ -784,7 +845,8 @@ static size_t solve_lds_bytes(const sp_plan* p, bool fused) {
   const Dims& d = p->d;
   const int jh8 = (((d.ny - 1) / 2 + 1) + 7) & ~7;
   return (size_t)p->mode_stride * sizeof(double) + 3 * (size_t)d.ny * sizeof(double) +
-         10 * (size_t)d.ny * sizeof(cd) + (fused ? 6 * (size_t)jh8 * sizeof(cd) : 0);
+         10 * (size_t)d.ny * sizeof(cd) +
+         (fused ? (6 * (size_t)jh8 + 4) * sizeof(cd) + 6 * 64 * sizeof(double) : 0);
 }
 
 #define SP_SOLVE_DISPATCH(LAUNCH)                   \
@@ -819,12 +881,12 @@ hipError_t launch_analysis_solve(sp_plan* p, const double2* x, double xa, double
   SP_PROF_BEGIN(p, KID_SOLVE);
 #define SP_SOLVE_LAUNCH(EV)                                                                       \
   if (fp32)                                                                                       \
-    hipLaunchKernelGGL((k_stokes_solve<EV, 2>), dim3(d.nx * d.nzh), dim3(64), sh, p->stream,      \
+    hipLaunchKernelGGL((k_stokes_solve<EV, 2>), dim3(d.nx * d.nzh), dim3(128), sh, p->stream,      \
                        nullptr, out, p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh,      \
                        d.alpha, d.gamma, d.re, d.inv_dt, d.wall_upper, d.wall_lower,             \
                        inhomogeneous, p->nv, p->f_tinv_th, x, xa);                                   \
   else                                                                                            \
-    hipLaunchKernelGGL((k_stokes_solve<EV, 1>), dim3(d.nx * d.nzh), dim3(64), sh, p->stream,      \
+    hipLaunchKernelGGL((k_stokes_solve<EV, 1>), dim3(d.nx * d.nzh), dim3(128), sh, p->stream,      \
                        nullptr, out, p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh,      \
                        d.alpha, d.gamma, d.re, d.inv_dt, d.wall_upper, d.wall_lower,             \
                        inhomogeneous, p->nv, p->d_tinv_th, x, xa)
