@@ -54,10 +54,10 @@ SOLVE_SOURCES = ["kernels.hip", "solve_row.h", "solve_core.h", "device_common.h"
 MEASURED_TRAFFIC = {
     "couette_48x65x48_re1000_dt100": {
         "k_stokes_solve": {
-            "fetch_kib": 6771.4, "write_kib": 3676.0,
-            # 256 MiB copy: FETCH_SIZE 131089.9 KiB, WRITE_SIZE 262144.0 KiB
-            "fetch_factor": 262144.0 / 131089.9, "write_factor": 1.0,
-            "sources_sha256": "3675b171074a9907ac5ec1300931d448b875a207841a8168e189c9ff23958431",
+            "fetch_kib": 6763.0, "write_kib": 3674.3,
+            # 256 MiB copy: FETCH_SIZE 131092.1 KiB, WRITE_SIZE 262144.0 KiB
+            "fetch_factor": 262144.0 / 131092.1, "write_factor": 1.0,
+            "sources_sha256": "1977ec6f330c80299cf0cd4cd8ca847d856773426f91a98b941ce4914243c066",
         },
     },
 }
@@ -781,9 +781,10 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-newton", action="store_true")
-    ap.add_argument("--newton-krylov", type=int, default=400,
+    ap.add_argument("--newton-krylov", type=int, default=600,
                     help="Krylov cap per Newton step (from the continued equilibrium at "
-                         "48x65x48, Re 1000, a cap of 200 stalls near ||r|| = 2e-7)")
+                         "48x65x48, Re 1000: caps of 200-350 stall before 1e-10; 400 is "
+                         "fastest with FP64 actions, 600 with the FP32 basis)")
     ap.add_argument("--newton-max", type=int, default=16)
     ap.add_argument("--newton-rtol", type=float, default=1e-4)
     ap.add_argument("--newton-energy", type=float, default=0.0,
