@@ -165,6 +165,96 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// The same contraction with 16 modes per wave: each lane loads one complex
+// coefficient (16 bytes) per k-step and feeds its real part to one MFMA column
+// group and its imaginary part to a second, so the two groups share every A
+// fragment, each lane issues half the loads per output value of
+// k_ysynth_mfma, and each output row of the wave is one contiguous run of 16
+// complex values (stored as pairs).
+template <typename R, int KS>
+__global__ void __launch_bounds__(256)
+    k_ysynth_mfma2(const double2* __restrict__ u, SynthSpec<R> spec, R* __restrict__ out,
+                   int nx, int ny, int nzh, int nzm) {
+  using MF = Mfma<R>;
+  using C = typename V2<R>::T;
+  const int lane = threadIdx.x & 63;
+  const int kq = lane >> 4;
+  const int nq = nzm * nx;
+  const Blk3 bk = ycontract_block();
+  const int g = bk.z;
+  const int q0 = (bk.x * 4 + (threadIdx.x >> 6)) * 16;
+  const int q = q0 + (lane & 15);
+  const bool qv = q < nq;
+  const size_t fstride = (size_t)ny * nq * 2;
+  R br[KS], bi[KS];
+  {
+    const int qc = qv ? q : nq - 1;
+    const int kz = qc / nx;
+    const int mx = qc - kz * nx;
+    const double2* src = u + (((size_t)spec.comp[g] * nx + mx) * nzh + kz) * ny;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int n = 4 * s + kq;
+      const double2 v = src[n < ny ? n : ny - 1];
+      const R m = (R)((qv && n < ny) ? 1 : 0);
+      br[s] = (R)v.x * m;
+      bi[s] = (R)v.y * m;
+    }
+  }
+  const int nt = ny >> 4;
+  const int t = bk.y;
+  for (int mi = 0; mi < spec.nmat[g]; ++mi) {
+    const YMat<R> M = spec.mat[g][mi];
+    R* o = out + (size_t)spec.field[g][mi] * fstride + 2 * (size_t)q;
+    if (t < nt) {
+      const R* fa = M.frag + (size_t)t * KS * 64 + lane;
+      R a[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) a[s] = fa[s * 64];
+      typename MF::acc_t accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        accr = MF::mma(a[s], br[s], accr);
+        acci = MF::mma(a[s], bi[s], acci);
+      }
+      if (qv) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          C v;
+          v.x = accr[i];
+          v.y = acci[i];
+          *reinterpret_cast<C*>(o + (size_t)(16 * t + MF::drow(kq, i)) * nq * 2) = v;
+        }
+      }
+    }
+    if (t == (int)gridDim.y - 1) {
+      for (int y = 16 * nt; y < ny; ++y) {
+        const R* mrow = M.full + (size_t)y * M.rs;
+        R mv[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const int n = 4 * s + kq;
+          mv[s] = mrow[(size_t)(n < ny ? n : ny - 1) * M.cs];
+        }
+        R pr = 0, pi = 0;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {  // br, bi = 0 past ny
+          pr += mv[s] * br[s];
+          pi += mv[s] * bi[s];
+        }
+        pr = sum_kphase(pr);
+        pi = sum_kphase(pi);
+        if (kq == 0 && qv) {
+          C v;
+          v.x = pr;
+          v.y = pi;
+          *reinterpret_cast<C*>(o + (size_t)y * nq * 2) = v;
+        }
+      }
+    }
+  }
+}
+
 // Loaders of the A operand of k_ycoef_mfma: the real part (ri = 0) or
 // imaginary part (ri = 1) of term t of component c at y-index j, mode q.
 template <typename R>
@@ -427,19 +517,20 @@ static dim3 ycoef_grid(const Dims& d, int* nqb) {
 
 hipError_t launch_synth_tab(sp_plan* p, const double2* u, int which, void* out, bool fp32) {
   const Dims& d = p->d;
-  const dim3 grid = ycontract_grid(d);
+  dim3 grid = ycontract_grid(d);
+  grid.x = (d.nzm * d.nx + 63) / 64;  // 64 modes per block (k_ysynth_mfma2)
   SP_PROF_BEGIN(p, KID_SYNTH_Y);
   if (fp32) {
     const SynthSpec<float> sp = synth_spec<float>(p, which);
 #define L32(KS)                                                                                  \
-  hipLaunchKernelGGL((k_ysynth_mfma<float, KS>), grid, dim3(256), 0, p->stream, u, sp,           \
+  hipLaunchKernelGGL((k_ysynth_mfma2<float, KS>), grid, dim3(256), 0, p->stream, u, sp,          \
                      (float*)out, d.nx, d.ny, d.nzh, d.nzm)
     SP_KS_DISPATCH(d.ny, L32);
 #undef L32
   } else {
     const SynthSpec<double> sp = synth_spec<double>(p, which);
 #define L64(KS)                                                                                  \
-  hipLaunchKernelGGL((k_ysynth_mfma<double, KS>), grid, dim3(256), 0, p->stream, u, sp,          \
+  hipLaunchKernelGGL((k_ysynth_mfma2<double, KS>), grid, dim3(256), 0, p->stream, u, sp,         \
                      (double*)out, d.nx, d.ny, d.nzh, d.nzm)
     SP_KS_DISPATCH(d.ny, L64);
 #undef L64
