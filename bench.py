@@ -113,10 +113,11 @@ def algorithmic_bytes(w, fp32=False, jvp=False):
 
 
 def record_bytes(w):
-    """Per-mode solve records (sweep factors, influence solutions, 2x2 inverse
-    influence matrices) and the three weight rows read by one solve launch."""
+    """Per-mode solve records (sweep factors of the two operators, influence
+    solutions, 2x2 inverse influence matrices: 6 (N+1) + 12 doubles) and the
+    three weight rows read by one solve launch."""
     n1 = w["ny"]
-    stride = ((10 * n1 + 12) + 1) // 2 * 2
+    stride = ((6 * n1 + 12) + 1) // 2 * 2
     return solve_modes(w) * stride * 8 + 3 * n1 * 8
 
 

@@ -147,8 +147,8 @@ __global__ void __launch_bounds__(64)
   }
   __syncthreads();
   const ModeLayout L{n1};
-  const SweepView helm(rec + L.helm(), n1);
-  const SweepView pois(rec + L.pois(), n1);
+  const SweepRec helm(rec + L.helm(), n1, lam);
+  const SweepRec pois(rec + L.pois(), n1, k2);
   const bool vrow = row < 2;
   const int pv = row & 1;  // v parity (rows 0, 1), u_perp / w parity (rows 2, 3)
   const int po = 1 - pv;
@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(64)
     if (vrow) SP_ROW_PAR(po, Pb[n] = Pb[n] + Tm[n];)
     __syncthreads();
     // P = Pois(div F), div F = i k F_par + D F_v
-    wsweep_T<E>(SweepView(rec + (vrow ? L.pois() : L.helm()), n1), hw, N, vrow ? po : pv, vrow ? Pb : Ub, vrow ? Db : Dm,
+    wsweep_T<E>(vrow ? pois : helm, hw, N, vrow ? po : pv, vrow ? Pb : Ub, vrow ? Db : Dm,
                 vrow ? W : W2, l);
     if (vrow) SP_ROW_PAR(po, Fpb[n] = mul_i(-Db[n]) * k;)
     __syncthreads();

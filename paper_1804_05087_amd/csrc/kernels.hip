@@ -542,8 +542,8 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
   }
   __syncthreads();
   const ModeLayout L{n1};
-  const SweepView helm(rec + L.helm(), n1);
-  const SweepView pois(rec + L.pois(), n1);
+  const SweepRec helm(rec + L.helm(), n1, lam);
+  const SweepRec pois(rec + L.pois(), n1, k2);
   const bool vrow = row < 2;
   const int pv = row & 1;  // v parity (rows 0, 1), u_perp / w parity (rows 2, 3)
   const int po = 1 - pv;
@@ -560,7 +560,7 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
     __syncthreads();
     // P = Pois(div F) on rows 0, 1; U = Helm(-F_perp) on rows 2, 3
     if (work)
-      wsweep<E>(SweepView(rec + (vrow ? L.pois() : L.helm()), n1), hw, N, vrow ? po : pv,
+      wsweep<E>(vrow ? pois : helm, hw, N, vrow ? po : pv,
                 vrow ? divF : Rp, cd(0.0), vrow ? P : U, l);
     __syncthreads();
     if (work) wderiv<E>(N, po, vrow ? P : Rp, vrow ? A : Dm, l);

@@ -141,6 +141,17 @@ static void influence_class(int N, double k, double lam, const double* helm, con
   (void)k;
 }
 
+// The record's sweep block (inv_den, Q, inv_sum) from a full factorisation
+// block (inv_den, cc, q, Q, inv_sum) of sweep_factor.
+static void compact_sweep(const double* full, int n1, double* out) {
+  for (int n = 0; n < n1; ++n) {
+    out[n] = full[n];               // inv_den
+    out[n1 + n] = full[3 * n1 + n];  // Q
+  }
+  out[2 * n1] = full[4 * n1];
+  out[2 * n1 + 1] = full[4 * n1 + 1];
+}
+
 sp_status build_mode_data(sp_plan* p) {
   const Dims& d = p->d;
   const int N = d.N;
@@ -151,6 +162,7 @@ sp_status build_mode_data(sp_plan* p) {
   std::vector<double> hw(3 * n1);
   rhs_weights(N, hw.data());
   std::vector<double> rec((size_t)nmodes * stride, 0.0);
+  std::vector<double> hfull(4 * n1 + 2), pfull(4 * n1 + 2);
   for (int i = 0; i < d.nx; ++i)
     for (int j = 0; j < d.nzh; ++j) {
       if (i == d.nx / 2 || j == d.nzh - 1) continue;
@@ -159,12 +171,16 @@ sp_status build_mode_data(sp_plan* p) {
       const double kx = d.alpha * mxv, kz = d.gamma * j;
       const double k2 = kx * kx + kz * kz;
       const double lam = k2 + d.re * d.inv_dt;
-      sweep_factor(N, lam, r + L.helm());
+      // full factorisations (inv_den, cc, q, Q, inv_sum) for the host's own
+      // influence solutions; the record keeps inv_den, Q and inv_sum
+      sweep_factor(N, lam, hfull.data());
+      compact_sweep(hfull.data(), n1, r + L.helm());
       if (i == 0 && j == 0) continue;
-      sweep_factor(N, k2, r + L.pois());
+      sweep_factor(N, k2, pfull.data());
+      compact_sweep(pfull.data(), n1, r + L.pois());
       const double k = std::sqrt(k2);
       for (int pv = 0; pv < 2; ++pv)
-        influence_class(N, k, lam, r + L.helm(), r + L.pois(), hw.data(), pv, r + L.vdel(),
+        influence_class(N, k, lam, hfull.data(), pfull.data(), hw.data(), pv, r + L.vdel(),
                         r + L.vb(), r + L.minv() + 4 * pv);
     }
   for (double x : rec)

@@ -113,9 +113,22 @@ __device__ inline void rec_down(const cd (&a)[E], const double (&b)[E], cd x_ini
 // it, which serialises the LDS round trips.
 __device__ inline double mask(bool c) { return c ? 1.0 : 0.0; }
 
+// Sweep data of one operator (D^2 - lam) in a mode record: inv_den, Q and
+// inv_sum stored, the band and pass factors formed from lam and the
+// right-hand-side weights w1 = hw, w3 = hw + 2 n1 of the quasi-tridiagonal
+// form: cc_n = -lam w3_n, q_n = lam w1_n inv_den_n (solve_core.h).
+struct SweepRec {
+  const double* inv_den;
+  const double* Q;
+  const double* inv_sum;
+  double lam;
+  __device__ SweepRec(const double* base, int n1, double lam_)
+      : inv_den(base), Q(base + n1), inv_sum(base + 2 * n1), lam(lam_) {}
+};
+
 // Parity-p part of (D^2 - lam) g = r (rows 0..N-2), sum_{n = p mod 2} g_n = beta.
 template <int E>
-__device__ inline void wsweep(SweepView sw, const double* __restrict__ hw, int N, int p,
+__device__ inline void wsweep(SweepRec sw, const double* __restrict__ hw, int N, int p,
                               const cd* r, cd beta, cd* g, int l) {
   const int n1 = N + 1;
   const int nmax = top_index(N, p);
@@ -136,11 +149,10 @@ __device__ inline void wsweep(SweepView sw, const double* __restrict__ hw, int N
     const double w2 = hw[n1 + nc] * mask(nc <= N - 2);
     const double w3 = hw[2 * n1 + nc] * mask(nc + 2 <= N - 2);
     const double id = sw.inv_den[nc];
-    const double c = sw.cc[nc];
-    qv[e] = sw.q[nc] * act;
+    qv[e] = sw.lam * w1 * id * act;  // q = lam w1 / den
     Qv[e] = sw.Q[nc];
     a[e] = (rm * w1 + r0 * w2 + rp * w3) * (id * act);
-    b[e] = fma(-c * id, act, 1.0 - act);  // -cc / den on the chain, 1 elsewhere
+    b[e] = fma(sw.lam * w3 * id, act, 1.0 - act);  // -cc / den = lam w3 / den on the chain, 1 elsewhere
   }
   rec_down<E>(a, b, cd(0.0), x);
 #pragma unroll
@@ -200,7 +212,7 @@ __device__ inline void wderiv(int N, int pa, const cd* a, cd* bout, int l) {
 // adjoint of the right-hand-side combination. Two barriers are taken inside
 // (every lane of the block must call together).
 template <int E>
-__device__ inline void wsweep_T(SweepView sw, const double* __restrict__ hw, int N, int p,
+__device__ inline void wsweep_T(SweepRec sw, const double* __restrict__ hw, int N, int p,
                                 const cd* gbar, cd* rbar, cd* db, int l) {
   const int n1 = N + 1;
   const int nmax = top_index(N, p);
@@ -214,11 +226,12 @@ __device__ inline void wsweep_T(SweepView sw, const double* __restrict__ hw, int
     const int n = p + 2 * k;
     const int nc = (k <= M) ? n : nmax;
     const int nc2 = (k >= 2 && k <= M) ? n - 2 : p;
+    const int np2 = nc + 2 <= nmax ? nc + 2 : nmax;
     gv[e] = gbar[nc] * mask(k <= M);
     Qv[e] = (k == 0) ? 1.0 : sw.Q[nc];
-    q2[e] = sw.q[nc + 2 <= nmax ? nc + 2 : nmax] * mask(n + 2 <= nmax);
+    q2[e] = sw.lam * hw[np2] * sw.inv_den[np2] * mask(n + 2 <= nmax);  // q_{n+2}
     id[e] = sw.inv_den[nc];
-    cm[e] = sw.inv_den[nc2] * sw.cc[nc2];
+    cm[e] = -sw.lam * hw[2 * n1 + nc2] * sw.inv_den[nc2];  // inv_den cc at n - 2
   }
   cd s(0.0);
 #pragma unroll

@@ -13,27 +13,29 @@ namespace sp {
 
 // Per-mode record of the implicit-solve data (doubles), for one Fourier mode.
 // Offsets in units of doubles; n1 = N + 1.
-//   [0      , 4 n1 + 2) Helmholtz (D^2 - lam) sweep data, lam = k^2 + Re/dt
-//   [4n1 + 2, 8 n1 + 4) Poisson   (D^2 - k^2) sweep data (unused for (0,0))
-//   [8n1 + 4, 9 n1 + 4) influence basis v_delta (even n: class 0, odd n: class 1)
-//   [9n1 + 4,10 n1 + 4) influence basis v_b
-//   [10n1 + 4,10n1 + 12) 2x2 inverse influence matrices of class 0 and class 1
-// Each sweep block: inv_den[n1], cc[n1], q[n1], Q[n1], inv_sum_q[2].
+//   [0      , 2 n1 + 2) Helmholtz (D^2 - lam) sweep data, lam = k^2 + Re/dt
+//   [2n1 + 2, 4 n1 + 4) Poisson   (D^2 - k^2) sweep data (unused for (0,0))
+//   [4n1 + 4, 5 n1 + 4) influence basis v_delta (even n: class 0, odd n: class 1)
+//   [5n1 + 4, 6 n1 + 4) influence basis v_b
+//   [6n1 + 4, 6 n1 + 12) 2x2 inverse influence matrices of class 0 and class 1
+// Each sweep block: inv_den[n1], Q[n1], inv_sum_q[2]. The other two arrays of
+// the factorisation follow from the operator parameter and the right-hand-side
+// weights (solve_core.h): cc_n = -lam w3_n, q_n = lam w1_n inv_den_n.
 struct ModeLayout {
   int n1;
   __host__ __device__ int helm() const { return 0; }
-  __host__ __device__ int pois() const { return 4 * n1 + 2; }
-  __host__ __device__ int vdel() const { return 8 * n1 + 4; }
-  __host__ __device__ int vb() const { return 9 * n1 + 4; }
-  __host__ __device__ int minv() const { return 10 * n1 + 4; }
-  __host__ __device__ int stride() const { return ((10 * n1 + 12) + 1) / 2 * 2; }
+  __host__ __device__ int pois() const { return 2 * n1 + 2; }
+  __host__ __device__ int vdel() const { return 4 * n1 + 4; }
+  __host__ __device__ int vb() const { return 5 * n1 + 4; }
+  __host__ __device__ int minv() const { return 6 * n1 + 4; }
+  __host__ __device__ int stride() const { return ((6 * n1 + 12) + 1) / 2 * 2; }
 };
 
 // Doubles each of the 64 lanes of the per-mode solve kernels loads to stage one
-// mode record and the three weight rows (stride + 3 ny = 13 ny + 12 values),
+// mode record and the three weight rows (stride + 3 ny = 9 ny + 12 values),
 // for E elements per lane and parity chain: enough up to ny = 32 E, the
 // largest (even) ny with E elements per lane.
-__host__ __device__ constexpr int solve_record_loads(int E) { return (416 * E + 12 + 63) / 64; }
+__host__ __device__ constexpr int solve_record_loads(int E) { return (288 * E + 12 + 63) / 64; }
 
 struct FFTPlan1D {
   int P = 0;
