@@ -650,7 +650,7 @@ def mixed_error(workload=DEFAULT, energy=1e-6, max_krylov=200, rtol=1e-4, max_ne
 
 
 def large_newton(workload="couette_96x97x96_re2000_dt100", max_newton=30, max_krylov=200,
-                 rtol=1e-3):
+                 rtol=1e-3, variants=("fp64", "mixed", "mixed_krylov_fp32", "fp64_advected")):
     """Trust-region (hookstep) Newton-GMRES to ||r|| < 1e-10 on the large grid
     (96x97x96, Re 2000, 4pi x 2 x 2pi box) from the streak + roll start, with FP64
     Jacobian actions, mixed ones, mixed ones with an FP32 Krylov basis, and FP64
@@ -671,6 +671,8 @@ def large_newton(workload="couette_96x97x96_re2000_dt100", max_newton=30, max_kr
     finals = {}
     for name, prec, kf32 in (("fp64", SP_FP64, False), ("mixed", SP_MIXED, False),
                              ("mixed_krylov_fp32", SP_MIXED, True)):
+        if name not in variants:
+            continue
         P.set_precision(prec)
         uu = u0.clone()
         torch.cuda.synchronize()
@@ -683,12 +685,14 @@ def large_newton(workload="couette_96x97x96_re2000_dt100", max_newton=30, max_kr
                      "res_history": [float(f"{x:.3e}") for x in rep["res_norm"]],
                      "krylov": rep["krylov"],
                      "dist_to_laminar_L2": float(f"{P.norm((uu - lam).contiguous()):.4e}")}
-        if name != "fp64":
+        if name != "fp64" and "fp64" in finals:
             out[name]["vs_fp64_final_L2"] = float(
                 f"{P.norm((uu - finals['fp64']).contiguous()):.3e}")
         log("large newton", name, out[name])
     P.set_precision(SP_FP64)
     del P
+    if "fp64_advected" not in variants:
+        return out
     # the same solve with the laminar advection in the implicit operator
     PA = Plan(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], w["re"], w["dt"], device=dev)
     tb = time.perf_counter()
@@ -797,6 +801,13 @@ def main():
     ap.add_argument("--large-newton", action="store_true",
                     help="instead of the benchmark line, run hookstep Newton to 1e-10 at "
                          "96x97x96, Re 2000, from the streak + roll start (FP64 and mixed)")
+    ap.add_argument("--large-krylov", type=int, default=0,
+                    help="Krylov cap of --large-newton (default 200)")
+    ap.add_argument("--large-steps", type=int, default=0,
+                    help="Newton steps of --large-newton (default 30)")
+    ap.add_argument("--large-variants", default="",
+                    help="comma-separated subset of fp64, mixed, mixed_krylov_fp32, "
+                         "fp64_advected for --large-newton")
     ap.add_argument("--mixed-error", action="store_true",
                     help="instead of the benchmark line, print the per-Newton-step distance of "
                          "the mixed-precision iterates from the FP64 ones at 48x65x48")
@@ -825,7 +836,14 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.large_newton:
-        print(json.dumps(large_newton()), flush=True)
+        kw = {}
+        if args.large_krylov:
+            kw["max_krylov"] = args.large_krylov
+        if args.large_steps:
+            kw["max_newton"] = args.large_steps
+        if args.large_variants:
+            kw["variants"] = tuple(args.large_variants.split(","))
+        print(json.dumps(large_newton(**kw)), flush=True)
         return
     if args.mixed_error:
         print(json.dumps(mixed_error()), flush=True)

@@ -20,9 +20,11 @@
 //   B (4 x 16):  lane l holds B[l / 16][l % 16]
 //   D (16 x 16): lane l, register i holds D[r][l % 16] with
 //                r = 4 (l / 16) + i for f32 and r = (l / 16) + 4 i for f64.
-// A wave owns 16 columns (8 modes) and one 16-row tile of the output; the
-// block's four waves own 32 consecutive modes. Rows beyond the last full tile
-// (ny = 2^k + 1 leaves one) are finished on the vector unit with a 4-lane
+// In k_ycoef_mfma a wave owns 16 real columns (8 modes) and one 16-row tile
+// of the output, the block's four waves 32 consecutive modes; in
+// k_ysynth_mfma a wave owns 16 modes (their real and imaginary columns as two
+// MFMA column groups), the block's four waves 64. Rows beyond the last full
+// tile (ny = 2^k + 1 leaves one) are finished on the vector unit with a 4-lane
 // reduction.
 #include <hip/hip_runtime.h>
 
@@ -94,86 +96,17 @@ __device__ inline Blk3 ycontract_block() {
   return Blk3{rest % gx, l % gy, rest / gx};
 }
 
+// Synthesis: a wave owns 16 modes (kz * nx + mx = q0 .. q0 + 15) and one
+// 16-row tile of the output. Each lane loads one complex coefficient (16 bytes)
+// per k-step and feeds its real part to one MFMA column group and its
+// imaginary part to a second, so the two groups share every A fragment, a lane
+// issues one load per two output values, and each output row of the wave is
+// one contiguous run of 16 complex values (stored as pairs). Loads use clamped
+// addresses and are masked after (a 0/1 factor rather than a select keeps the
+// compiler from sinking each load into a branch of its own).
 template <typename R, int KS>
 __global__ void __launch_bounds__(256)
-    k_ysynth_mfma(const double2* __restrict__ u, SynthSpec<R> spec, R* __restrict__ out, int nx,
-                  int ny, int nzh, int nzm) {
-  using MF = Mfma<R>;
-  const int lane = threadIdx.x & 63;
-  const int kq = lane >> 4;
-  const int nq = nzm * nx;
-  const Blk3 bk = ycontract_block();
-  const int g = bk.z;
-  const int q0 = (bk.x * 4 + (threadIdx.x >> 6)) * 8;
-  const int q = q0 + ((lane & 15) >> 1);
-  const bool qv = q < nq;
-  const size_t fstride = (size_t)ny * nq * 2;
-  // B fragments: coefficient n = 4 s + kq of this lane's column. Addresses are
-  // clamped into range and out-of-range values zeroed after the load, so the
-  // loads stay unconditional and issue back to back.
-  R b[KS];
-  {
-    const int qc = qv ? q : nq - 1;
-    const int kz = qc / nx;
-    const int mx = qc - kz * nx;
-    const double* src =
-        reinterpret_cast<const double*>(u + (((size_t)spec.comp[g] * nx + mx) * nzh + kz) * ny) +
-        (lane & 1);
-    // (multiplying by a 0/1 mask rather than selecting keeps the compiler from
-    // sinking each load into a branch of its own)
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int n = 4 * s + kq;
-      const double v = src[2 * (n < ny ? n : ny - 1)];
-      b[s] = (R)v * (R)((qv && n < ny) ? 1 : 0);
-    }
-  }
-  const int nt = ny >> 4;
-  const int t = bk.y;
-  for (int mi = 0; mi < spec.nmat[g]; ++mi) {
-    const YMat<R> M = spec.mat[g][mi];
-    R* o = out + (size_t)spec.field[g][mi] * fstride + 2 * (size_t)q0 + (lane & 15);
-    if (t < nt) {
-      const R* fa = M.frag + (size_t)t * KS * 64 + lane;
-      R a[KS];
-#pragma unroll
-      for (int s = 0; s < KS; ++s) a[s] = fa[s * 64];
-      typename MF::acc_t acc = {0, 0, 0, 0};
-#pragma unroll
-      for (int s = 0; s < KS; ++s) acc = MF::mma(a[s], b[s], acc);
-      if (qv) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) o[(size_t)(16 * t + MF::drow(kq, i)) * nq * 2] = acc[i];
-      }
-    }
-    if (t == (int)gridDim.y - 1) {
-      for (int y = 16 * nt; y < ny; ++y) {
-        const R* mrow = M.full + (size_t)y * M.rs;
-        R mv[KS];
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          const int n = 4 * s + kq;
-          mv[s] = mrow[(size_t)(n < ny ? n : ny - 1) * M.cs];
-        }
-        R part = 0;
-#pragma unroll
-        for (int s = 0; s < KS; ++s) part += mv[s] * b[s];  // b[s] = 0 past ny
-        part = sum_kphase(part);
-        if (kq == 0 && qv) o[(size_t)y * nq * 2] = part;
-      }
-    }
-  }
-}
-
-// The same contraction with 16 modes per wave: each lane loads one complex
-// coefficient (16 bytes) per k-step and feeds its real part to one MFMA column
-// group and its imaginary part to a second, so the two groups share every A
-// fragment, each lane issues half the loads per output value of
-// k_ysynth_mfma, and each output row of the wave is one contiguous run of 16
-// complex values (stored as pairs).
-template <typename R, int KS>
-__global__ void __launch_bounds__(256)
-    k_ysynth_mfma2(const double2* __restrict__ u, SynthSpec<R> spec, R* __restrict__ out,
+    k_ysynth_mfma(const double2* __restrict__ u, SynthSpec<R> spec, R* __restrict__ out,
                    int nx, int ny, int nzh, int nzm) {
   using MF = Mfma<R>;
   using C = typename V2<R>::T;
@@ -352,7 +285,7 @@ __global__ void __launch_bounds__(256)
     for (int s = 0; s < KS; ++s) {
       const int j = 4 * s + kq;
       const R v = (tm < nterm) ? load(tm, c, j < ny ? j : ny - 1, qcl, kza, mxa, ra) : (R)0;
-      a[tm][s] = v * (R)((qav && j < ny) ? 1 : 0);  // a mask, not a select: see k_ysynth_mfma
+      a[tm][s] = v * (R)((qav && j < ny) ? 1 : 0);  // a mask, not a select (see k_ysynth_mfma)
     }
   }
   for (int t = ALLT ? 0 : bk.y; t < (ALLT ? ty : bk.y + 1); ++t) {
@@ -518,19 +451,19 @@ static dim3 ycoef_grid(const Dims& d, int* nqb) {
 hipError_t launch_synth_tab(sp_plan* p, const double2* u, int which, void* out, bool fp32) {
   const Dims& d = p->d;
   dim3 grid = ycontract_grid(d);
-  grid.x = (d.nzm * d.nx + 63) / 64;  // 64 modes per block (k_ysynth_mfma2)
+  grid.x = (d.nzm * d.nx + 63) / 64;  // 64 modes per block (k_ysynth_mfma)
   SP_PROF_BEGIN(p, KID_SYNTH_Y);
   if (fp32) {
     const SynthSpec<float> sp = synth_spec<float>(p, which);
 #define L32(KS)                                                                                  \
-  hipLaunchKernelGGL((k_ysynth_mfma2<float, KS>), grid, dim3(256), 0, p->stream, u, sp,          \
+  hipLaunchKernelGGL((k_ysynth_mfma<float, KS>), grid, dim3(256), 0, p->stream, u, sp,          \
                      (float*)out, d.nx, d.ny, d.nzh, d.nzm)
     SP_KS_DISPATCH(d.ny, L32);
 #undef L32
   } else {
     const SynthSpec<double> sp = synth_spec<double>(p, which);
 #define L64(KS)                                                                                  \
-  hipLaunchKernelGGL((k_ysynth_mfma2<double, KS>), grid, dim3(256), 0, p->stream, u, sp,         \
+  hipLaunchKernelGGL((k_ysynth_mfma<double, KS>), grid, dim3(256), 0, p->stream, u, sp,         \
                      (double*)out, d.nx, d.ny, d.nzh, d.nzm)
     SP_KS_DISPATCH(d.ny, L64);
 #undef L64
