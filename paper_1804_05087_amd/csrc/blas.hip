@@ -9,12 +9,14 @@
 namespace sp {
 
 // partial[(v * NR + r) * nb + chunk] = a chunk's share of <V_v, w_r>,
-// v = 0..nvec-1, r < NR (one or two right-hand vectors). V is nvec contiguous
-// canonical vectors of n complex entries. Block (chunk, g) owns 256 * kDotEPT
-// consecutive entries and the vectors 32 g .. 32 g + 31: each thread keeps its
-// weighted entries of the w_r in registers (weights computed once), streams
-// the vectors eight at a time, and the sums are reduced with wave shuffles
-// and LDS.
+// v = 0..nvec-1, r < NR (one or two right-hand vectors). Block (chunk, g) owns
+// 256 * ept consecutive entries of V's layout and the vectors 32 g .. 32 g + 31:
+// each thread keeps its weighted entries of the w_r in registers (weights
+// computed once), streams the vectors a group at a time, and the sums are
+// reduced with wave shuffles and LDS.
+// Layouts of V: CanonLayout (canonical fields, the packed product's weights)
+// or CompactLayout (the Krylov basis: compact vectors, every weight 1; the w_r
+// are canonical fields gathered through the map).
 // The Krylov basis is stored in FP64 (double2) or, to halve the traffic of the
 // orthogonalisation, in FP32 (float2); every sum is accumulated in FP64.
 __device__ inline double2 ld_basis(const double2* V, size_t i) { return V[i]; }
@@ -33,6 +35,28 @@ __device__ inline double2 st_basis(float2* V, size_t i, double x, double y) {
   return make_double2(f.x, f.y);
 }
 
+// Entry t of a canonical field: itself, with the packed product's weight.
+struct CanonLayout {
+  int n, nx, ny, nzh;
+  __device__ int size() const { return n; }
+  __device__ int canon(int t, double* wt) const {
+    const int j = (t / ny) % nzh;
+    const int m = (t / (ny * nzh)) % nx;
+    *wt = (m == nx / 2 || j == nzh - 1) ? 0.0 : (j > 0 ? 1.0 : (m == 0 ? 1.0 : 0.5));
+    return t;
+  }
+};
+// Entry t of a compact vector: its canonical index, weight 1.
+struct CompactLayout {
+  CMap m;
+  __device__ int size() const { return m.len; }
+  __device__ int canon(int t, double* wt) const {
+    int mir;
+    *wt = 1.0;
+    return m.canon(t, &mir);
+  }
+};
+
 // Launch shape per basis precision (measured at 48x65x48 with 24-200 vectors:
 // an FP32 basis streams fastest with four vectors per group and eight entries
 // per thread, an FP64 one with eight and four).
@@ -46,16 +70,16 @@ struct DotShape<float2> {
 };
 constexpr int kDotVecs = 32;
 
-template <int NR, typename T>
+template <int NR, typename T, class Layout>
 __global__ void __launch_bounds__(256)
     k_multidot(const T* __restrict__ V, int nvec, const double2* __restrict__ w0,
-               const double2* __restrict__ w1, double* __restrict__ partial, int n, int nx,
-               int ny, int nzh) {
+               const double2* __restrict__ w1, double* __restrict__ partial, Layout L) {
   constexpr int kDotGroup = DotShape<T>::group;
   constexpr int kDotEPT = DotShape<T>::ept;
   __shared__ double red[4][kDotGroup * NR];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
+  const int n = L.size();
   const int t0 = blockIdx.x * 256 * kDotEPT + threadIdx.x;
   double wr[NR][kDotEPT], wi[NR][kDotEPT];
   int tc[kDotEPT];
@@ -63,13 +87,12 @@ __global__ void __launch_bounds__(256)
   for (int i = 0; i < kDotEPT; ++i) {
     const int t = t0 + 256 * i;
     tc[i] = t < n ? t : n - 1;
-    const int j = (tc[i] / ny) % nzh;
-    const int m = (tc[i] / (ny * nzh)) % nx;
-    double wt = (m == nx / 2 || j == nzh - 1) ? 0.0 : (j > 0 ? 1.0 : (m == 0 ? 1.0 : 0.5));
+    double wt;
+    const int ci = L.canon(tc[i], &wt);
     if (t >= n) wt = 0.0;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      const double2 x = (r == 0 ? w0 : w1)[tc[i]];
+      const double2 x = (r == 0 ? w0 : w1)[ci];
       wr[r][i] = wt * x.x;
       wi[r][i] = wt * x.y;
     }
@@ -127,12 +150,16 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0) out[v] = red[0];
 }
 
-// w = beta * w + alpha * sum_v h[v] V_v   (h in device memory). One entry per
-// thread; the vector loop is unrolled by eight so eight loads are in flight.
+// w = beta * w + alpha * sum_v h[v] V_v (h in device memory) on the compact
+// basis: entry t adds to its canonical entry of w and, conjugated, to the
+// mirror entry (-m_x) of the m_z = 0 plane; w's other entries are untouched.
+// One compact entry per thread; the vector loop is unrolled by eight so eight
+// loads are in flight.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_multiaxpy(const T* __restrict__ V, int nvec, const double* __restrict__ h,
-                double alpha, double beta, double2* __restrict__ w, int n) {
+                double alpha, double beta, double2* __restrict__ w, CMap m) {
+  const int n = m.len;
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= n) return;
   double rx = 0.0, ry = 0.0;
@@ -154,22 +181,32 @@ __global__ void __launch_bounds__(256)
     rx += c * a.x;
     ry += c * a.y;
   }
-  const double2 o = w[t];
-  w[t] = make_double2(beta * o.x + alpha * rx, beta * o.y + alpha * ry);
+  int mir;
+  const int ci = m.canon(t, &mir);
+  const double2 o = w[ci];
+  w[ci] = make_double2(beta * o.x + alpha * rx, beta * o.y + alpha * ry);
+  if (mir >= 0) {
+    const double2 om = w[mir];
+    w[mir] = make_double2(beta * om.x + alpha * rx, beta * om.y - alpha * ry);
+  }
 }
 
-// One pass of the delayed-reorthogonalisation Arnoldi step (newton.cpp):
+// One pass of the delayed-reorthogonalisation Arnoldi step (newton.cpp) on the
+// compact basis:
 //   q    = (u - sum_{i<j} a_i V_i) * inv_gamma            (written over u = V_j)
 //   unew = w * inv_gamma - sum_{i<j} c_i V_i - c_j q
-// Each V_i is read once for both sums. q and unew are stored in the basis
-// precision and c_j multiplies the stored q; u64 (FP32 basis only, else NULL)
-// receives the stored unew widened to FP64, the input of the next Jacobian
-// action, so that the action and the basis see the same vector.
+// Each V_i is read once for both sums; w is canonical (gathered through the
+// map). q and unew are stored in the basis precision and c_j multiplies the
+// stored q; u64 receives the stored unew as a canonical FP64 field (mirror
+// entries conjugated; its Nyquist entries are never written and stay zero),
+// the input of the next Jacobian action, so that the action and the basis see
+// the same vector.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_dcgs2_update(T* V, int j, const double* __restrict__ a, const double* __restrict__ c,
-                   double inv_gamma, const double2* __restrict__ w, T* unew, double2* u64,
-                   int n) {
+                   double inv_gamma, const double2* __restrict__ w, T* unew,
+                   double2* __restrict__ u64, CMap m) {
+  const int n = m.len;
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= n) return;
   double ax = 0.0, ay = 0.0, cx = 0.0, cy = 0.0;
@@ -194,23 +231,34 @@ __global__ void __launch_bounds__(256)
     cx += c[i] * v.x;
     cy += c[i] * v.y;
   }
+  int mir;
+  const int cidx = m.canon(t, &mir);
   const double2 u = ld_basis(V, (size_t)j * n + t);
   const double2 q = st_basis(V, (size_t)j * n + t, (u.x - ax) * inv_gamma, (u.y - ay) * inv_gamma);
-  const double2 wv = w[t];
+  const double2 wv = w[cidx];
   const double cj = c[j];
   const double2 un =
       st_basis(unew, t, wv.x * inv_gamma - cx - cj * q.x, wv.y * inv_gamma - cy - cj * q.y);
-  if (u64) u64[t] = un;
+  u64[cidx] = un;
+  if (mir >= 0) u64[mir] = make_double2(un.x, -un.y);
 }
 
-// dst = (float) src, then src <- (double) dst: the first vector of an FP32
-// basis and its FP64 copy for the Jacobian action.
+// dst (compact) = src (canonical, in the Hermitian form); with write_back the
+// stored (possibly rounded) values replace src's entries and mirrors, so that
+// src is the FP64 image of what the basis holds.
+template <typename T>
 __global__ void __launch_bounds__(256)
-    k_round_basis(double2* src, float2* __restrict__ dst, int n) {
+    k_compact(double2* src, T* __restrict__ dst, CMap m, int write_back) {
   const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= n) return;
-  const double2 v = src[t];
-  src[t] = st_basis(dst, t, v.x, v.y);
+  if (t >= m.len) return;
+  int mir;
+  const int ci = m.canon(t, &mir);
+  const double2 v = src[ci];
+  const double2 s = st_basis(dst, t, v.x, v.y);
+  if (write_back) {
+    src[ci] = s;
+    if (mir >= 0) src[mir] = make_double2(s.x, -s.y);
+  }
 }
 
 // x = s * y
@@ -256,28 +304,29 @@ static int nblocks_for(size_t n) {
   return (int)b;
 }
 
-// element chunks of the FP64 shape; the FP32 shape has fewer (ept is larger)
+// element chunks of the FP64 shape over a canonical field; the compact layout
+// and the FP32 shape have fewer
 int multidot_blocks(const sp_plan* p) {
   const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
   constexpr int e = DotShape<double2>::ept;
   return (n + 256 * e - 1) / (256 * e);
 }
 
-template <typename T>
-static hipError_t multidot_impl(sp_plan* p, const T* V, int nvec, const double2* w0,
-                                const double2* w1, int nr, double* partial, double* out) {
-  const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
+template <typename T, class Layout>
+static hipError_t multidot_impl(sp_plan* p, const T* V, int n, Layout L, int nvec,
+                                const double2* w0, const double2* w1, int nr, double* partial,
+                                double* out) {
   constexpr int ept = DotShape<T>::ept;
   static_assert(ept >= DotShape<double2>::ept, "the partial buffer holds multidot_blocks chunks");
   const int nb = (n + 256 * ept - 1) / (256 * ept);
   SP_PROF_BEGIN(p, KID_MULTIDOT);
   const dim3 grid(nb, (nvec + kDotVecs - 1) / kDotVecs);
   if (nr == 1)
-    hipLaunchKernelGGL((k_multidot<1, T>), grid, dim3(256), 0, p->stream, V, nvec, w0, w0,
-                       partial, n, p->d.nx, p->d.ny, p->d.nzh);
+    hipLaunchKernelGGL((k_multidot<1, T, Layout>), grid, dim3(256), 0, p->stream, V, nvec, w0, w0,
+                       partial, L);
   else
-    hipLaunchKernelGGL((k_multidot<2, T>), grid, dim3(256), 0, p->stream, V, nvec, w0, w1,
-                       partial, n, p->d.nx, p->d.ny, p->d.nzh);
+    hipLaunchKernelGGL((k_multidot<2, T, Layout>), grid, dim3(256), 0, p->stream, V, nvec, w0, w1,
+                       partial, L);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_rows, dim3(nr * nvec), dim3(256), 0, p->stream, partial, nb, out);
@@ -288,62 +337,78 @@ static hipError_t multidot_impl(sp_plan* p, const T* V, int nvec, const double2*
 hipError_t launch_multidot(sp_plan* p, const double2* V, int nvec, const double2* w,
                            double* partial, double* out, int* nb_out) {
   if (nb_out) *nb_out = multidot_blocks(p);
-  return multidot_impl(p, V, nvec, w, w, 1, partial, out);
+  const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
+  const CanonLayout L{n, p->d.nx, p->d.ny, p->d.nzh};
+  return multidot_impl(p, V, n, L, nvec, w, w, 1, partial, out);
 }
 
-hipError_t launch_multidot2(sp_plan* p, const double2* V, int nvec, const double2* w0,
-                            const double2* w1, double* partial, double* out) {
-  return multidot_impl(p, V, nvec, w0, w1, 2, partial, out);
+template <typename T>
+static hipError_t kmultidot2(sp_plan* p, const T* V, int nvec, const double2* w0,
+                             const double2* w1, double* partial, double* out) {
+  const CompactLayout L{compact_map(p->d)};
+  return multidot_impl(p, V, L.m.len, L, nvec, w0, w1, 2, partial, out);
 }
-hipError_t launch_multidot2(sp_plan* p, const float2* V, int nvec, const double2* w0,
-                            const double2* w1, double* partial, double* out) {
-  return multidot_impl(p, V, nvec, w0, w1, 2, partial, out);
+hipError_t launch_krylov_multidot2(sp_plan* p, const double2* V, int nvec, const double2* w0,
+                                   const double2* w1, double* partial, double* out) {
+  return kmultidot2(p, V, nvec, w0, w1, partial, out);
+}
+hipError_t launch_krylov_multidot2(sp_plan* p, const float2* V, int nvec, const double2* w0,
+                                   const double2* w1, double* partial, double* out) {
+  return kmultidot2(p, V, nvec, w0, w1, partial, out);
 }
 
 template <typename T>
 static hipError_t multiaxpy_impl(sp_plan* p, const T* V, int nvec, const double* h, double alpha,
                                  double beta, double2* w) {
-  const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
+  const CMap m = compact_map(p->d);
   SP_PROF_BEGIN(p, KID_MULTIAXPY);
-  hipLaunchKernelGGL(k_multiaxpy<T>, dim3((n + 255) / 256), dim3(256), 0, p->stream, V, nvec, h,
-                     alpha, beta, w, n);
+  hipLaunchKernelGGL(k_multiaxpy<T>, dim3((m.len + 255) / 256), dim3(256), 0, p->stream, V, nvec,
+                     h, alpha, beta, w, m);
   SP_PROF_END(p, KID_MULTIAXPY);
   return hipGetLastError();
 }
-hipError_t launch_multiaxpy(sp_plan* p, const double2* V, int nvec, const double* h, double alpha,
-                            double beta, double2* w) {
+hipError_t launch_krylov_multiaxpy(sp_plan* p, const double2* V, int nvec, const double* h,
+                                   double alpha, double beta, double2* w) {
   return multiaxpy_impl(p, V, nvec, h, alpha, beta, w);
 }
-hipError_t launch_multiaxpy(sp_plan* p, const float2* V, int nvec, const double* h, double alpha,
-                            double beta, double2* w) {
+hipError_t launch_krylov_multiaxpy(sp_plan* p, const float2* V, int nvec, const double* h,
+                                   double alpha, double beta, double2* w) {
   return multiaxpy_impl(p, V, nvec, h, alpha, beta, w);
 }
 
 template <typename T>
 static hipError_t dcgs2_impl(sp_plan* p, T* V, int j, const double* a, const double* c,
                              double inv_gamma, const double2* w, T* unew, double2* u64) {
-  const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
+  const CMap m = compact_map(p->d);
   SP_PROF_BEGIN(p, KID_MULTIAXPY);
-  hipLaunchKernelGGL(k_dcgs2_update<T>, dim3((n + 255) / 256), dim3(256), 0, p->stream, V, j, a,
-                     c, inv_gamma, w, unew, u64, n);
+  hipLaunchKernelGGL(k_dcgs2_update<T>, dim3((m.len + 255) / 256), dim3(256), 0, p->stream, V, j,
+                     a, c, inv_gamma, w, unew, u64, m);
   SP_PROF_END(p, KID_MULTIAXPY);
   return hipGetLastError();
 }
 hipError_t launch_dcgs2_update(sp_plan* p, double2* V, int j, const double* a, const double* c,
-                              double inv_gamma, const double2* w, double2* unew) {
-  return dcgs2_impl(p, V, j, a, c, inv_gamma, w, unew, (double2*)nullptr);
+                              double inv_gamma, const double2* w, double2* unew, double2* u64) {
+  return dcgs2_impl(p, V, j, a, c, inv_gamma, w, unew, u64);
 }
 hipError_t launch_dcgs2_update(sp_plan* p, float2* V, int j, const double* a, const double* c,
                               double inv_gamma, const double2* w, float2* unew, double2* u64) {
   return dcgs2_impl(p, V, j, a, c, inv_gamma, w, unew, u64);
 }
 
-hipError_t launch_round_basis(sp_plan* p, double2* src, float2* dst) {
-  const int n = 3 * p->d.nx * p->d.nzh * p->d.ny;
+template <typename T>
+static hipError_t compact_impl(sp_plan* p, double2* src, T* dst, int write_back) {
+  const CMap m = compact_map(p->d);
   SP_PROF_BEGIN(p, KID_SCALE);
-  hipLaunchKernelGGL(k_round_basis, dim3((n + 255) / 256), dim3(256), 0, p->stream, src, dst, n);
+  hipLaunchKernelGGL(k_compact<T>, dim3((m.len + 255) / 256), dim3(256), 0, p->stream, src, dst,
+                     m, write_back);
   SP_PROF_END(p, KID_SCALE);
   return hipGetLastError();
+}
+hipError_t launch_compact(sp_plan* p, double2* src, double2* dst) {
+  return compact_impl(p, src, dst, 0);
+}
+hipError_t launch_compact(sp_plan* p, double2* src, float2* dst) {
+  return compact_impl(p, src, dst, 1);
 }
 
 // out = a x + b y on a canonical field, written in the form the packed real

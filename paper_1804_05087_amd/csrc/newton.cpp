@@ -4,7 +4,10 @@
 // GMRES: unrestarted, x0 = 0, Givens rotations and the least-squares solve on
 // the host. The residual, its norm, the GMRES scalars and every sum of the
 // orthogonalisation are FP64; the Jacobian actions use the plan's precision
-// and the basis is stored in FP64 or (krylov_fp32) FP32.
+// and the basis is stored in FP64 or (krylov_fp32) FP32, in the compact layout
+// (only the entries of the packed real vector space: no Nyquist entries, the
+// m_z = 0 plane at m_x >= 0 only), 8 % smaller than a canonical field at
+// 48x65x48, which is what every pass of the orthogonalisation streams.
 //
 // Arnoldi orthogonalisation: classical Gram-Schmidt with the second
 // (re-orthogonalising) pass delayed by one iteration, so every iteration reads
@@ -49,14 +52,17 @@ namespace {
 size_t canon_bytes(const sp_plan* p) {
   return (size_t)3 * p->d.nx * p->d.nzh * p->d.ny * sizeof(double2);
 }
+size_t compact_bytes(const sp_plan* p) {
+  return (size_t)compact_map(p->d).len * sizeof(double2);
+}
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 size_t ws_bytes_for(const sp_plan* p, int K) {
   size_t b = 0;
-  b += align256((size_t)(K + 1) * canon_bytes(p));         // Krylov basis
+  b += align256((size_t)(K + 1) * compact_bytes(p));       // Krylov basis (compact)
   b += align256(canon_bytes(p));                           // w
   b += align256(canon_bytes(p));                           // scratch field
-  b += align256(canon_bytes(p));                           // FP64 copy of u_j (FP32 basis)
+  b += align256(canon_bytes(p));                           // u_j, canonical FP64
   b += align256((size_t)2 * (K + 1) * multidot_blocks(p) * sizeof(double));  // partials
   b += 3 * align256((size_t)2 * (K + 2) * sizeof(double));  // dots, a|c, y
   return b;
@@ -77,7 +83,7 @@ Workspace carve(sp_plan* p, int K) {
   Workspace W;
   char* c = (char*)p->ws;
   W.V = (double2*)c;
-  c += align256((size_t)(K + 1) * canon_bytes(p));
+  c += align256((size_t)(K + 1) * compact_bytes(p));
   W.w = (double2*)c;
   c += align256(canon_bytes(p));
   W.s = (double2*)c;
@@ -161,8 +167,8 @@ sp_status ensure_workspace(sp_plan* p, int K) {
 }
 
 // Unrestarted GMRES on J_r du = r from du = 0 with delayed CGS2 Arnoldi. After
-// solve(): the first kd basis slots of W.V hold q_0..q_{kd-1} (orthonormal in
-// the packed product), R the Givens-rotated Hessenberg matrix (upper
+// solve(): the first kd basis slots of W.V hold q_0..q_{kd-1} (compact,
+// orthonormal in the packed product), R the Givens-rotated Hessenberg matrix (upper
 // triangular kd x kd, column-major with leading dimension K+1), g the rotated
 // right-hand side (g[kd] the least-squares residual), beta = ||r||.
 struct Gmres {
@@ -170,19 +176,21 @@ struct Gmres {
   const sp_newton_opts* o;
   int K;
   Workspace W;
-  size_t canon, nc;
+  size_t canon, nc, nk;
   double* hbuf = nullptr;  // pinned: dots[2(K+2)], a|c[2(K+2)]
   std::vector<double> H, R, cs, sn, g, hprev, a, b, Ha, cvec;
   int kd = 0;
   double beta = 0.0, relres = 1.0;
-  // FP32 basis: slot j of Vf holds q_j (u_j while iteration j runs); W.u holds
-  // u_j widened to FP64 for the Jacobian action
+  // slot j of the basis holds q_j (u_j while iteration j runs), in FP64 (W.V)
+  // or FP32 (Vf, the same memory); W.u holds u_j as a canonical FP64 field,
+  // the input of the Jacobian action
   const bool f32;
   float2* Vf;
 
   Gmres(sp_plan* p_, const sp_newton_opts* o_)
       : p(p_), o(o_), K(o_->max_krylov), W(carve(p_, o_->max_krylov)),
         canon(canon_bytes(p_)), nc(canon_bytes(p_) / sizeof(double2)),
+        nk((size_t)compact_map(p_->d).len),
         f32(o_->krylov_fp32 != 0), Vf((float2*)W.V),
         H((size_t)(K + 1) * K), R((size_t)(K + 1) * K), cs(K), sn(K), g(K + 1), hprev(K + 1),
         a(K + 1), b(K + 1), Ha(K + 1), cvec(K + 1) {}
@@ -204,14 +212,12 @@ struct Gmres {
     double* d_dots = W.h1;             // 2 (K + 2) doubles
     double* d_ac = W.h2;               // 2 (K + 2) doubles
     // u_0 = r (unnormalised; gamma_0 = ||r|| comes out of the first reduction)
-    if (f32) {
-      SP_TRY_HIP(hipMemcpyAsync(W.u, r, canon, hipMemcpyDeviceToDevice, p->stream), "copy r");
-      SP_TRY_HIP(launch_hermitian(p, W.u), "hermitian");
-      SP_TRY_HIP(launch_round_basis(p, W.u, Vf), "round r");
-    } else {
-      SP_TRY_HIP(hipMemcpyAsync(W.V, r, canon, hipMemcpyDeviceToDevice, p->stream), "copy r");
-      SP_TRY_HIP(launch_hermitian(p, W.V), "hermitian");
-    }
+    SP_TRY_HIP(hipMemcpyAsync(W.u, r, canon, hipMemcpyDeviceToDevice, p->stream), "copy r");
+    SP_TRY_HIP(launch_hermitian(p, W.u), "hermitian");
+    if (f32)
+      SP_TRY_HIP(launch_compact(p, W.u, Vf), "compact r");
+    else
+      SP_TRY_HIP(launch_compact(p, W.u, W.V), "compact r");
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(R.begin(), R.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
@@ -219,7 +225,7 @@ struct Gmres {
     kd = 0;
     relres = 1.0;
     for (int j = 0; j <= K; ++j) {
-      double2* uj = f32 ? W.u : W.V + (size_t)j * nc;
+      double2* uj = W.u;
       const bool last = (j == K);  // only completes column K-1: no new direction
       if (!last) {
         if (o->jvp_mode == 0) {
@@ -240,11 +246,13 @@ struct Gmres {
       }
       // dots of q_0..q_{j-1} and u_j with u_j and with w
       if (f32)
-        SP_TRY_HIP(launch_multidot2(p, Vf, j + 1, uj, last ? uj : W.w, W.partial, d_dots),
-                   "multidot");
+        SP_TRY_HIP(
+            launch_krylov_multidot2(p, Vf, j + 1, uj, last ? uj : W.w, W.partial, d_dots),
+            "multidot");
       else
-        SP_TRY_HIP(launch_multidot2(p, W.V, j + 1, uj, last ? uj : W.w, W.partial, d_dots),
-                   "multidot");
+        SP_TRY_HIP(
+            launch_krylov_multidot2(p, W.V, j + 1, uj, last ? uj : W.w, W.partial, d_dots),
+            "multidot");
       SP_TRY_HIP(hipMemcpyAsync(hdots, d_dots, 2 * (j + 1) * sizeof(double),
                                 hipMemcpyDeviceToHost, p->stream),
                  "copy dots");
@@ -308,10 +316,11 @@ struct Gmres {
                  "upload a, c");
       if (f32)
         SP_TRY_HIP(launch_dcgs2_update(p, Vf, j, d_ac, d_ac + (K + 2), ig, W.w,
-                                       Vf + (size_t)(j + 1) * nc, W.u),
+                                       Vf + (size_t)(j + 1) * nk, W.u),
                    "dcgs2 update");
       else
-        SP_TRY_HIP(launch_dcgs2_update(p, W.V, j, d_ac, d_ac + (K + 2), ig, W.w, uj + nc),
+        SP_TRY_HIP(launch_dcgs2_update(p, W.V, j, d_ac, d_ac + (K + 2), ig, W.w,
+                                       W.V + (size_t)(j + 1) * nk, W.u),
                    "dcgs2 update");
     }
     return SP_OK;
@@ -331,9 +340,9 @@ struct Gmres {
     SP_TRY_HIP(hipMemcpyAsync(W.y, y, kd * sizeof(double), hipMemcpyHostToDevice, p->stream),
                "upload y");
     if (f32)
-      SP_TRY_HIP(launch_multiaxpy(p, Vf, kd, W.y, -1.0, 1.0, target), "update");
+      SP_TRY_HIP(launch_krylov_multiaxpy(p, Vf, kd, W.y, -1.0, 1.0, target), "update");
     else
-      SP_TRY_HIP(launch_multiaxpy(p, W.V, kd, W.y, -1.0, 1.0, target), "update");
+      SP_TRY_HIP(launch_krylov_multiaxpy(p, W.V, kd, W.y, -1.0, 1.0, target), "update");
     return SP_OK;
   }
 };

@@ -352,8 +352,9 @@ extern "C" sp_status sp_plan_create(const sp_params* prm, void* hip_stream, sp_p
       return fail(s);
   }
   {
-    // MFMA fragment tables of the six y-contraction matrices
-    const int ny = d.ny, nt = ny / 16, ks = ycontract_ks(ny);
+    // MFMA fragment tables of the six y-contraction matrices: every 16-row tile
+    // including a last partial one (rows past ny and columns past ny zero)
+    const int ny = d.ny, nt = (ny + 15) / 16, ks = ycontract_ks(ny);
     const size_t per = std::max<size_t>((size_t)nt * ks * 64, 64);
     std::vector<double> fr((size_t)YM_COUNT * per, 0.0);
     auto elem = [&](int m, int r, int c) -> double {
@@ -371,7 +372,7 @@ extern "C" sp_status sp_plan_create(const sp_params* prm, void* hip_stream, sp_p
         for (int st = 0; st < ks; ++st)
           for (int l = 0; l < 64; ++l) {
             const int r = 16 * t + l % 16, c = 4 * st + l / 16;
-            if (c < ny) fr[m * per + ((size_t)t * ks + st) * 64 + l] = elem(m, r, c);
+            if (r < ny && c < ny) fr[m * per + ((size_t)t * ks + st) * 64 + l] = elem(m, r, c);
           }
     p->yfrag_stride = per;
     if ((s = upload(p, (void**)&p->d_yfrag, fr.data(), fr.size() * sizeof(double), "yfrag")))

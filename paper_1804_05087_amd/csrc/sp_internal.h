@@ -57,6 +57,55 @@ struct Dims {
   double alpha, gamma, re, dt, inv_dt, wall_upper, wall_lower;
 };
 
+// Compact storage of a Krylov vector: the canonical entries of the packed real
+// vector space, as one contiguous run of canonical entries per (component,
+// m_x):
+//   m_x in [0, nx/2):   m_z in [0, nzh - 1)  (the m_z = 0 plane keeps +m_x only)
+//   m_x = nx/2:         none (x Nyquist)
+//   m_x in (nx/2, nx):  m_z in [1, nzh - 1)
+// with all ny coefficients each. For fields in the Hermitian form (m_z = 0
+// entry at -m_x the conjugate of the one at +m_x, Nyquist entries zero) the
+// packed product is the plain sum of a.re b.re + a.im b.im over the compact
+// entries: each m_z = 0 pair appears once with weight 1 instead of twice
+// with weight 1/2.
+struct CMap {
+  int nx, ny, nzh;
+  int h;    // nx / 2
+  int r1;   // run length for m_x < nx/2: (nzh - 1) ny
+  int r2;   // run length for m_x > nx/2: (nzh - 2) ny
+  int lc;   // entries per component
+  int len;  // 3 lc
+  // canonical index of compact entry k; *mirror = canonical index of its
+  // conjugate partner (m_z = 0, 0 < m_x < nx/2) or -1
+  __host__ __device__ int canon(int k, int* mirror) const {
+    const int c = k / lc;
+    int r = k - c * lc;
+    if (r < h * r1) {
+      const int mx = r / r1;
+      const int off = r - mx * r1;  // kz * ny + n
+      *mirror = (off < ny && mx > 0) ? ((c * nx + (nx - mx)) * nzh) * ny + off : -1;
+      return ((c * nx + mx) * nzh) * ny + off;
+    }
+    r -= h * r1;
+    const int q = r / r2;
+    const int off = r - q * r2;
+    *mirror = -1;
+    return ((c * nx + h + 1 + q) * nzh + 1) * ny + off;
+  }
+};
+inline CMap compact_map(const Dims& d) {
+  CMap m;
+  m.nx = d.nx;
+  m.ny = d.ny;
+  m.nzh = d.nzh;
+  m.h = d.nx / 2;
+  m.r1 = (d.nzh - 1) * d.ny;
+  m.r2 = (d.nzh - 2) * d.ny;
+  m.lc = m.h * m.r1 + (m.h - 1) * m.r2;
+  m.len = 3 * m.lc;
+  return m;
+}
+
 // Intermediates and stream of one member of a batched call (see api.cpp).
 struct BatchSet {
   void* mem = nullptr;
@@ -213,24 +262,30 @@ hipError_t launch_unpack(sp_plan* p, const double* packed, double2* c);
 // GMRES BLAS (blas.hip)
 hipError_t launch_multidot(sp_plan* p, const double2* V, int nvec, const double2* w,
                            double* partial, double* out, int* nb_out);
-// out[2 v + r] = <V_v, w_r> for r = 0, 1 (partial: 2 nvec multidot_blocks(p) doubles)
-hipError_t launch_multidot2(sp_plan* p, const double2* V, int nvec, const double2* w0,
-                            const double2* w1, double* partial, double* out);
-hipError_t launch_multiaxpy(sp_plan* p, const double2* V, int nvec, const double* h, double alpha,
-                            double beta, double2* w);
-// V_j <- (V_j - sum_{i<j} a_i V_i) inv_gamma ; unew <- w inv_gamma - sum_{i<j} c_i V_i - c_j V_j
+// Krylov basis kernels (compact vectors, see CMap; T = double2 or float2, sums
+// in FP64):
+// out[2 v + r] = <V_v, w_r> for r = 0, 1 with w_r canonical fields in the
+// Hermitian form (partial: 2 nvec multidot_blocks(p) doubles)
+hipError_t launch_krylov_multidot2(sp_plan* p, const double2* V, int nvec, const double2* w0,
+                                   const double2* w1, double* partial, double* out);
+hipError_t launch_krylov_multidot2(sp_plan* p, const float2* V, int nvec, const double2* w0,
+                                   const double2* w1, double* partial, double* out);
+// w (canonical) = beta w + alpha sum_v h[v] V_v on the entries the compact
+// layout holds and their mirrors
+hipError_t launch_krylov_multiaxpy(sp_plan* p, const double2* V, int nvec, const double* h,
+                                   double alpha, double beta, double2* w);
+hipError_t launch_krylov_multiaxpy(sp_plan* p, const float2* V, int nvec, const double* h,
+                                   double alpha, double beta, double2* w);
+// V_j <- (V_j - sum_{i<j} a_i V_i) inv_gamma ; unew <- w inv_gamma - sum_{i<j} c_i V_i - c_j V_j,
+// w canonical; u64 (canonical) receives the stored unew in FP64
 hipError_t launch_dcgs2_update(sp_plan* p, double2* V, int j, const double* a, const double* c,
-                              double inv_gamma, const double2* w, double2* unew);
-// The same on an FP32 basis (sums in FP64); the update also writes the stored
-// unew widened to FP64 into u64.
-hipError_t launch_multidot2(sp_plan* p, const float2* V, int nvec, const double2* w0,
-                            const double2* w1, double* partial, double* out);
-hipError_t launch_multiaxpy(sp_plan* p, const float2* V, int nvec, const double* h, double alpha,
-                            double beta, double2* w);
+                              double inv_gamma, const double2* w, double2* unew, double2* u64);
 hipError_t launch_dcgs2_update(sp_plan* p, float2* V, int j, const double* a, const double* c,
                               double inv_gamma, const double2* w, float2* unew, double2* u64);
-// dst = (float) src, then src <- (double) dst
-hipError_t launch_round_basis(sp_plan* p, double2* src, float2* dst);
+// dst (compact) = src (canonical, Hermitian form); the FP32 form also writes the
+// rounded values back into src
+hipError_t launch_compact(sp_plan* p, double2* src, double2* dst);
+hipError_t launch_compact(sp_plan* p, double2* src, float2* dst);
 hipError_t launch_scale(sp_plan* p, const double2* y, double s, double2* x);
 hipError_t launch_hermitian(sp_plan* p, double2* a);
 hipError_t launch_symmetrize(sp_plan* p, double2* a);

@@ -21,11 +21,12 @@
 //   D (16 x 16): lane l, register i holds D[r][l % 16] with
 //                r = 4 (l / 16) + i for f32 and r = (l / 16) + 4 i for f64.
 // In k_ycoef_mfma a wave owns 16 real columns (8 modes) and one 16-row tile
-// of the output, the block's four waves 32 consecutive modes; in
-// k_ysynth_mfma a wave owns 16 modes (their real and imaginary columns as two
-// MFMA column groups), the block's four waves 64. Rows beyond the last full
-// tile (ny = 2^k + 1 leaves one) are finished on the vector unit with a 4-lane
-// reduction.
+// of the output, the block's four waves 32 consecutive modes, and rows beyond
+// the last full tile (ny = 2^k + 1 leaves one) are finished on the vector unit
+// with a 4-lane reduction; in k_ysynth_mfma a wave owns 16 modes (their real
+// and imaginary columns as two MFMA column groups), the block's four waves 64,
+// and the last, partial row tile goes through the MFMA like the others (its
+// padded rows are zero).
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -62,24 +63,24 @@ __device__ inline R sum_kphase(R v) {
   return v;
 }
 
-// One contraction matrix: its MFMA fragment table (full 16-row tiles, zero
-// padded beyond ny columns) and the plain matrix with (row, column) strides
-// for the rows past the last full tile.
+// One contraction matrix: its MFMA fragment table (every 16-row tile, the
+// last one partial when 16 does not divide ny; zero padded beyond ny rows and
+// columns) and the plain matrix with (row, column) strides.
 template <typename R>
 struct YMat {
-  const R* frag;  // [ny / 16][KS][64]
+  const R* frag;  // [ceil(ny / 16)][KS][64]
   const R* full;
   int rs, cs;     // element (r, c) at full[r * rs + c * cs]
 };
 
-// Up to three groups (one per velocity component); a group applies one or two
-// matrices to its component and writes one y-valued field per matrix.
+// Synthesis work list: entry g applies matrix mat[g] to component comp[g] and
+// writes y-valued field field[g] (one grid z index per entry).
 template <typename R>
 struct SynthSpec {
-  int comp[3];
-  int nmat[3];
-  int field[3][2];
-  YMat<R> mat[3][2];
+  int n;
+  int comp[5];
+  int field[5];
+  YMat<R> mat[5];
 };
 
 // Logical (x, y, z) block of a contraction grid: the hardware index is
@@ -96,14 +97,17 @@ __device__ inline Blk3 ycontract_block() {
   return Blk3{rest % gx, l % gy, rest / gx};
 }
 
-// Synthesis: a wave owns 16 modes (kz * nx + mx = q0 .. q0 + 15) and one
-// 16-row tile of the output. Each lane loads one complex coefficient (16 bytes)
-// per k-step and feeds its real part to one MFMA column group and its
-// imaginary part to a second, so the two groups share every A fragment, a lane
-// issues one load per two output values, and each output row of the wave is
-// one contiguous run of 16 complex values (stored as pairs). Loads use clamped
-// addresses and are masked after (a 0/1 factor rather than a select keeps the
-// compiler from sinking each load into a branch of its own).
+// Synthesis: a wave owns 16 modes (kz * nx + mx = q0 .. q0 + 15), one 16-row
+// tile of the output (the last tile may be partial: its padded rows are zero
+// in the table and are not stored) and one work-list entry (matrix, component,
+// field), so that every wave is one load -> MFMA -> store chain. Each lane
+// loads one complex coefficient (16 bytes) per k-step and feeds its real part
+// to one MFMA column group and its imaginary part to a second, so the two
+// groups share every A fragment, a lane issues one load per two output values,
+// and each output row of the wave is one contiguous run of 16 complex values
+// (stored as pairs). Loads use clamped addresses and are masked after (a 0/1
+// factor rather than a select keeps the compiler from sinking each load into
+// a branch of its own).
 template <typename R, int KS>
 __global__ void __launch_bounds__(256)
     k_ysynth_mfma(const double2* __restrict__ u, SynthSpec<R> spec, R* __restrict__ out,
@@ -115,12 +119,17 @@ __global__ void __launch_bounds__(256)
   const int nq = nzm * nx;
   const Blk3 bk = ycontract_block();
   const int g = bk.z;
+  const int t = bk.y;
   const int q0 = (bk.x * 4 + (threadIdx.x >> 6)) * 16;
   const int q = q0 + (lane & 15);
   const bool qv = q < nq;
   const size_t fstride = (size_t)ny * nq * 2;
-  R br[KS], bi[KS];
+  const YMat<R> M = spec.mat[g];
+  R a[KS], br[KS], bi[KS];
   {
+    const R* fa = M.frag + (size_t)t * KS * 64 + lane;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) a[s] = fa[s * 64];
     const int qc = qv ? q : nq - 1;
     const int kz = qc / nx;
     const int mx = qc - kz * nx;
@@ -134,55 +143,25 @@ __global__ void __launch_bounds__(256)
       bi[s] = (R)v.y * m;
     }
   }
-  const int nt = ny >> 4;
-  const int t = bk.y;
-  for (int mi = 0; mi < spec.nmat[g]; ++mi) {
-    const YMat<R> M = spec.mat[g][mi];
-    R* o = out + (size_t)spec.field[g][mi] * fstride + 2 * (size_t)q;
-    if (t < nt) {
-      const R* fa = M.frag + (size_t)t * KS * 64 + lane;
-      R a[KS];
+  // issue every load before the first MFMA waits on one: with one or two
+  // waves per SIMD nothing else hides their latency (left alone, the
+  // scheduler interleaves them with the MFMAs and keeps about ten in flight)
+  typename MF::acc_t accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
 #pragma unroll
-      for (int s = 0; s < KS; ++s) a[s] = fa[s * 64];
-      typename MF::acc_t accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+  for (int s = 0; s < KS; ++s) {
+    accr = MF::mma(a[s], br[s], accr);
+    acci = MF::mma(a[s], bi[s], acci);
+  }
+  if (qv) {
+    R* o = out + (size_t)spec.field[g] * fstride + 2 * (size_t)q;
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        accr = MF::mma(a[s], br[s], accr);
-        acci = MF::mma(a[s], bi[s], acci);
-      }
-      if (qv) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          C v;
-          v.x = accr[i];
-          v.y = acci[i];
-          *reinterpret_cast<C*>(o + (size_t)(16 * t + MF::drow(kq, i)) * nq * 2) = v;
-        }
-      }
-    }
-    if (t == (int)gridDim.y - 1) {
-      for (int y = 16 * nt; y < ny; ++y) {
-        const R* mrow = M.full + (size_t)y * M.rs;
-        R mv[KS];
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          const int n = 4 * s + kq;
-          mv[s] = mrow[(size_t)(n < ny ? n : ny - 1) * M.cs];
-        }
-        R pr = 0, pi = 0;
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {  // br, bi = 0 past ny
-          pr += mv[s] * br[s];
-          pi += mv[s] * bi[s];
-        }
-        pr = sum_kphase(pr);
-        pi = sum_kphase(pi);
-        if (kq == 0 && qv) {
-          C v;
-          v.x = pr;
-          v.y = pi;
-          *reinterpret_cast<C*>(o + (size_t)y * nq * 2) = v;
-        }
+    for (int i = 0; i < 4; ++i) {
+      const int y = 16 * t + MF::drow(kq, i);
+      if (y < ny) {
+        C v;
+        v.x = accr[i];
+        v.y = acci[i];
+        *reinterpret_cast<C*>(o + (size_t)y * nq * 2) = v;
       }
     }
   }
@@ -413,22 +392,21 @@ static YMat<R> ymat(const sp_plan* p, int id) {
 template <typename R>
 static SynthSpec<R> synth_spec(const sp_plan* p, int which) {
   SynthSpec<R> sp{};
-  for (int g = 0; g < 3; ++g) sp.comp[g] = g;
   if (which == 0) {  // forward: fields u, du/dy, v, w, dw/dy
-    const int nm[3] = {2, 1, 2};
-    const int flds[3][2] = {{0, 1}, {2, 2}, {3, 4}};
-    for (int g = 0; g < 3; ++g) {
-      sp.nmat[g] = nm[g];
-      sp.field[g][0] = flds[g][0];
-      sp.field[g][1] = flds[g][1];
-      sp.mat[g][0] = ymat<R>(p, YM_T);
-      sp.mat[g][1] = ymat<R>(p, YM_TD);
+    const int comp[5] = {0, 0, 1, 2, 2};
+    const int mat[5] = {YM_T, YM_TD, YM_T, YM_T, YM_TD};
+    sp.n = 5;
+    for (int g = 0; g < 5; ++g) {
+      sp.comp[g] = comp[g];
+      sp.field[g] = g;
+      sp.mat[g] = ymat<R>(p, mat[g]);
     }
   } else {  // adjoint of the analysis: Tinv^T on each component
+    sp.n = 3;
     for (int g = 0; g < 3; ++g) {
-      sp.nmat[g] = 1;
-      sp.field[g][0] = sp.field[g][1] = g;
-      sp.mat[g][0] = sp.mat[g][1] = ymat<R>(p, YM_TINV_T);
+      sp.comp[g] = g;
+      sp.field[g] = g;
+      sp.mat[g] = ymat<R>(p, YM_TINV_T);
     }
   }
   return sp;
@@ -450,8 +428,9 @@ static dim3 ycoef_grid(const Dims& d, int* nqb) {
 
 hipError_t launch_synth_tab(sp_plan* p, const double2* u, int which, void* out, bool fp32) {
   const Dims& d = p->d;
-  dim3 grid = ycontract_grid(d);
-  grid.x = (d.nzm * d.nx + 63) / 64;  // 64 modes per block (k_ysynth_mfma)
+  // 64 modes per block, every 16-row tile, one work-list entry per z index
+  const SynthSpec<double> sp64 = synth_spec<double>(p, which);
+  const dim3 grid((d.nzm * d.nx + 63) / 64, (d.ny + 15) / 16, sp64.n);
   SP_PROF_BEGIN(p, KID_SYNTH_Y);
   if (fp32) {
     const SynthSpec<float> sp = synth_spec<float>(p, which);
@@ -461,7 +440,7 @@ hipError_t launch_synth_tab(sp_plan* p, const double2* u, int which, void* out, 
     SP_KS_DISPATCH(d.ny, L32);
 #undef L32
   } else {
-    const SynthSpec<double> sp = synth_spec<double>(p, which);
+    const SynthSpec<double>& sp = sp64;
 #define L64(KS)                                                                                  \
   hipLaunchKernelGGL((k_ysynth_mfma<double, KS>), grid, dim3(256), 0, p->stream, u, sp,         \
                      (double*)out, d.nx, d.ny, d.nzh, d.nzm)

@@ -17,6 +17,8 @@
 // Block: XL x-lines of one y-plane.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "sp_internal.h"
 
@@ -29,6 +31,7 @@ namespace sp {
 template <typename R>
 struct OpCross {  // n = u x omega; in = (u + i v, w + i ox, oy + i oz); out = (nx + i ny, nz)
   static constexpr int NI = 3, NF = 2;
+  static constexpr bool kBase = false;  // reads no base state
   template <typename C>
   __device__ void operator()(const C (&in)[3], C (&out)[2], const R*, size_t, size_t) const {
     const R u = in[0].x, v = in[0].y, w = in[1].x, ox = in[1].y, oy = in[2].x, oz = in[2].y;
@@ -40,6 +43,7 @@ struct OpCross {  // n = u x omega; in = (u + i v, w + i ox, oy + i oz); out = (
 template <typename R>
 struct OpCrossLin {  // n = du x Omega + U x domega with (U, Omega) from base
   static constexpr int NI = 3, NF = 2;
+  static constexpr bool kBase = true;
   template <typename C>
   __device__ void operator()(const C (&in)[3], C (&out)[2], const R* base, size_t bs,
                              size_t bo) const {
@@ -54,11 +58,13 @@ struct OpCrossLin {  // n = du x Omega + U x domega with (U, Omega) from base
 template <typename R>
 struct OpStoreBase {  // cache U, Omega of the base state; no forward transform
   static constexpr int NI = 3, NF = 0;
+  static constexpr bool kBase = true;
 };
 
 template <typename R>
 struct OpAdjCross {  // in = (lam_x + i lam_y, lam_z); out = adjoint of the linearised product
   static constexpr int NI = 2, NF = 3;
+  static constexpr bool kBase = true;
   template <typename C>
   __device__ void operator()(const C (&in)[2], C (&out)[3], const R* base, size_t bs,
                              size_t bo) const {
@@ -139,53 +145,83 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
 
-  // step 2 of the inverse transforms, the pointwise stage and step 1 of the
-  // forward transforms: task (xl, k1), points z = k1 + P1 k2
+  // step 2 of the inverse transforms, in place: task (xl, line i, k1); column
+  // k1 of the exchange block then holds the physical points z = k1 + P1 k2
   const size_t bs = (size_t)ny * px * P;
-  for (int task = tid; task < XL * P1; task += 256) {
+  for (int task = tid; task < XL * NI * P1; task += 256) {
     const int k1 = task % P1;
-    const int xl = task / P1;
+    const int li = task / P1;  // xl * NI + i
+    const int xl = li / NI;
     if (xl < nxl) {
-      C ph[NI][P2];
+      C* e = ex1 + (li * P2) * S1 + k1;
+      C ph[P2];
 #pragma unroll
-      for (int i = 0; i < NI; ++i) {
-        const C* e = ex1 + ((xl * NI + i) * P2) * S1 + k1;
-#pragma unroll
-        for (int n2 = 0; n2 < P2; ++n2) ph[i][n2] = e[n2 * S1];
-        dft_reg<P2, P, C, R>(ph[i], (R)1, twl);
-      }
-      const size_t bo0 = ((size_t)y * px + x0 + xl) * P + k1;
-      if constexpr (NF == 0) {
+      for (int n2 = 0; n2 < P2; ++n2) ph[n2] = e[n2 * S1];
+      dft_reg<P2, P, C, R>(ph, (R)1, twl);
+      if constexpr (NF == 0) {  // the base state: packed line i holds fields 2i, 2i + 1
+        const int i = li % NI;
+        const size_t bo0 = ((size_t)y * px + x0 + xl) * P + k1;
 #pragma unroll
         for (int k2 = 0; k2 < P2; ++k2) {
           const size_t bo = bo0 + (size_t)P1 * k2;
-          base[bo] = ph[0][k2].x;
-          base[bs + bo] = ph[0][k2].y;
-          base[2 * bs + bo] = ph[1][k2].x;
-          base[3 * bs + bo] = ph[1][k2].y;
-          base[4 * bs + bo] = ph[2][k2].x;
-          base[5 * bs + bo] = ph[2][k2].y;
+          base[(size_t)(2 * i) * bs + bo] = ph[k2].x;
+          base[(size_t)(2 * i + 1) * bs + bo] = ph[k2].y;
         }
       } else {
-        C fw[NF][P2];
-        const Op op{};
 #pragma unroll
-        for (int k2 = 0; k2 < P2; ++k2) {
-          C pin[NI], pout[NF];
+        for (int k2 = 0; k2 < P2; ++k2) e[k2 * S1] = ph[k2];
+      }
+    }
+  }
+  if constexpr (NF > 0) {
+    __syncthreads();
+    // the pointwise stage and step 1 of the forward transforms: task (xl, k1,
+    // forward line f) for operators that read no base state, else (xl, k1)
+    // with every f in one task, so the base state is read once per point
+    constexpr int NFT = Op::kBase ? 1 : NF;  // forward lines per task split
+    for (int task = tid; task < XL * P1 * NFT; task += 256) {
+      // f slowest: with XL * P1 a multiple of 64 it is uniform over a wave
+      const int fsel = task / (XL * P1);
+      const int k1 = task % P1;
+      const int xl = (task / P1) % XL;
+      if (xl < nxl) {
+        const size_t bo0 = ((size_t)y * px + x0 + xl) * P + k1;
+        // forward lines F0 .. F0 + NFL - 1 (compile-time, so pout stays in registers)
+        auto run = [&](auto f0) {
+          constexpr int F0 = decltype(f0)::value;
+          constexpr int NFL = Op::kBase ? NF : 1;
+          C fw[NFL][P2];
+          const Op op{};
 #pragma unroll
-          for (int i = 0; i < NI; ++i) pin[i] = ph[i][k2];
-          op(pin, pout, base, bs, bo0 + (size_t)P1 * k2);
+          for (int k2 = 0; k2 < P2; ++k2) {
+            C pin[NI], pout[NF];
 #pragma unroll
-          for (int f = 0; f < NF; ++f) fw[f][k2] = pout[f];
-        }
+            for (int i = 0; i < NI; ++i) pin[i] = ex1[((xl * NI + i) * P2 + k2) * S1 + k1];
+            op(pin, pout, base, bs, bo0 + (size_t)P1 * k2);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          dft_reg<P2, P, C, R>(fw[f], (R)-1, twl);
-          C* e = ex2 + ((xl * NF + f) * P2) * S1 + k1;
+            for (int q = 0; q < NFL; ++q) fw[q][k2] = pout[F0 + q];
+          }
 #pragma unroll
-          for (int m2 = 0; m2 < P2; ++m2)
-            e[m2 * S1] = (m2 == 0 || k1 == 0) ? fw[f][m2]
-                                              : cmul(fw[f][m2], wpow<P, P, C, R>(k1 * m2, (R)-1, twl));
+          for (int q = 0; q < NFL; ++q) {
+            dft_reg<P2, P, C, R>(fw[q], (R)-1, twl);
+            C* e = ex2 + ((xl * NF + F0 + q) * P2) * S1 + k1;
+#pragma unroll
+            for (int m2 = 0; m2 < P2; ++m2)
+              e[m2 * S1] = (m2 == 0 || k1 == 0)
+                               ? fw[q][m2]
+                               : cmul(fw[q][m2], wpow<P, P, C, R>(k1 * m2, (R)-1, twl));
+          }
+        };
+        if constexpr (Op::kBase) {
+          run(std::integral_constant<int, 0>{});
+        } else {
+          if (fsel == 0) run(std::integral_constant<int, 0>{});
+          if constexpr (NF > 1) {
+            if (fsel == 1) run(std::integral_constant<int, 1>{});
+          }
+          if constexpr (NF > 2) {
+            if (fsel == 2) run(std::integral_constant<int, 2>{});
+          }
         }
       }
     }

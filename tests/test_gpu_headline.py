@@ -11,6 +11,8 @@
 * The JVP on sampled modes at 96x97x96 (Re = 2000, 4pi x 2 x 2pi box).
 * Newton at 16x17x16 capped at 5 steps of 40 GMRES iterations (eqs. linear,
   biglin): the GPU's residual history against the oracle's.
+* A non-laminar equilibrium found on the GPU at 32x33x32 is a root of the
+  oracle's residual.
 
 Bars. FP64: relative error <= 1e-12 in the Frobenius norm of the whole field.
 Differences of two O(1) fields (r = (Phi - u)/dt and the residual form of the
@@ -236,3 +238,38 @@ def test_newton_history_16_capped(torch_mod):
     worst = max(abs(a - b) / b for a, b in zip(rep["res_norm"], rep_ref["res_norm"]))
     say("largest relative difference of the residual norms", worst)
     assert worst <= 1e-8
+
+
+def test_nonlaminar_root_is_a_root_of_the_oracle(torch_mod):
+    """A non-laminar equilibrium found on the GPU (32x33x32, Re = 400, dt = 100,
+    hookstep Newton from the perturbation family, as the benchmark's
+    continuation starts) is a root of the oracle's residual: the oracle's own
+    ||r|| at the GPU's converged state is below 1e-10 and equals the GPU's to
+    1e-12 of (||Phi|| + ||u||)/dt (reading of the residual's accuracy), and the
+    state is far from laminar flow."""
+    from paper_1804_05087_amd import Plan
+    dims = (32, 33, 32)
+    re, dt = 400.0, 100.0
+    say("non-laminar root 32x33x32")
+    g = Grid(*dims, *BOX)
+    P = Plan(*dims, *BOX, re, dt)
+    lam = synth.laminar_field(*dims)
+    found = None
+    for seed in (8, 1, 0, 2, 3):
+        u = to_dev(synth.perturbation_field(*dims, *BOX, seed=seed))
+        rep = P.newton_hookstep(u, max_newton=30, max_krylov=400, gmres_rtol=1e-4,
+                                newton_tol=1e-11)
+        d = P.norm((u - to_dev(lam)).contiguous())
+        say("seed", seed, rep["converged"], rep["res_norm"][-1], d)
+        if rep["converged"] and d > 1e-2:
+            found = (to_np(u), rep["res_norm"][-1], d)
+            break
+    assert found is not None, "no non-laminar equilibrium from seeds 8, 1, 0, 2, 3"
+    u, res_gpu, d = found
+    B = Befe(g, re, dt)
+    phi = B.phi(u)
+    res_oracle = B.norm_l2((phi - u) / dt)
+    say("oracle ||r||", res_oracle, "GPU", res_gpu, "distance from laminar", d)
+    assert res_oracle < 1e-10
+    assert abs(res_oracle - res_gpu) <= 1e-12 * (B.norm_l2(phi) + B.norm_l2(u)) / dt
+    assert B.norm_l2(u - lam) > 0.1

@@ -27,3 +27,17 @@ def test_host_math_under_asan_ubsan(tmp_path):
     assert res.returncode == 0, res.stdout + res.stderr
     assert "all checks passed" in res.stdout
     assert "runtime error" not in res.stderr and "AddressSanitizer" not in res.stderr
+
+
+@pytest.mark.skipif(not os.path.exists("/opt/rocm/bin/hipcc"), reason="hipcc not available")
+def test_compact_krylov_layout_is_a_bijection_onto_the_packed_space(tmp_path):
+    """The map of the compact Krylov-vector layout (host code of the same
+    header the kernels use), built for the host with hipcc and run on the CPU."""
+    exe = tmp_path / "compact_map"
+    cmd = ["/opt/rocm/bin/hipcc", "-std=c++17", "-O1", "--offload-arch=gfx950",
+           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           os.path.join(ROOT, "tests", "compact_map_driver.cpp"), "-o", str(exe)]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    res = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert res.returncode == 0, res.stdout + res.stderr
+    assert "all checks passed" in res.stdout
