@@ -649,68 +649,179 @@ def mixed_error(workload=DEFAULT, energy=1e-6, max_krylov=200, rtol=1e-4, max_ne
     return out
 
 
-def large_newton(workload="couette_96x97x96_re2000_dt100", max_newton=30, max_krylov=200,
-                 rtol=1e-3, variants=("fp64", "mixed", "mixed_krylov_fp32", "fp64_advected")):
-    """Trust-region (hookstep) Newton-GMRES to ||r|| < 1e-10 on the large grid
-    (96x97x96, Re 2000, 4pi x 2 x 2pi box) from the streak + roll start, with FP64
-    Jacobian actions, mixed ones, mixed ones with an FP32 Krylov basis, and FP64
-    actions of the step with the laminar advection in its implicit operator.
-    Reported per solve: convergence, Newton steps, Krylov iterations, seconds,
-    the residual history and the distance of the end state from laminar flow
-    and from the FP64 solve's end state."""
+def re_continuation(dev, u, dims, box, re0, re1, dre, max_krylov=800, rtol=1e-4, tol=1e-10):
+    """Hookstep Newton roots at Re = re0, re0 + dre, ..., re1 in the box, each
+    the start of the next solve (the step is halved after a failed solve, down
+    to dre / 8). Returns the root at re1 (or None) and the path."""
+    import torch
+    from paper_1804_05087_amd import Plan, synth
+    lam = torch.from_numpy(synth.laminar_field(*dims)).to(dev)
+    path, re, step = [], re0, dre
+    while True:
+        P = Plan(*dims, *box, re, 100.0, device=dev)
+        x = u.clone()
+        rep = P.newton_hookstep(x, max_newton=50, max_krylov=max_krylov, gmres_rtol=rtol,
+                                newton_tol=tol)
+        dist = P.norm((x - lam).contiguous())
+        path.append({"re": re, "converged": rep["converged"], "newton_iters": rep["newton_iters"],
+                     "res": float(f"{rep['res_norm'][-1]:.2e}"),
+                     "seconds": round(rep["seconds"], 2),
+                     "dist_to_laminar_L2": float(f"{dist:.4e}")})
+        log("continuation", dims, path[-1])
+        del P
+        if not rep["converged"] or dist < 1e-3:
+            if step <= dre / 8:
+                return None, path
+            re -= step
+            step /= 2
+            re += step
+            continue
+        u = x
+        if re >= re1:
+            return u, path
+        re = min(re + step, re1)
+
+
+def box_continued_equilibrium(dev, box, dims=(32, 33, 32), re=400.0, nsteps=8):
+    """An equilibrium of the box at Re 400: the one of PAPER_BOX found at 32x33x32
+    from the perturbation family (seed 8), carried to the box by continuation in
+    (Lx, Lz) in nsteps equal steps (halved after a failed solve)."""
+    import torch
+    from paper_1804_05087_amd import Plan, synth
+    lam = torch.from_numpy(synth.laminar_field(*dims)).to(dev)
+    P = Plan(*dims, *PAPER_BOX, re, 100.0, device=dev)
+    u = torch.from_numpy(synth.perturbation_field(*dims, *PAPER_BOX, seed=8)).to(dev)
+    rep = P.newton_hookstep(u, max_newton=30, max_krylov=400, gmres_rtol=1e-4, newton_tol=1e-12)
+    if not rep["converged"] or P.norm((u - lam).contiguous()) < 1e-3:
+        return None, {"error": "no non-laminar root from seed 8"}
+    path, s, ds = [], 0.0, 1.0 / nsteps
+    while s < 1.0:
+        s1 = min(1.0, s + ds)
+        lx = PAPER_BOX[0] + s1 * (box[0] - PAPER_BOX[0])
+        lz = PAPER_BOX[1] + s1 * (box[1] - PAPER_BOX[1])
+        P = Plan(*dims, lx, lz, re, 100.0, device=dev)
+        x = u.clone()
+        rep = P.newton_hookstep(x, max_newton=30, max_krylov=400, gmres_rtol=1e-4,
+                                newton_tol=1e-11)
+        dist = P.norm((x - lam).contiguous())
+        path.append({"lx": round(lx, 4), "lz": round(lz, 4), "converged": rep["converged"],
+                     "newton_iters": rep["newton_iters"],
+                     "dist_to_laminar_L2": float(f"{dist:.4e}")})
+        del P
+        if rep["converged"] and dist > 1e-3:
+            u, s = x, s1
+        else:
+            ds /= 2
+            if ds < 1.0 / 256:
+                return None, {"error": "box continuation failed", "path": path}
+    return u, {"found_in": "PAPER_BOX, 32x33x32, Re 400, seed 8", "box_path": path}
+
+
+def large_newton(workload="couette_96x97x96_re2000_dt100", max_newton=20, max_krylov=800,
+                 rtol=1e-4, full_newton=8, oracle_modes=24):
+    """Newton to ||r|| < 1e-10 on the large workload (96x97x96, Re 2000, 4pi x 2 x
+    2pi box) by continuation, as the paper reaches Re 2000 (Sec. 3.3): the
+    equilibrium of PAPER_BOX is carried to the 2pi x pi box (half the workload's
+    periods), continued in Re to Re 1950 on the workload's y-grid (48x97x48),
+    and then
+    - timed: hookstep Newton at Re 2000 in that box (FP64, mixed, mixed with an
+      FP32 Krylov basis), which is the workload's problem restricted to its
+      invariant subspace of fields periodic over half the box (the embedding
+      of synth.embed_periodic maps roots to roots exactly);
+    - the FP64 root embedded in the workload's grid: its residual there on the
+      GPU, and the oracle's residual on sampled modes against the GPU's;
+    - hookstep Newton on the full workload grid from the embedded Re-1950 root
+      (full_newton steps, FP64), reported as measured."""
+    import numpy as np
     import torch
     from paper_1804_05087_amd import SP_FP64, SP_MIXED, Plan, synth
     w = WORKLOADS[workload]
     dev = torch.device("cuda", 0)
-    P = Plan(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], w["re"], w["dt"], device=dev)
-    u0 = torch.from_numpy(synth.streak_roll_field(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"],
-                                                  seed=0)).to(dev)
-    lam = torch.from_numpy(synth.laminar_field(w["nx"], w["ny"], w["nz"])).to(dev)
+    big = (w["nx"], w["ny"], w["nz"])
+    sub = (w["nx"] // 2, w["ny"], w["nz"] // 2)
+    box_s = (w["lx"] / 2, w["lz"] / 2)
+    t0 = time.perf_counter()
+    u32, info = box_continued_equilibrium(dev, box_s)
     out = {"metric": "large_grid_newton", "workload": workload, "newton": "hookstep",
-           "max_krylov": max_krylov, "gmres_rtol": rtol, "newton_tol": 1e-10}
-    finals = {}
+           "max_krylov": max_krylov, "gmres_rtol": rtol, "newton_tol": 1e-10,
+           "start": info}
+    if u32 is None:
+        return out
+    u = torch.from_numpy(synth.regrid(u32.cpu().numpy(), *sub)).to(dev)
+    u, path = re_continuation(dev, u, sub, box_s, 400.0, w["re"] - 50.0, 100.0,
+                              max_krylov=max_krylov, rtol=rtol)
+    out["start"].update({"re_path": path, "continued_to_re": w["re"] - 50.0,
+                         "grid": list(sub), "box": list(box_s),
+                         "seconds": round(time.perf_counter() - t0, 1)})
+    if u is None:
+        return out
+    lam_s = torch.from_numpy(synth.laminar_field(*sub)).to(dev)
+    P = Plan(*sub, *box_s, w["re"], w["dt"], device=dev)
+    roots = {}
+    sub_out = {"grid": list(sub), "box": list(box_s)}
     for name, prec, kf32 in (("fp64", SP_FP64, False), ("mixed", SP_MIXED, False),
                              ("mixed_krylov_fp32", SP_MIXED, True)):
-        if name not in variants:
-            continue
         P.set_precision(prec)
-        uu = u0.clone()
+        x = u.clone()
         torch.cuda.synchronize()
-        rep = P.newton_hookstep(uu, max_newton=max_newton, max_krylov=max_krylov,
+        rep = P.newton_hookstep(x, max_newton=max_newton, max_krylov=max_krylov,
                                 gmres_rtol=rtol, newton_tol=1e-10, krylov_fp32=kf32)
-        finals[name] = uu
-        out[name] = {"converged": rep["converged"], "newton_iters": rep["newton_iters"],
-                     "total_krylov": rep["total_krylov"], "actions": rep["total_actions"],
-                     "seconds": round(rep["seconds"], 3),
-                     "res_history": [float(f"{x:.3e}") for x in rep["res_norm"]],
-                     "krylov": rep["krylov"],
-                     "dist_to_laminar_L2": float(f"{P.norm((uu - lam).contiguous()):.4e}")}
-        if name != "fp64" and "fp64" in finals:
-            out[name]["vs_fp64_final_L2"] = float(
-                f"{P.norm((uu - finals['fp64']).contiguous()):.3e}")
-        log("large newton", name, out[name])
-    P.set_precision(SP_FP64)
+        roots[name] = x
+        sub_out[name] = {"converged": rep["converged"], "newton_iters": rep["newton_iters"],
+                         "total_krylov": rep["total_krylov"], "actions": rep["total_actions"],
+                         "seconds": round(rep["seconds"], 3),
+                         "res_history": [float(f"{v:.3e}") for v in rep["res_norm"]],
+                         "krylov": rep["krylov"],
+                         "dist_to_laminar_L2": float(f"{P.norm((x - lam_s).contiguous()):.4e}")}
+        if name != "fp64":
+            sub_out[name]["vs_fp64_final_L2"] = float(
+                f"{P.norm((x - roots['fp64']).contiguous()):.3e}")
+        log("large newton (subspace)", name, sub_out[name])
+    out["subspace"] = sub_out
     del P
-    if "fp64_advected" not in variants:
-        return out
-    # the same solve with the laminar advection in the implicit operator
-    PA = Plan(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], w["re"], w["dt"], device=dev)
-    tb = time.perf_counter()
-    PA.set_advection(True)
-    torch.cuda.synchronize()
-    build_s = time.perf_counter() - tb
-    uu = u0.clone()
-    rep = PA.newton_hookstep(uu, max_newton=max_newton, max_krylov=max_krylov,
-                             gmres_rtol=rtol, newton_tol=1e-10)
-    out["fp64_advected"] = {"converged": rep["converged"], "newton_iters": rep["newton_iters"],
-                            "total_krylov": rep["total_krylov"], "actions": rep["total_actions"],
-                            "seconds": round(rep["seconds"], 3),
-                            "operator_build_seconds": round(build_s, 3),
-                            "res_history": [float(f"{x:.3e}") for x in rep["res_norm"]],
-                            "krylov": rep["krylov"],
-                            "dist_to_laminar_L2": float(
-                                f"{PA.norm((uu - lam).contiguous()):.4e}")}
-    log("large newton", "fp64_advected", out["fp64_advected"])
+    # the FP64 root on the workload's grid
+    xb_np = synth.embed_periodic(roots["fp64"].cpu().numpy(), 2, 2)
+    xb = torch.from_numpy(xb_np).to(dev)
+    PB = Plan(*big, w["lx"], w["lz"], w["re"], w["dt"], device=dev)
+    rb, rbn = PB.residual(xb, norm=True)
+    phib = PB.befe_step(xb)
+    emb = {"gpu_res_norm": float(f"{rbn:.3e}")}
+    if oracle_modes:
+        from oracle.befe import Befe
+        from oracle.grid import Grid
+        rng = np.random.default_rng(0)
+        valid = [(i, j) for i in range(big[0]) for j in range(big[2] // 2)
+                 if i != big[0] // 2]
+        pick = [valid[k] for k in rng.choice(len(valid), oracle_modes - 1, replace=False)]
+        pick = [(0, 0)] + pick
+        B = Befe(Grid(big[0], big[1], big[2], w["lx"], w["lz"]), w["re"], w["dt"], modes=pick)
+        to = time.perf_counter()
+        ro = B.residual(xb_np)
+        rg = rb.cpu().numpy()
+        sel = np.zeros_like(ro)
+        for (i, j) in pick:
+            sel[:, i, j, :] = 1.0
+        scale = (PB.norm(phib) + PB.norm(xb)) / w["dt"]
+        emb.update({"oracle_modes": len(pick),
+                    "oracle_res_norm_sampled": float(f"{B.norm_l2(ro * sel):.3e}"),
+                    "gpu_res_norm_sampled": float(f"{B.norm_l2(rg * sel):.3e}"),
+                    "max_abs_diff_over_scale": float(
+                        f"{np.max(np.abs((rg - ro) * sel)) / scale:.3e}"),
+                    "oracle_seconds": round(time.perf_counter() - to, 1)})
+    out["embedded_root"] = emb
+    log("large newton (embedded root)", emb)
+    # full-space Newton from the embedded Re-1950 root
+    lam_b = torch.from_numpy(synth.laminar_field(*big)).to(dev)
+    x = torch.from_numpy(synth.embed_periodic(u.cpu().numpy(), 2, 2)).to(dev)
+    rep = PB.newton_hookstep(x, max_newton=full_newton, max_krylov=max_krylov, gmres_rtol=rtol,
+                             newton_tol=1e-10)
+    out["full_space_fp64"] = {
+        "converged": rep["converged"], "newton_iters": rep["newton_iters"],
+        "seconds": round(rep["seconds"], 3),
+        "res_history": [float(f"{v:.3e}") for v in rep["res_norm"]],
+        "gmres_relres": [float(f"{v:.2e}") for v in rep["gmres_relres"]],
+        "dist_to_laminar_L2": float(f"{PB.norm((x - lam_b).contiguous()):.4e}")}
+    log("large newton (full space)", out["full_space_fp64"])
     return out
 
 
@@ -799,15 +910,18 @@ def main():
     ap.add_argument("--no-oracle-newton", action="store_true",
                     help="skip the oracle's residual norms at the Newton iterates")
     ap.add_argument("--large-newton", action="store_true",
-                    help="instead of the benchmark line, run hookstep Newton to 1e-10 at "
-                         "96x97x96, Re 2000, from the streak + roll start (FP64 and mixed)")
+                    help="instead of the benchmark line, reach Re 2000 at 96x97x96 (4pi x 2pi "
+                         "box) by continuation and time hookstep Newton to 1e-10 there "
+                         "(several minutes)")
     ap.add_argument("--large-krylov", type=int, default=0,
-                    help="Krylov cap of --large-newton (default 200)")
+                    help="Krylov cap of --large-newton (default 800)")
     ap.add_argument("--large-steps", type=int, default=0,
-                    help="Newton steps of --large-newton (default 30)")
-    ap.add_argument("--large-variants", default="",
-                    help="comma-separated subset of fp64, mixed, mixed_krylov_fp32, "
-                         "fp64_advected for --large-newton")
+                    help="Newton steps of the timed solves of --large-newton (default 20)")
+    ap.add_argument("--large-full-steps", type=int, default=-1,
+                    help="Newton steps on the full 96x97x96 grid in --large-newton (default 8)")
+    ap.add_argument("--large-oracle-modes", type=int, default=-1,
+                    help="modes of the oracle residual check in --large-newton (default 24, 0 "
+                         "to skip)")
     ap.add_argument("--mixed-error", action="store_true",
                     help="instead of the benchmark line, print the per-Newton-step distance of "
                          "the mixed-precision iterates from the FP64 ones at 48x65x48")
@@ -841,8 +955,10 @@ def main():
             kw["max_krylov"] = args.large_krylov
         if args.large_steps:
             kw["max_newton"] = args.large_steps
-        if args.large_variants:
-            kw["variants"] = tuple(args.large_variants.split(","))
+        if args.large_full_steps >= 0:
+            kw["full_newton"] = args.large_full_steps
+        if args.large_oracle_modes >= 0:
+            kw["oracle_modes"] = args.large_oracle_modes
         print(json.dumps(large_newton(**kw)), flush=True)
         return
     if args.mixed_error:

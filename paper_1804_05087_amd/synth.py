@@ -213,3 +213,23 @@ def regrid(a: np.ndarray, nx: int, ny: int, nz: int) -> np.ndarray:
     for m in range(-(hx - 1), hx):
         out[:, m % nx, :hz, :n] = a[:, m % ax, :hz, :n]
     return hermitian_project(out)
+
+
+def embed_periodic(a: np.ndarray, fx: int, fz: int) -> np.ndarray:
+    """The canonical field a of an Lx x Lz box as a field of the fx Lx x fz Lz
+    box (integers fx, fz >= 1): the same function of (x, y, z), periodic
+    extension, so mode (m_x, m_z) moves to (fx m_x, fz m_z) of an
+    (fx nx) x (fz nz) grid and every other mode is zero. An equilibrium of the
+    small box is one of the large box, in its subspace of fields invariant
+    under the translations by Lx and Lz."""
+    a = np.asarray(a)
+    _, nxs, nzhs, ny = a.shape
+    nxb, nzb = fx * nxs, fz * 2 * (nzhs - 1)
+    out = np.zeros((3, nxb, nzb // 2 + 1, ny), dtype=np.complex128)
+    for i in range(nxs):
+        if i == nxs // 2:
+            continue  # Nyquist: zero in canonical fields
+        m = i if i < nxs // 2 else i - nxs
+        for j in range(nzhs - 1):
+            out[:, (fx * m) % nxb, fz * j, :] = a[:, i, j, :]
+    return out
