@@ -1133,7 +1133,8 @@ def main():
                               "newton_tol": 1e-10, "driver": "sp_newton_gmres (full step)"}
         finals, iterates = {}, {}
         for name, prec, kf32 in (("fp64", SP_FP64, False), ("mixed", SP_MIXED, False),
-                                 ("mixed_krylov_fp32", SP_MIXED, True)):
+                                 ("mixed_krylov_fp32", SP_MIXED, True),
+                                 ("fp64_krylov_fp32", SP_FP64, True)):
             P.set_precision(prec)
             uu = u0.clone()
             torch.cuda.synchronize()
@@ -1165,7 +1166,7 @@ def main():
             iterates[name] = its
             newton[name]["replay_final_vs_timed_L2"] = P.norm((its[-1] - finals[name]).contiguous())
         P.set_precision(SP_FP64)
-        for name in ("mixed", "mixed_krylov_fp32"):
+        for name in ("mixed", "mixed_krylov_fp32", "fp64_krylov_fp32"):
             ref = iterates["fp64"]
             newton[name]["dist_to_fp64_iterate_L2"] = [
                 float(f"{P.norm((a - b).contiguous()):.3e}")
@@ -1180,6 +1181,8 @@ def main():
         newton["mixed_vs_fp64_final_L2"] = P.norm((finals["mixed"] - finals["fp64"]).contiguous())
         newton["mixed_krylov_fp32_vs_fp64_final_L2"] = P.norm(
             (finals["mixed_krylov_fp32"] - finals["fp64"]).contiguous())
+        newton["fp64_krylov_fp32_vs_fp64_final_L2"] = P.norm(
+            (finals["fp64_krylov_fp32"] - finals["fp64"]).contiguous())
         # the same solve with the laminar advection in the implicit operator
         # (Sec. 3.6's proposed remedy; same roots, fewer Krylov iterations)
         PA = Plan(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], w["re"], w["dt"], device=dev)
