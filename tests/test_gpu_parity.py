@@ -223,3 +223,26 @@ def test_newton_history_matches_oracle(torch_mod):
     assert rep["krylov"] == rep_ref["krylov"]
     for a, b in zip(rep["res_norm"], rep_ref["res_norm"]):
         assert abs(a - b) <= 1e-8 * b
+
+
+@pytest.mark.parametrize("kf32", [False, True])
+def test_newton_history_matches_oracle_nonsquare_even_ny(torch_mod, kf32):
+    """The same comparison on a grid with nx != nz and even ny (the compact
+    Krylov layout's runs differ in length between m_x < nx/2 and m_x > nx/2,
+    and the m_z = 0 plane's mirrors sit nz/2+1 slots apart), with the FP64 and
+    the FP32 basis; the FP32 basis is held to its own accuracy (the oracle's
+    GMRES is FP64 throughout)."""
+    from oracle import krylov
+    say("newton nonsquare", kf32)
+    dims = (12, 20, 16)
+    g, B, P = _setup(dims, 400.0, 100.0)
+    u0 = synth.perturbation_field(*dims, *BOX, seed=1)
+    _, rep_ref = krylov.newton_befe(B, u0, 1e-10, 2, 12, 1e-6)
+    u = to_dev(u0)
+    rep = P.newton_gmres(u, max_newton=2, max_krylov=12, gmres_rtol=1e-6, newton_tol=1e-10,
+                         krylov_fp32=kf32)
+    say("gpu", rep["res_norm"], rep["krylov"], "oracle", rep_ref["res_norm"], rep_ref["krylov"])
+    assert rep["krylov"] == rep_ref["krylov"]
+    tol = 1e-4 if kf32 else 1e-8
+    for a, b in zip(rep["res_norm"], rep_ref["res_norm"]):
+        assert abs(a - b) <= tol * b
