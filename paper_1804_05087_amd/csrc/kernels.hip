@@ -554,18 +554,25 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
       wsweep<E>(helm, hw, N, pv, vrow ? Rv : Rp, bu, vrow ? P : U, l);
     }
   } else {
-    if (work) wderiv<E>(N, pv, vrow ? Fv : Rp, vrow ? A : Dm, l);
-    __syncthreads();
-    if (work && vrow) SP_ROW_PAR(po, divF[n] = mul_i(Fpar[n] * k) + A[n];)
+    // divF = i k F_par + D F_v on rows 0, 1, formed as the derivative is stored
+    // (rows 2, 3 differentiate into the idle array: a per-lane select, no branch)
+    if (work)
+      wderiv<E>(N, pv, vrow ? Fv : Rp, vrow ? divF : Dm, l, [&](int m, cd v) {
+        const cd t = mul_i(Fpar[m] * k) + v;
+        return vrow ? t : v;
+      });
     __syncthreads();
     // P = Pois(div F) on rows 0, 1; U = Helm(-F_perp) on rows 2, 3
     if (work)
       wsweep<E>(vrow ? pois : helm, hw, N, vrow ? po : pv,
                 vrow ? divF : Rp, cd(0.0), vrow ? P : U, l);
     __syncthreads();
-    if (work) wderiv<E>(N, po, vrow ? P : Rp, vrow ? A : Dm, l);
-    __syncthreads();
-    if (work && vrow) SP_ROW_PAR(pv, Rv[n] = A[n] - Fv[n];)
+    // Rv = D P - F_v on rows 0, 1, formed as the derivative is stored
+    if (work)
+      wderiv<E>(N, po, vrow ? P : Rp, vrow ? Rv : Dm, l, [&](int m, cd v) {
+        const cd t = v - Fv[m];
+        return vrow ? t : v;
+      });
     __syncthreads();
     if (work) wsweep<E>(helm, hw, N, pv, vrow ? Rv : Rp, cd(0.0), vrow ? V : Dm, l);
     __syncthreads();
@@ -585,9 +592,14 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
     const double* vdel = rec + L.vdel();
     const double* vb = rec + L.vb();
     __syncthreads();
-    if (work && vrow) SP_ROW_PAR(pv, V[n] = V[n] + ca * vdel[n] + cb * vb[n];)
-    __syncthreads();
-    if (work) wderiv<E>(N, pv, vrow ? V : Rp, vrow ? A : Dm, l);
+    // V += c_delta vdel + c_b vb on rows 0, 1, taken as the derivative loads V (the
+    // lane that owns n updates it and stores it back for the output)
+    if (work)
+      wderiv<E>(N, pv, vrow ? V : Rp, vrow ? A : Dm, l, StoreDeriv(), [&](int n, cd v, bool own) {
+        const cd t = v + ca * vdel[n] + cb * vb[n];
+        if (vrow && own) V[n] = t;
+        return vrow ? t : v;
+      });
   }
   __syncthreads();
   if (!work) return;

@@ -182,9 +182,24 @@ __device__ inline void wsweep(SweepRec sw, const double* __restrict__ hw, int N,
   }
 }
 
-// b = D a for the parity-pa entries of a (b: parity 1-pa entries, b_N = 0 if it exists).
-template <int E>
-__device__ inline void wderiv(int N, int pa, const cd* a, cd* bout, int l) {
+// Stores its argument (the plain derivative).
+struct StoreDeriv {
+  __device__ cd operator()(int, cd v) const { return v; }
+};
+
+// Uses the loaded entry as it is.
+struct LoadDeriv {
+  __device__ cd operator()(int, cd v, bool) const { return v; }
+};
+
+// b = D a for the parity-pa entries of a (b: parity 1-pa entries, b_N = 0 if it exists);
+// bout[m] receives post(m, b_m), so that an element-wise step on b is taken where
+// each entry is stored, and entry a_n enters as pre(n, a_n, own), own telling the
+// one lane that owns n (the lane of chain position (n - pa) / 2, as in SP_ROW_PAR),
+// so that an element-wise step on a is taken where each entry is loaded.
+template <int E, class Post = StoreDeriv, class Pre = LoadDeriv>
+__device__ inline void wderiv(int N, int pa, const cd* a, cd* bout, int l, Post post = Post(),
+                              Pre pre = Pre()) {
   const int nmax = top_index(N, pa);
   const int K = (nmax - pa) / 2;
   cd c[E], x[E];
@@ -195,16 +210,16 @@ __device__ inline void wderiv(int N, int pa, const cd* a, cd* bout, int l) {
     const int n = pa + 2 * k;
     one[e] = 1.0;
     const int nc = (k <= K) ? n : nmax;
-    c[e] = a[nc] * ((2.0 * n) * mask(k <= K && n >= 1));
+    c[e] = pre(nc, a[nc], k <= K) * ((2.0 * n) * mask(k <= K && n >= 1));
   }
   rec_down<E>(c, one, cd(0.0), x);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int k = l * E + e;
     const int n = pa + 2 * k;
-    if (k <= K && n >= 1) bout[n - 1] = (n == 1) ? x[e] * 0.5 : x[e];
+    if (k <= K && n >= 1) bout[n - 1] = post(n - 1, (n == 1) ? x[e] * 0.5 : x[e]);
   }
-  if (l == 0 && nmax + 1 <= N) bout[nmax + 1] = cd(0.0);
+  if (l == 0 && nmax + 1 <= N) bout[nmax + 1] = post(nmax + 1, cd(0.0));
 }
 
 // Transposes (adjoint, beta = 0): rbar = H^T gbar on the parity-p chain.
