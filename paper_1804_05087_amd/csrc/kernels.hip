@@ -267,6 +267,11 @@ __global__ void __launch_bounds__(256)
 // (0,0) mode: rows 0, 1 solve for u (parity r), rows 2, 3 for w (parity r - 2).
 // Rows without work in a step run it on a dummy array.
 // ---------------------------------------------------------------------------
+// Orders one wave's LDS accesses between two steps of the solve when no other
+// wave of the block takes part: a workgroup-scope fence waits for the wave's
+// LDS operations and keeps the compiler from moving any across it.
+__device__ inline void lds_order() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup"); }
+
 #define SP_ROW_PAR(par, body)                       \
   _Pragma("unroll") for (int e_ = 0; e_ < E; ++e_) { \
     const int n = (par) + 2 * (l * E + e_);          \
@@ -323,8 +328,7 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
   const int mode = i * nzh + j;
   // With the fused analysis (AN != 0) a mode has two waves: wave 1 loads half of
   // the record and sums half of the analysis' terms, hands its partial sums to
-  // wave 0, and from then on only takes part in the barriers (a wave-uniform
-  // branch skips its work); wave 0 does everything else.
+  // wave 0 and leaves; wave 0 does everything else.
   constexpr int NW = (AN != 0) ? 2 : 1;
   const int tid = threadIdx.x & 63;
   const bool shadow = (threadIdx.x >> 6) != 0;
@@ -520,8 +524,11 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
       gc[t] = make_double2(((double)a2r + xa * x2.x) * keep, ((double)a2i + xa * x2.y) * keep);
     }
   }
-  const bool work = !shadow;  // wave-uniform: wave 1 only meets the barriers below
-  if (work) {
+  // wave 1's part ended with the analysis' last barrier (it is uniform per wave):
+  // from here on one wave works, and its steps exchange data through LDS,
+  // ordered by lds_order() instead of barriers
+  if (shadow) return;
+  {
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       const int n = tid + 64 * t;
@@ -540,7 +547,7 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
       }
     }
   }
-  __syncthreads();
+  lds_order();
   const ModeLayout L{n1};
   const SweepRec helm(rec + L.helm(), n1, lam);
   const SweepRec pois(rec + L.pois(), n1, k2);
@@ -548,37 +555,32 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
   const int pv = row & 1;  // v parity (rows 0, 1), u_perp / w parity (rows 2, 3)
   const int po = 1 - pv;
   if (mean) {
-    if (work) {
-      cd bu(0.0);
-      if (inhomogeneous && vrow) bu = cd(pv == 0 ? 0.5 * (wu + wl) : 0.5 * (wu - wl));
-      wsweep<E>(helm, hw, N, pv, vrow ? Rv : Rp, bu, vrow ? P : U, l);
-    }
+    cd bu(0.0);
+    if (inhomogeneous && vrow) bu = cd(pv == 0 ? 0.5 * (wu + wl) : 0.5 * (wu - wl));
+    wsweep<E>(helm, hw, N, pv, vrow ? Rv : Rp, bu, vrow ? P : U, l);
   } else {
     // divF = i k F_par + D F_v on rows 0, 1, formed as the derivative is stored
     // (rows 2, 3 differentiate into the idle array: a per-lane select, no branch)
-    if (work)
-      wderiv<E>(N, pv, vrow ? Fv : Rp, vrow ? divF : Dm, l, [&](int m, cd v) {
-        const cd t = mul_i(Fpar[m] * k) + v;
-        return vrow ? t : v;
-      });
-    __syncthreads();
+    wderiv<E>(N, pv, vrow ? Fv : Rp, vrow ? divF : Dm, l, [&](int m, cd v) {
+      const cd t = mul_i(Fpar[m] * k) + v;
+      return vrow ? t : v;
+    });
+    lds_order();
     // P = Pois(div F) on rows 0, 1; U = Helm(-F_perp) on rows 2, 3
-    if (work)
-      wsweep<E>(vrow ? pois : helm, hw, N, vrow ? po : pv,
-                vrow ? divF : Rp, cd(0.0), vrow ? P : U, l);
-    __syncthreads();
+    wsweep<E>(vrow ? pois : helm, hw, N, vrow ? po : pv, vrow ? divF : Rp, cd(0.0), vrow ? P : U,
+              l);
+    lds_order();
     // Rv = D P - F_v on rows 0, 1, formed as the derivative is stored
-    if (work)
-      wderiv<E>(N, po, vrow ? P : Rp, vrow ? Rv : Dm, l, [&](int m, cd v) {
-        const cd t = v - Fv[m];
-        return vrow ? t : v;
-      });
-    __syncthreads();
-    if (work) wsweep<E>(helm, hw, N, pv, vrow ? Rv : Rp, cd(0.0), vrow ? V : Dm, l);
-    __syncthreads();
+    wderiv<E>(N, po, vrow ? P : Rp, vrow ? Rv : Dm, l, [&](int m, cd v) {
+      const cd t = v - Fv[m];
+      return vrow ? t : v;
+    });
+    lds_order();
+    wsweep<E>(helm, hw, N, pv, vrow ? Rv : Rp, cd(0.0), vrow ? V : Dm, l);
+    lds_order();
     // influence correction: (c_delta, c_b) = -Minv (D v(1), tau definition)
     cd ca(0.0), cb(0.0);
-    if (work) {
+    {
       cd la(0.0);
       SP_ROW_PAR(pv, la = la + V[n] * ((double)n * n);)
       la = row_sum(la);
@@ -591,18 +593,16 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
     }
     const double* vdel = rec + L.vdel();
     const double* vb = rec + L.vb();
-    __syncthreads();
+    lds_order();
     // V += c_delta vdel + c_b vb on rows 0, 1, taken as the derivative loads V (the
     // lane that owns n updates it and stores it back for the output)
-    if (work)
-      wderiv<E>(N, pv, vrow ? V : Rp, vrow ? A : Dm, l, StoreDeriv(), [&](int n, cd v, bool own) {
-        const cd t = v + ca * vdel[n] + cb * vb[n];
-        if (vrow && own) V[n] = t;
-        return vrow ? t : v;
-      });
+    wderiv<E>(N, pv, vrow ? V : Rp, vrow ? A : Dm, l, StoreDeriv(), [&](int n, cd v, bool own) {
+      const cd t = v + ca * vdel[n] + cb * vb[n];
+      if (vrow && own) V[n] = t;
+      return vrow ? t : v;
+    });
   }
-  __syncthreads();
-  if (!work) return;
+  lds_order();
   for (int n = tid; n < n1; n += 64) {
     cd uo, vo, wo;
     if (mean) {
