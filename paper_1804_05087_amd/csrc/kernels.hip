@@ -447,9 +447,11 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
     const R* Ti = reinterpret_cast<const R*>(tinv_raw);
     __syncthreads();
     const int tmax = (N - 2) / 64 + 1;  // passes over n <= N-2 (uniform)
-    // groups of 8 folded terms: wave 0 sums [0, gsplit), wave 1 [gsplit, ng)
+    // groups of 8 folded terms: wave 0 sums [0, gsplit), wave 1 [gsplit, ng), the
+    // larger share to wave 1 (wave 0 also stores the folded columns before, and
+    // goes on with the solve after)
     const int ng = jh8 / 8;
-    const int gsplit = (NW == 2) ? (ng + 1) / 2 : ng;
+    const int gsplit = (NW == 2) ? ng / 2 : ng;
     const int gbeg = shadow ? gsplit : 0;
     const int gend = shadow ? ng : gsplit;
     R* part = reinterpret_cast<R*>(colO + 3 * jh8);  // [6][64] partial sums of wave 1
