@@ -517,7 +517,7 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
         a1i += part[192 + tid];
         a2r += part[256 + tid];
         a2i += part[320 + tid];
-        __syncthreads();  // the next pass rewrites part
+        if (t + 1 < tmax) __syncthreads();  // the next pass rewrites part (uniform)
       }
       const double keep = n <= N - 2 ? 1.0 : 0.0;
       const double2 x0 = ga[t], x1 = gb[t], x2 = gc[t];
