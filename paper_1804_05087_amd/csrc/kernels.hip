@@ -605,7 +605,12 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
     });
   }
   lds_order();
-  for (int n = tid; n < n1; n += 64) {
+  // n1 <= 32 E coefficients: a fixed, unrolled pass count, so the LDS reads of
+  // every pass are issued together
+#pragma unroll
+  for (int q = 0; q < (32 * E + 63) / 64; ++q) {
+    const int n = tid + 64 * q;
+    if (n >= n1) break;
     cd uo, vo, wo;
     if (mean) {
       uo = P[n];
