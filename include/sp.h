@@ -274,6 +274,10 @@ typedef struct {
                            relative, so gmres_rtol should be >= 1e-6)        */
 } sp_newton_opts;
 
+/* total_actions counts the residual evaluations and the Jacobian actions
+ * performed. The device runs one Arnoldi iteration ahead of the host's stop
+ * test, so a GMRES solve that stops before max_krylov performs two actions
+ * beyond its last basis direction (one at max_krylov). */
 typedef struct {
   int32_t converged, newton_iters, total_krylov, total_actions;
   double seconds;
@@ -284,7 +288,9 @@ typedef struct {
 
 /* Newton-GMRES on r(U) = (Phi_dt(U) - U)/dt = 0 (Sec. 2): U <- U - du with
  * J_r du = r solved by unrestarted GMRES (x0 = 0, classical Gram-Schmidt with
- * reorthogonalisation, Givens rotations) in the packed Euclidean product.
+ * reorthogonalisation, Givens rotations) in the packed Euclidean product. The
+ * Arnoldi iterations run on the device without a host round trip; the host
+ * applies the rotations and the stop test one iteration behind.
  * u_inout: initial guess in, final iterate out. Synchronises. Returns SP_OK on
  * convergence, SP_ERR_NOT_CONVERGED otherwise (report filled either way). */
 sp_status sp_newton_gmres(sp_plan* plan, double* u_inout, const sp_newton_opts* opts,

@@ -65,6 +65,11 @@ size_t ws_bytes_for(const sp_plan* p, int K) {
   b += align256(canon_bytes(p));                           // u_j, canonical FP64
   b += align256((size_t)2 * (K + 1) * multidot_blocks(p) * sizeof(double));  // partials
   b += 3 * align256((size_t)2 * (K + 2) * sizeof(double));  // dots, a|c, y
+  b += align256((size_t)(K + 1) * K * sizeof(double));      // Hessenberg matrix
+  b += align256((size_t)(K + 2) * sizeof(double));          // provisional column
+  b += align256((size_t)(K + 2) * sizeof(double));          // H a
+  b += align256(sizeof(double));                            // 1 / gamma
+  b += align256((size_t)2 * (K + 5) * sizeof(double));      // two host records
   return b;
 }
 
@@ -77,6 +82,11 @@ struct Workspace {
   double* h1;
   double* h2;
   double* y;
+  double* H;      // (K+1) x K, row-major
+  double* hprev;  // K+2
+  double* ha;     // K+2
+  double* ig;     // 1
+  double* rec;    // 2 (K+5)
 };
 
 Workspace carve(sp_plan* p, int K) {
@@ -97,6 +107,16 @@ Workspace carve(sp_plan* p, int K) {
   W.h2 = (double*)c;
   c += align256((size_t)2 * (K + 2) * sizeof(double));
   W.y = (double*)c;
+  c += align256((size_t)2 * (K + 2) * sizeof(double));
+  W.H = (double*)c;
+  c += align256((size_t)(K + 1) * K * sizeof(double));
+  W.hprev = (double*)c;
+  c += align256((size_t)(K + 2) * sizeof(double));
+  W.ha = (double*)c;
+  c += align256((size_t)(K + 2) * sizeof(double));
+  W.ig = (double*)c;
+  c += align256(sizeof(double));
+  W.rec = (double*)c;
   return W;
 }
 
@@ -171,14 +191,25 @@ sp_status ensure_workspace(sp_plan* p, int K) {
 // orthonormal in the packed product), R the Givens-rotated Hessenberg matrix (upper
 // triangular kd x kd, column-major with leading dimension K+1), g the rotated
 // right-hand side (g[kd] the least-squares residual), beta = ||r||.
+//
+// Each Arnoldi iteration runs on the device from end to end: the Jacobian
+// action, the fused projections, the coefficients (launch_arnoldi_coef) and the
+// update pass. The host only reads each iteration's Hessenberg column back
+// (a small record copied to pinned memory) and applies the Givens rotations
+// and the stop test one iteration behind the device, so the device never waits
+// for it. When the test stops the solve at iteration j, iteration j + 1 has
+// already been queued; its work writes only basis slots j + 1 and above and
+// the Jacobian action's buffers, none of which the solution uses, and its
+// action is counted.
 struct Gmres {
   sp_plan* p;
   const sp_newton_opts* o;
   int K;
   Workspace W;
   size_t canon, nc, nk;
-  double* hbuf = nullptr;  // pinned: dots[2(K+2)], a|c[2(K+2)]
-  std::vector<double> H, R, cs, sn, g, hprev, a, b, Ha, cvec;
+  double* hrec = nullptr;  // pinned: two records of K+5 doubles
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::vector<double> H, R, cs, sn, g;
   int kd = 0;
   double beta = 0.0, relres = 1.0;
   // slot j of the basis holds q_j (u_j while iteration j runs), in FP64 (W.V)
@@ -191,26 +222,114 @@ struct Gmres {
       : p(p_), o(o_), K(o_->max_krylov), W(carve(p_, o_->max_krylov)),
         canon(canon_bytes(p_)), nc(canon_bytes(p_) / sizeof(double2)),
         nk((size_t)compact_map(p_->d).len),
-        f32(o_->krylov_fp32 != 0), Vf((float2*)W.V),
-        H((size_t)(K + 1) * K), R((size_t)(K + 1) * K), cs(K), sn(K), g(K + 1), hprev(K + 1),
-        a(K + 1), b(K + 1), Ha(K + 1), cvec(K + 1) {}
+        H((size_t)(K + 1) * K), R((size_t)(K + 1) * K), cs(K), sn(K), g(K + 1),
+        f32(o_->krylov_fp32 != 0), Vf((float2*)W.V) {}
   ~Gmres() {
-    if (hbuf) (void)hipHostFree(hbuf);
+    // the queued work may still use the pinned records
+    if (hrec || ev[0] || ev[1]) (void)hipStreamSynchronize(p->stream);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (hrec) (void)hipHostFree(hrec);
   }
   sp_status init() {
-    SP_TRY_HIP(hipHostMalloc((void**)&hbuf, 4 * (K + 2) * sizeof(double)), "hipHostMalloc");
+    SP_TRY_HIP(hipHostMalloc((void**)&hrec, 2 * (K + 5) * sizeof(double)), "hipHostMalloc");
+    for (hipEvent_t& e : ev)
+      SP_TRY_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
     return SP_OK;
   }
   double& Hat(int i, int k) { return H[(size_t)k * (K + 1) + i]; }
   double& Rat(int i, int k) { return R[(size_t)k * (K + 1) + i]; }
 
+  // Queues iteration j: u_j -> w = J u_j (none at j = K, which only completes
+  // column K-1), the dots of q_0..q_{j-1} and u_j with u_j and w, the
+  // coefficients, the update pass (q_j into slot j, u_{j+1} into slot j+1 and
+  // W.u), and the copy of the record to pinned slot j % 2.
+  sp_status enqueue(int j, const double2* U, const double2* r, double unorm, int* actions) {
+    double2* uj = W.u;
+    double* d_dots = W.h1;  // 2 (K + 2) doubles
+    double* d_ac = W.h2;    // a[0..K+1] then c[0..K+1]
+    const bool last = (j == K);
+    if (!last) {
+      if (o->jvp_mode == 0) {
+        SP_TRY(jvp_lin(p, SP_OP_RESIDUAL, uj, W.w));
+      } else {
+        // finite difference along u_j / ||u_j||, scaled back by ||u_j||
+        double uu = 0.0;
+        SP_TRY(dot_host(p, uj, uj, W.partial, W.h1, &uu));
+        const double un = std::sqrt(uu > 0 ? uu : 1.0);
+        const double eps = o->fd_eps * (unorm > 0 ? unorm : 1.0) / un;
+        SP_TRY_HIP(launch_axpby(p, U, 1.0, uj, eps, W.s, nc), "axpby");
+        SP_TRY(residual_into(p, W.s, W.w));
+        SP_TRY_HIP(launch_axpby(p, W.w, 1.0 / eps, r, -1.0 / eps, W.w, nc), "axpby");
+      }
+      *actions += 1;
+      // the exact residual JVP already writes the Hermitian form
+      if (o->jvp_mode != 0) SP_TRY_HIP(launch_hermitian(p, W.w), "hermitian");
+    }
+    if (f32)
+      SP_TRY_HIP(launch_krylov_multidot2(p, Vf, j + 1, uj, last ? uj : W.w, W.partial, d_dots),
+                 "multidot");
+    else
+      SP_TRY_HIP(launch_krylov_multidot2(p, W.V, j + 1, uj, last ? uj : W.w, W.partial, d_dots),
+                 "multidot");
+    double* rec = W.rec + (size_t)(j & 1) * (K + 5);
+    SP_TRY_HIP(launch_arnoldi_coef(p, j, K, K + 2, d_dots, W.H, W.hprev, W.ha, d_ac, W.ig, rec),
+               "arnoldi coefficients");
+    if (!last) {
+      if (f32)
+        SP_TRY_HIP(launch_dcgs2_update(p, Vf, j, d_ac, d_ac + (K + 2), W.ig, W.w,
+                                       Vf + (size_t)(j + 1) * nk, W.u),
+                   "dcgs2 update");
+      else
+        SP_TRY_HIP(launch_dcgs2_update(p, W.V, j, d_ac, d_ac + (K + 2), W.ig, W.w,
+                                       W.V + (size_t)(j + 1) * nk, W.u),
+                   "dcgs2 update");
+    }
+    SP_TRY_HIP(hipMemcpyAsync(hrec + (size_t)(j & 1) * (K + 5), rec, (5 + j) * sizeof(double),
+                              hipMemcpyDeviceToHost, p->stream),
+               "copy record");
+    SP_TRY_HIP(hipEventRecord(ev[j & 1], p->stream), "record event");
+    return SP_OK;
+  }
+
+  // Waits for iteration j's record, completes column j-1 of the host's H,
+  // rotates it and tests convergence of the j-dimensional space.
+  sp_status take(int j, bool* stop) {
+    SP_TRY_HIP(hipEventSynchronize(ev[j & 1]), "sync");
+    const double* rc = hrec + (size_t)(j & 1) * (K + 5);
+    const double gamma = rc[0];
+    if (!std::isfinite(rc[1])) return set_error(p, SP_ERR_NONFINITE, "Arnoldi norm not finite");
+    *stop = false;
+    if (j == 0) {
+      beta = gamma;
+      if (!(beta > 0)) return set_error(p, SP_ERR_NONFINITE, "zero or non-finite residual");
+      g[0] = beta;
+      return SP_OK;
+    }
+    const int k = j - 1;
+    for (int i = 0; i <= j; ++i) Hat(i, k) = rc[4 + i];
+    for (int i = 0; i <= j; ++i) Rat(i, k) = Hat(i, k);
+    for (int i = 0; i < k; ++i) {
+      const double t = cs[i] * Rat(i, k) + sn[i] * Rat(i + 1, k);
+      Rat(i + 1, k) = -sn[i] * Rat(i, k) + cs[i] * Rat(i + 1, k);
+      Rat(i, k) = t;
+    }
+    const double dd = std::hypot(Rat(k, k), Rat(k + 1, k));
+    cs[k] = Rat(k, k) / dd;
+    sn[k] = Rat(k + 1, k) / dd;
+    Rat(k, k) = dd;
+    Rat(k + 1, k) = 0.0;
+    g[k + 1] = -sn[k] * g[k];
+    g[k] = cs[k] * g[k];
+    kd = j;
+    relres = std::fabs(g[k + 1]) / beta;
+    *stop = std::fabs(g[k + 1]) <= o->gmres_rtol * beta || !(gamma > 0) || j == K;
+    return SP_OK;
+  }
+
   // U the linearisation point (its base state must be cached for the exact
   // JVP), r = r(U); unorm = ||U|| for the finite-difference mode.
   sp_status solve(const double2* U, const double2* r, double unorm, int* actions) {
-    double* hdots = hbuf;              // [2 v + r]: r = 0 against u_j, r = 1 against w
-    double* hac = hbuf + 2 * (K + 2);  // a[0..K+1] then c[0..K+1]
-    double* d_dots = W.h1;             // 2 (K + 2) doubles
-    double* d_ac = W.h2;               // 2 (K + 2) doubles
     // u_0 = r (unnormalised; gamma_0 = ||r|| comes out of the first reduction)
     SP_TRY_HIP(hipMemcpyAsync(W.u, r, canon, hipMemcpyDeviceToDevice, p->stream), "copy r");
     SP_TRY_HIP(launch_hermitian(p, W.u), "hermitian");
@@ -224,104 +343,11 @@ struct Gmres {
     beta = 0.0;
     kd = 0;
     relres = 1.0;
-    for (int j = 0; j <= K; ++j) {
-      double2* uj = W.u;
-      const bool last = (j == K);  // only completes column K-1: no new direction
-      if (!last) {
-        if (o->jvp_mode == 0) {
-          SP_TRY(jvp_lin(p, SP_OP_RESIDUAL, uj, W.w));
-        } else {
-          // finite difference along u_j / ||u_j||, scaled back by ||u_j||
-          double uu = 0.0;
-          SP_TRY(dot_host(p, uj, uj, W.partial, W.h1, &uu));
-          const double un = std::sqrt(uu > 0 ? uu : 1.0);
-          const double eps = o->fd_eps * (unorm > 0 ? unorm : 1.0) / un;
-          SP_TRY_HIP(launch_axpby(p, U, 1.0, uj, eps, W.s, nc), "axpby");
-          SP_TRY(residual_into(p, W.s, W.w));
-          SP_TRY_HIP(launch_axpby(p, W.w, 1.0 / eps, r, -1.0 / eps, W.w, nc), "axpby");
-        }
-        *actions += 1;
-        // the exact residual JVP already writes the Hermitian form
-        if (o->jvp_mode != 0) SP_TRY_HIP(launch_hermitian(p, W.w), "hermitian");
-      }
-      // dots of q_0..q_{j-1} and u_j with u_j and with w
-      if (f32)
-        SP_TRY_HIP(
-            launch_krylov_multidot2(p, Vf, j + 1, uj, last ? uj : W.w, W.partial, d_dots),
-            "multidot");
-      else
-        SP_TRY_HIP(
-            launch_krylov_multidot2(p, W.V, j + 1, uj, last ? uj : W.w, W.partial, d_dots),
-            "multidot");
-      SP_TRY_HIP(hipMemcpyAsync(hdots, d_dots, 2 * (j + 1) * sizeof(double),
-                                hipMemcpyDeviceToHost, p->stream),
-                 "copy dots");
-      SP_TRY_HIP(hipStreamSynchronize(p->stream), "sync");
-      double aa = 0.0;
-      for (int i = 0; i < j; ++i) {
-        a[i] = hdots[2 * i];
-        b[i] = hdots[2 * i + 1];
-        aa += a[i] * a[i];
-      }
-      const double alpha = hdots[2 * j];
-      const double uw = hdots[2 * j + 1];
-      const double g2 = alpha - aa;
-      if (!std::isfinite(g2)) return set_error(p, SP_ERR_NONFINITE, "Arnoldi norm not finite");
-      const double gamma = g2 > 0 ? std::sqrt(g2) : 0.0;
-      bool stop = false;
-      if (j == 0) {
-        beta = gamma;
-        if (!(beta > 0)) return set_error(p, SP_ERR_NONFINITE, "zero or non-finite residual");
-        g[0] = beta;
-      } else {
-        // complete column j-1, rotate it, test convergence of the j-dimensional space
-        const int k = j - 1;
-        for (int i = 0; i < j; ++i) Hat(i, k) = hprev[i] + a[i];
-        Hat(j, k) = gamma;
-        for (int i = 0; i <= j; ++i) Rat(i, k) = Hat(i, k);
-        for (int i = 0; i < k; ++i) {
-          const double t = cs[i] * Rat(i, k) + sn[i] * Rat(i + 1, k);
-          Rat(i + 1, k) = -sn[i] * Rat(i, k) + cs[i] * Rat(i + 1, k);
-          Rat(i, k) = t;
-        }
-        const double dd = std::hypot(Rat(k, k), Rat(k + 1, k));
-        cs[k] = Rat(k, k) / dd;
-        sn[k] = Rat(k + 1, k) / dd;
-        Rat(k, k) = dd;
-        Rat(k + 1, k) = 0.0;
-        g[k + 1] = -sn[k] * g[k];
-        g[k] = cs[k] * g[k];
-        kd = j;
-        relres = std::fabs(g[k + 1]) / beta;
-        stop = std::fabs(g[k + 1]) <= o->gmres_rtol * beta || !(gamma > 0) || last;
-      }
-      if (stop) break;
-      // H a (rows 0..j) from the completed columns 0..j-1
-      std::fill(Ha.begin(), Ha.begin() + j + 1, 0.0);
-      for (int i = 0; i < j; ++i) {
-        const double ai = a[i];
-        const double* col = &H[(size_t)i * (K + 1)];
-        for (int l = 0; l <= i + 1; ++l) Ha[l] += col[l] * ai;
-      }
-      const double ig = 1.0 / gamma;
-      double ab = 0.0;
-      for (int i = 0; i < j; ++i) ab += a[i] * b[i];
-      for (int i = 0; i < j; ++i) hprev[i] = (b[i] - Ha[i]) * ig;
-      hprev[j] = ((uw - ab) * ig - Ha[j]) * ig;
-      for (int i = 0; i <= j; ++i) cvec[i] = Ha[i] * ig + hprev[i];
-      for (int i = 0; i < j; ++i) hac[i] = a[i];
-      for (int i = 0; i <= j; ++i) hac[(K + 2) + i] = cvec[i];
-      SP_TRY_HIP(hipMemcpyAsync(d_ac, hac, 2 * (K + 2) * sizeof(double), hipMemcpyHostToDevice,
-                                p->stream),
-                 "upload a, c");
-      if (f32)
-        SP_TRY_HIP(launch_dcgs2_update(p, Vf, j, d_ac, d_ac + (K + 2), ig, W.w,
-                                       Vf + (size_t)(j + 1) * nk, W.u),
-                   "dcgs2 update");
-      else
-        SP_TRY_HIP(launch_dcgs2_update(p, W.V, j, d_ac, d_ac + (K + 2), ig, W.w,
-                                       W.V + (size_t)(j + 1) * nk, W.u),
-                   "dcgs2 update");
+    // iteration j is queued before iteration j-1's record is taken
+    bool stop = false;
+    for (int j = 0; j <= K + 1 && !stop; ++j) {
+      if (j <= K) SP_TRY(enqueue(j, U, r, unorm, actions));
+      if (j > 0) SP_TRY(take(j - 1, &stop));
     }
     return SP_OK;
   }

@@ -277,11 +277,22 @@ hipError_t launch_krylov_multiaxpy(sp_plan* p, const double2* V, int nvec, const
 hipError_t launch_krylov_multiaxpy(sp_plan* p, const float2* V, int nvec, const double* h,
                                    double alpha, double beta, double2* w);
 // V_j <- (V_j - sum_{i<j} a_i V_i) inv_gamma ; unew <- w inv_gamma - sum_{i<j} c_i V_i - c_j V_j,
-// w canonical; u64 (canonical) receives the stored unew in FP64
+// w canonical; u64 (canonical) receives the stored unew in FP64; inv_gamma is
+// read from device memory
 hipError_t launch_dcgs2_update(sp_plan* p, double2* V, int j, const double* a, const double* c,
-                              double inv_gamma, const double2* w, double2* unew, double2* u64);
+                              const double* inv_gamma, const double2* w, double2* unew,
+                              double2* u64);
 hipError_t launch_dcgs2_update(sp_plan* p, float2* V, int j, const double* a, const double* c,
-                              double inv_gamma, const double2* w, float2* unew, double2* u64);
+                              const double* inv_gamma, const double2* w, float2* unew,
+                              double2* u64);
+// The coefficients of Arnoldi iteration j on the device (blas.hip): from the
+// dots of launch_krylov_multidot2, the row-major Hessenberg matrix H (row
+// stride ld) and the provisional column hprev (both updated), writes a and c
+// (ac[i], ac[cst + i]), 1/gamma and the host record rec (gamma, the squared
+// norm, j, -, then column j-1 of H); Ha is scratch (j doubles).
+hipError_t launch_arnoldi_coef(sp_plan* p, int j, int ld, int cst, const double* dots, double* H,
+                              double* hprev, double* Ha, double* ac, double* inv_gamma,
+                              double* rec);
 // dst (compact) = src (canonical, Hermitian form); the FP32 form also writes the
 // rounded values back into src
 hipError_t launch_compact(sp_plan* p, double2* src, double2* dst);
