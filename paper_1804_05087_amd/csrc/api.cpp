@@ -228,6 +228,17 @@ sp_status jvp_lin(sp_plan* p, int op, const double2* du, double2* out) {
     return SP_OK;
   }
   const int n = (op == SP_OP_PHI) ? 1 : p->nsteps;
+  if (n == 1 && op != SP_OP_PHI && !p->advect) {
+    // (J_Phi du - du) / dt formed by the solve itself, in the Hermitian form
+    sp_status s = base_at(p, 0);
+    if (s) return s;
+    const bool fp32 = (p->precision == SP_MIXED);
+    s = nonlinear_to_nv(p, du, 1, fp32);
+    if (s) return s;
+    SP_TRY_HIP(launch_analysis_solve_res(p, du, p->d.inv_dt, p->d.inv_dt, -p->d.inv_dt, out, fp32),
+               "analysis+solve (residual form)");
+    return SP_OK;
+  }
   if (n == 1) {
     sp_status s = base_at(p, 0);
     if (s) return s;

@@ -289,7 +289,11 @@ __device__ inline void lds_order() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "w
 // th[j][n] = Tinv[n][j], so the lanes' loads are contiguous.
 // Two-wave blocks are held to at most 168 VGPRs (3 waves per SIMD), so that
 // every mode's block is resident at once at 48x65x48 (2 x 1128 waves).
-template <int E, int AN>
+// RES (with AN != 0): the residual form of a Jacobian action, out = oa S(g) +
+// ob x, written in the Hermitian form: the block of an m_z = 0 mode at m_x > 0
+// also writes the conjugate at -m_x (whose block has nothing to do), and the
+// (0,0) mode is real. x's entries n <= N are kept in LDS for it.
+template <int E, int AN, bool RES = false>
 __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
     __attribute__((amdgpu_waves_per_eu(AN != 0 ? 3 : 1)))
     k_stokes_solve(const double2* __restrict__ g, double2* __restrict__ out,
@@ -297,7 +301,8 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
                    int stride, int nx, int ny, int nzh, double alpha, double gamma, double re,
                    double inv_dt, double wu, double wl, int inhomogeneous,
                    const void* __restrict__ nv_raw, const void* __restrict__ tinv_raw,
-                   const double2* __restrict__ x, double xa) {
+                   const double2* __restrict__ x, double xa, double oa = 1.0, double ob = 0.0) {
+  static_assert(!RES || AN != 0, "the residual form reads x through the fused analysis");
   extern __shared__ unsigned char smem_raw[];
   const int N = ny - 1;
   const int n1 = ny;
@@ -319,6 +324,8 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
   // odd halves f_j - f_{N-j} ([3][jh8]), 64 bytes past the even ones so that
   // the two addresses an analysis load broadcasts fall in different banks
   cd* colO = colE + 3 * jh8 + 4;
+  // x at n <= N for the residual form ([3][n1]), past wave 1's partial sums
+  cd* Yx = reinterpret_cast<cd*>(reinterpret_cast<double*>(colO + 3 * jh8) + 6 * 64);
 
   // logical order: x mode fastest, so the modes whose product-field entries
   // share a cache line (consecutive m_x at one m_z) run on one XCD
@@ -336,6 +343,9 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
   const int l = tid & 15;
   const size_t cs = (size_t)nx * nzh * ny;  // component stride
   const size_t mo = ((size_t)i * nzh + j) * ny;
+  if constexpr (RES) {
+    if (j == 0 && i > nx / 2) return;  // written by its mirror's block (uniform per block)
+  }
   const bool nyq = (i == nx / 2) || (j == nzh - 1);
   if (nyq) {
     if (shadow) return;  // uniform per block: both waves leave
@@ -372,10 +382,12 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
     }
   } else {
     // u/dt part of the right-hand side: issued first, consumed after the analysis
+    // (the residual form keeps x up to n = N)
+    constexpr int kTop = RES ? 0 : 2;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       const int n = tid + 64 * t;
-      const int nc = n <= N - 2 ? n : N - 2;
+      const int nc = n <= N - kTop ? n : N - kTop;
       ga[t] = x[mo + nc];
       gb[t] = x[cs + mo + nc];
       gc[t] = x[2 * cs + mo + nc];
@@ -457,6 +469,14 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
     R* part = reinterpret_cast<R*>(colO + 3 * jh8);  // [6][64] partial sums of wave 1
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
+      if constexpr (RES) {
+        const int n = tid + 64 * t;
+        if (!shadow && n <= N) {
+          Yx[n] = cd(ga[t].x, ga[t].y);
+          Yx[n1 + n] = cd(gb[t].x, gb[t].y);
+          Yx[2 * n1 + n] = cd(gc[t].x, gc[t].y);
+        }
+      }
       if (t >= tmax) {
         ga[t] = gb[t] = gc[t] = make_double2(0.0, 0.0);
         continue;
@@ -621,9 +641,23 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
       wo = (upar * kz - U[n] * kx) * ik;
       vo = V[n];
     }
+    if constexpr (RES) {
+      uo = uo * oa + Yx[n] * ob;
+      vo = vo * oa + Yx[n1 + n] * ob;
+      wo = wo * oa + Yx[2 * n1 + n] * ob;
+      if (mean) uo.im = vo.im = wo.im = 0.0;
+    }
     out[mo + n] = make_double2(uo.re, uo.im);
     out[cs + mo + n] = make_double2(vo.re, vo.im);
     out[2 * cs + mo + n] = make_double2(wo.re, wo.im);
+    if constexpr (RES) {
+      if (j == 0 && i > 0) {  // 0 < m_x < nx/2: its mirror at -m_x
+        const size_t mm = (size_t)(nx - i) * nzh * ny;
+        out[mm + n] = make_double2(uo.re, -uo.im);
+        out[cs + mm + n] = make_double2(vo.re, -vo.im);
+        out[2 * cs + mm + n] = make_double2(wo.re, -wo.im);
+      }
+    }
   }
 }
 
@@ -860,12 +894,13 @@ hipError_t launch_fft_x_fwd_lds(sp_plan* p, const void* in, void* out, int nfiel
 // elements per lane of a 16-lane row covering one parity chain (ny <= 129)
 int solve_lanes_per_chain(int ny) { return ((ny - 1) / 2 + 1 + 15) / 16; }
 
-static size_t solve_lds_bytes(const sp_plan* p, bool fused) {
+static size_t solve_lds_bytes(const sp_plan* p, bool fused, bool res = false) {
   const Dims& d = p->d;
   const int jh8 = (((d.ny - 1) / 2 + 1) + 7) & ~7;
   return (size_t)p->mode_stride * sizeof(double) + 3 * (size_t)d.ny * sizeof(double) +
          10 * (size_t)d.ny * sizeof(cd) +
-         (fused ? (6 * (size_t)jh8 + 4) * sizeof(cd) + 6 * 64 * sizeof(double) : 0);
+         (fused ? (6 * (size_t)jh8 + 4) * sizeof(cd) + 6 * 64 * sizeof(double) : 0) +
+         (res ? 3 * (size_t)d.ny * sizeof(cd) : 0);
 }
 
 #define SP_SOLVE_DISPATCH(LAUNCH)                   \
@@ -903,12 +938,36 @@ hipError_t launch_analysis_solve(sp_plan* p, const double2* x, double xa, double
     hipLaunchKernelGGL((k_stokes_solve<EV, 2>), dim3(d.nx * d.nzh), dim3(128), sh, p->stream,      \
                        nullptr, out, p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh,      \
                        d.alpha, d.gamma, d.re, d.inv_dt, d.wall_upper, d.wall_lower,             \
-                       inhomogeneous, p->nv, p->f_tinv_th, x, xa);                                   \
+                       inhomogeneous, p->nv, p->f_tinv_th, x, xa, 1.0, 0.0);                         \
   else                                                                                            \
     hipLaunchKernelGGL((k_stokes_solve<EV, 1>), dim3(d.nx * d.nzh), dim3(128), sh, p->stream,      \
                        nullptr, out, p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny, d.nzh,      \
                        d.alpha, d.gamma, d.re, d.inv_dt, d.wall_upper, d.wall_lower,             \
-                       inhomogeneous, p->nv, p->d_tinv_th, x, xa)
+                       inhomogeneous, p->nv, p->d_tinv_th, x, xa, 1.0, 0.0)
+  SP_SOLVE_DISPATCH(SP_SOLVE_LAUNCH)
+#undef SP_SOLVE_LAUNCH
+  SP_PROF_END(p, KID_SOLVE);
+  return hipGetLastError();
+}
+
+// The residual form of the same: out = oa S(Tinv nv + xa x) + ob x in the
+// Hermitian form, homogeneous walls.
+hipError_t launch_analysis_solve_res(sp_plan* p, const double2* x, double xa, double oa, double ob,
+                                     double2* out, bool fp32) {
+  const Dims& d = p->d;
+  const size_t sh = solve_lds_bytes(p, true, true);
+  SP_PROF_BEGIN(p, KID_SOLVE);
+#define SP_SOLVE_LAUNCH(EV)                                                                       \
+  if (fp32)                                                                                       \
+    hipLaunchKernelGGL((k_stokes_solve<EV, 2, true>), dim3(d.nx * d.nzh), dim3(128), sh,           \
+                       p->stream, nullptr, out, p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny,  \
+                       d.nzh, d.alpha, d.gamma, d.re, d.inv_dt, d.wall_upper, d.wall_lower, 0,   \
+                       p->nv, p->f_tinv_th, x, xa, oa, ob);                                      \
+  else                                                                                            \
+    hipLaunchKernelGGL((k_stokes_solve<EV, 1, true>), dim3(d.nx * d.nzh), dim3(128), sh,           \
+                       p->stream, nullptr, out, p->d_mode, p->d_hw, p->mode_stride, d.nx, d.ny,  \
+                       d.nzh, d.alpha, d.gamma, d.re, d.inv_dt, d.wall_upper, d.wall_lower, 0,   \
+                       p->nv, p->d_tinv_th, x, xa, oa, ob)
   SP_SOLVE_DISPATCH(SP_SOLVE_LAUNCH)
 #undef SP_SOLVE_LAUNCH
   SP_PROF_END(p, KID_SOLVE);

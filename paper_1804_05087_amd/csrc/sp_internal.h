@@ -249,6 +249,10 @@ hipError_t launch_stokes_solve(sp_plan* p, const double2* g, double2* out, int i
 // y-valued product fields p->nv -> Chebyshev analysis + xa * x -> solve, one kernel
 hipError_t launch_analysis_solve(sp_plan* p, const double2* x, double xa, double2* out,
                                  int inhomogeneous, bool fp32);
+// the same with homogeneous walls in the residual form out = oa S + ob x, written
+// in the Hermitian form (m_z = 0 plane exactly Hermitian, Nyquist entries zero)
+hipError_t launch_analysis_solve_res(sp_plan* p, const double2* x, double xa, double oa, double ob,
+                                     double2* out, bool fp32);
 // out = a x + b y with the m_z = 0 plane made exactly Hermitian and Nyquist
 // entries zero (out must not alias x or y)
 hipError_t launch_axpby_herm(sp_plan* p, const double2* x, double a, const double2* y, double b,
