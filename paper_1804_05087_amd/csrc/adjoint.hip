@@ -324,21 +324,6 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// out <- a s out + b w, s = 1/2 on the (0,0) mode (Parseval -> packed-Euclidean
-// weights) and 1 elsewhere: the end of the VJP, with the residual's (. - w)/dt.
-__global__ void k_vjp_finish(double2* __restrict__ out, const double2* __restrict__ w, double a,
-                             double b, int nx, int nzh, int ny, size_t n) {
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
-       t += (size_t)gridDim.x * blockDim.x) {
-    const int j = (int)((t / ny) % nzh);
-    const int i = (int)((t / ((size_t)ny * nzh)) % nx);
-    const double s = (i == 0 && j == 0) ? 0.5 * a : a;
-    const double2 v = out[t];
-    const double2 x = (b != 0.0) ? w[t] : make_double2(0.0, 0.0);  // SP_OP_PHI: w unused
-    out[t] = make_double2(s * v.x + b * x.x, s * v.y + b * x.y);
-  }
-}
-
 // ----------------------------------- launchers -----------------------------------
 
 
@@ -417,22 +402,18 @@ sp_status vjp_lin(sp_plan* p, int op, const double2* w, double2* out) {
   }
   const bool fp32 = (p->precision == SP_MIXED);
   const Dims& d = p->d;
-  const size_t n = (size_t)3 * d.nx * d.nzh * d.ny;
   // the adjoint solve weighs the (0,0) mode of w twice (packed-Euclidean ->
-  // Parseval), the finishing pass halves it back
+  // Parseval); the transposed synthesis halves it back as it finishes each
+  // entry, and forms the residual's (. - w)/dt
   SP_TRY_HIP(launch_stokes_solve_adj(p, w, p->t2), "stokes_solve_adj");
   SP_TRY_HIP(launch_synth_tab(p, p->t2, 1, p->nv, fp32), "analysis^T");
   SP_TRY_HIP(launch_fft_x_inv_gen(p, p->nv, p->xp, 3, 1, fp32), "pad+ifft_x");
   SP_TRY_HIP(launch_adj_z(p, fp32), "adj_z");
   SP_TRY_HIP(launch_fft_x_fwd_gen(p, p->xp, p->yv, 6, fp32), "fft_x+truncate");
-  SP_TRY_HIP(launch_adj_synth(p, p->t2, d.inv_dt, out, fp32), "adj_synth");
   const bool res = (op == SP_OP_RESIDUAL);
-  SP_PROF_BEGIN(p, KID_MEAN_SCALE);
-  hipLaunchKernelGGL(k_vjp_finish, dim3(n < 4096 * 256 ? (n + 255) / 256 : 4096), dim3(256), 0,
-                     p->stream, out, w, res ? d.inv_dt : 1.0, res ? -d.inv_dt : 0.0, d.nx, d.nzh,
-                     d.ny, n);
-  SP_PROF_END(p, KID_MEAN_SCALE);
-  SP_TRY_HIP(hipGetLastError(), "vjp finish");
+  SP_TRY_HIP(launch_adj_synth(p, p->t2, d.inv_dt, res ? d.inv_dt : 1.0, res ? -d.inv_dt : 0.0,
+                              res ? w : nullptr, out, fp32),
+             "adj_synth");
   return SP_OK;
 }
 

@@ -25,7 +25,6 @@ enum KernelId {
   KID_ADJ_Z,
   KID_ADJ_X_FWD,
   KID_ADJ_SYNTH,
-  KID_MEAN_SCALE,
   KID_ADV,
   KID_COUNT
 };
@@ -35,7 +34,7 @@ inline const char* kernel_name(int id) {
       "k_synth_y",      "k_fft_x_inv",   "k_z_product", "k_fft_x_fwd", "k_analysis_rhs",
       "k_stokes_solve", "k_axpby",       "k_norm_partial", "k_pack",    "k_unpack",
       "k_multidot",     "k_multiaxpy",   "k_scale",     "k_stokes_solve_adj", "k_adj_z",
-      "k_adj_fft_x",    "k_adj_synth_y", "k_vjp_finish", "k_adv_apply"};
+      "k_adj_fft_x",    "k_adj_synth_y", "k_adv_apply"};
   return names[id];
 }
 

@@ -243,7 +243,10 @@ hipError_t launch_fft_x_fwd_gen(sp_plan* p, const void* in, void* out, int nfiel
 // adjoint kernels (adjoint.hip)
 hipError_t launch_stokes_solve_adj(sp_plan* p, const double2* w, double2* out);
 hipError_t launch_adj_z(sp_plan* p, bool fp32);
-hipError_t launch_adj_synth(sp_plan* p, const double2* x, double a, double2* out, bool fp32);
+// transposed synthesis of the six adjoint fields p->yv, finished as
+// out = fa s (. + a x) + fb w with s = 1/2 on the (0,0) mode (x, w may be NULL)
+hipError_t launch_adj_synth(sp_plan* p, const double2* x, double a, double fa, double fb,
+                            const double2* w, double2* out, bool fp32);
 hipError_t launch_analysis_rhs(sp_plan* p, const double2* x, double a, double2* g, bool fp32);
 hipError_t launch_stokes_solve(sp_plan* p, const double2* g, double2* out, int inhomogeneous);
 // y-valued product fields p->nv -> Chebyshev analysis + xa * x -> solve, one kernel

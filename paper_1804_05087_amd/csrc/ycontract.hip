@@ -7,7 +7,9 @@
 //   k_ysynth_mfma  coefficients -> y-values:  out_f[y][col] = sum_n M_f[y][n] u_c[n][col]
 //                  (synthesis with T and T.D; adjoint of the analysis with Tinv^T)
 //   k_ycoef_mfma   y-values -> coefficients:  out_c[col][n] = sum_t sum_j M_t[n][j] Y_t[j][col]
-//                  (analysis with Tinv; adjoint of the synthesis with T^T, (T.D)^T)
+//                  (analysis with Tinv)
+//   k_adjsynth_mfma  the same form for the adjoint of the synthesis (T^T, (T.D)^T
+//                  applied to curl-combined adjoint fields), operand staged in LDS
 //
 // A column is (kz, mx, re|im) with kz < nz/2, i.e. q = kz * nx + mx and
 // col = 2q + re|im, which is the contiguous order of the y-valued layout
@@ -190,7 +192,9 @@ struct AdjSynthLoad {
   const typename V2<R>::T* F;  // [6][ny][nzm][nx]
   int nx, ny, nq;
   R alpha, gamma;
-  __device__ R operator()(int term, int c, int j, int q, int kz, int mx, int ri) const {
+  // the combined value of term t, component c at y index j, mode q = (kz, mx)
+  // (zero in the x Nyquist column)
+  __device__ typename V2<R>::T value(int term, int c, int j, int q, int kz, int mx) const {
     using C = typename V2<R>::T;
     const size_t fs = (size_t)ny * nq;
     const size_t off = (size_t)j * nq + q;
@@ -210,8 +214,7 @@ struct AdjSynthLoad {
     } else {
       v = (c == 0) ? cscale(F[5 * fs + off], (R)-1) : F[3 * fs + off];
     }
-    const R r = ri ? v.y : v.x;
-    return (mx == nx / 2) ? (R)0 : r;
+    return (mx == nx / 2) ? mk((R)0, (R)0) : v;
   }
 };
 
@@ -219,10 +222,7 @@ struct AdjSynthLoad {
 // for kz < nz/2 (x may be NULL); the z Nyquist rows kz = nz/2 get xa * x (or
 // zero) from the blocks past the first nqb column blocks. nterm[c] terms for
 // component c = the logical z block index.
-// ALLT: each wave computes every row tile from the A fragments it loaded
-// (grid y = 1) instead of one tile per block; for loaders that gather several
-// fields per element this removes the re-loads across the row tiles.
-template <typename R, int KS, class Load, bool ALLT = false>
+template <typename R, int KS, class Load>
 __global__ void __launch_bounds__(256)
     k_ycoef_mfma(Load load, int nterm0, int nterm1, int nterm2, YMat<R> M0, YMat<R> M1,
                  const double2* __restrict__ x, double xa, double2* __restrict__ out, int nx,
@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(256)
   const int kza = qcl / nx;
   const int mxa = qcl - kza * nx;
   const int nt = ny >> 4;
-  const int ty = ALLT ? (nt > 0 ? nt : 1) : (int)gridDim.y;  // row tiles of the launch
+  const int ty = (int)gridDim.y;  // row tiles of the launch
   R a[2][KS];
 #pragma unroll
   for (int tm = 0; tm < 2; ++tm) {
@@ -267,7 +267,8 @@ __global__ void __launch_bounds__(256)
       a[tm][s] = v * (R)((qav && j < ny) ? 1 : 0);  // a mask, not a select (see k_ysynth_mfma)
     }
   }
-  for (int t = ALLT ? 0 : bk.y; t < (ALLT ? ty : bk.y + 1); ++t) {
+  {
+  const int t = bk.y;
   const bool tile = t < nt;
   const bool tail = (t == ty - 1) && (16 * nt < ny);
   if (tile) {
@@ -354,7 +355,121 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
-  }  // row tiles
+  }
+}
+
+// The transposed synthesis with its operand staged in LDS: a block owns 8 modes
+// (16 real columns) of output component c. Its threads gather the curl-combined
+// operand of those columns (AdjSynthLoad, every y index and term) once into
+// LDS; wave t then computes output row tile t from it, the last tile partial
+// (the tables' rows past ny are zero; those rows are not stored). So every
+// operand element is gathered once, as with all tiles in one wave, while the
+// tiles run on separate waves. Blocks past the ncb column blocks write the z
+// Nyquist rows. Every entry is finished as
+//   out = fa s (sum + xa x) + fb w,  s = 1/2 on the (0,0) mode and 1 elsewhere
+// (x and w may be NULL: zero), the end of the VJP.
+template <typename R, int KS>
+__global__ void __launch_bounds__(640)
+    k_adjsynth_mfma(AdjSynthLoad<R> ld, YMat<R> M0, YMat<R> M1, const double2* __restrict__ x,
+                    double xa, double fa, double fb, const double2* __restrict__ w,
+                    double2* __restrict__ out, int nx, int ny, int nzh, int nzm, int ncb) {
+  using MF = Mfma<R>;
+  using C = typename V2<R>::T;
+  __shared__ R ys[2][4 * KS][16];
+  const Blk3 bk = ycontract_block();
+  const int c = bk.z;
+  if (bk.x >= ncb) {  // block-uniform
+    const int e = (bk.x - ncb) * (int)blockDim.x + (int)threadIdx.x;
+    if (e < nx * ny) {
+      const int mx = e / ny;
+      const int n = e - mx * ny;
+      const size_t o = (((size_t)c * nx + mx) * nzh + (nzh - 1)) * ny + n;
+      double2 v = make_double2(0.0, 0.0);
+      if (x != nullptr) v = make_double2(xa * x[o].x, xa * x[o].y);
+      v = make_double2(fa * v.x, fa * v.y);
+      if (w != nullptr) v = make_double2(v.x + fb * w[o].x, v.y + fb * w[o].y);
+      out[o] = v;
+    }
+    return;
+  }
+  const int nq = nzm * nx;
+  const int q0 = bk.x * 8;
+  const int nterm = (c == 1) ? 1 : 2;
+  for (int e = threadIdx.x; e < nterm * 4 * KS * 8; e += blockDim.x) {
+    const int m = e & 7;
+    const int rest = e >> 3;
+    const int j = rest % (4 * KS);
+    const int tm = rest / (4 * KS);
+    const int q = q0 + m;
+    C v = mk((R)0, (R)0);
+    if (j < ny && q < nq) {
+      const int kz = q / nx;
+      v = ld.value(tm, c, j, q, kz, q - kz * nx);
+    }
+    ys[tm][j][2 * m] = v.x;
+    ys[tm][j][2 * m + 1] = v.y;
+  }
+  __syncthreads();
+  const int t = threadIdx.x >> 6;  // row tile (blockDim = 64 * row tiles)
+  const int lane = threadIdx.x & 63;
+  const int kq = lane >> 4;
+  typename MF::acc_t acc = {0, 0, 0, 0};
+  for (int tm = 0; tm < nterm; ++tm) {
+    const R* fb = (tm ? M1.frag : M0.frag) + (size_t)t * KS * 64 + lane;
+    R bm[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) bm[s] = fb[s * 64];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) acc = MF::mma(ys[tm][4 * s + kq][lane & 15], bm[s], acc);
+  }
+  // D row r is data column 2 q0 + r (see k_ycoef_mfma)
+  R pre[2], pim[2];
+  int qd2[2];
+  if constexpr (MF::kRegMajor) {
+    R other[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) other[i] = __shfl_xor(acc[i], 16, 64);
+    const int e = kq & 1;
+#pragma unroll
+    for (int pr = 0; pr < 2; ++pr) {
+      const int i = 2 * e + pr;
+      pre[pr] = e ? other[i] : acc[i];
+      pim[pr] = e ? acc[i] : other[i];
+      qd2[pr] = q0 + (kq >> 1) + 2 * i;
+    }
+  } else {
+#pragma unroll
+    for (int pr = 0; pr < 2; ++pr) {
+      pre[pr] = acc[2 * pr];
+      pim[pr] = acc[2 * pr + 1];
+      qd2[pr] = q0 + 2 * kq + pr;
+    }
+  }
+  const int n = 16 * t + (lane & 15);
+#pragma unroll
+  for (int pr = 0; pr < 2; ++pr) {
+    const int qd = qd2[pr];
+    if (qd < nq && n < ny) {
+      const int kz = qd / nx;
+      const int mx = qd - kz * nx;
+      const size_t o = (((size_t)c * nx + mx) * nzh + kz) * ny + n;
+      double re = (double)pre[pr], im = (double)pim[pr];
+      if (x != nullptr) {
+        const double2 xv = x[o];
+        re += xa * xv.x;
+        im += xa * xv.y;
+      }
+      const double sa = (qd == 0) ? 0.5 * fa : fa;  // qd = 0: the (0,0) mode
+      re *= sa;
+      im *= sa;
+      if (w != nullptr) {
+        const double2 wv = w[o];
+        re += fb * wv.x;
+        im += fb * wv.y;
+      }
+      out[o] = make_double2(re, im);
+    }
+  }
 }
 
 // ----------------------------------- launchers -----------------------------------
@@ -482,32 +597,30 @@ hipError_t launch_analysis_rhs(sp_plan* p, const double2* x, double a, double2* 
   return hipGetLastError();
 }
 
-hipError_t launch_adj_synth(sp_plan* p, const double2* x, double a, double2* out, bool fp32) {
+hipError_t launch_adj_synth(sp_plan* p, const double2* x, double a, double fa, double fb,
+                            const double2* w, double2* out, bool fp32) {
   const Dims& d = p->d;
   const int nq = d.nzm * d.nx;
-  int nqb;
-  const dim3 grid = ycoef_grid(d, &nqb);
-  // FP64: all row tiles per wave (grid y = 1), since the loader gathers up to
-  // three fields per element (measured: VJP 10.2 -> 11.5 k/s at 48x65x48);
-  // FP32 keeps one tile per block (its loads are cheap, its waves more useful)
-  dim3 grid1 = grid;
-  grid1.y = 1;
+  const int ntile = (d.ny + 15) / 16;
+  const int nthr = 64 * ntile;
+  const int ncb = (nq + 7) / 8;
+  const dim3 grid(ncb + (d.nx * d.ny + nthr - 1) / nthr, 1, 3);
   SP_PROF_BEGIN(p, KID_ADJ_SYNTH);
   if (fp32) {
     const AdjSynthLoad<float> ld{(const float2*)p->yv, d.nx, d.ny, nq, (float)d.alpha,
                                  (float)d.gamma};
     const YMat<float> m0 = ymat<float>(p, YM_T_T), m1 = ymat<float>(p, YM_TD_T);
 #define L32(KS)                                                                                \
-  hipLaunchKernelGGL((k_ycoef_mfma<float, KS, AdjSynthLoad<float>>), grid, dim3(256), 0,        \
-                     p->stream, ld, 2, 1, 2, m0, m1, x, a, out, d.nx, d.ny, d.nzh, d.nzm, nqb)
+  hipLaunchKernelGGL((k_adjsynth_mfma<float, KS>), grid, dim3(nthr), 0, p->stream, ld, m0, m1,  \
+                     x, a, fa, fb, w, out, d.nx, d.ny, d.nzh, d.nzm, ncb)
     SP_KS_DISPATCH(d.ny, L32);
 #undef L32
   } else {
     const AdjSynthLoad<double> ld{(const double2*)p->yv, d.nx, d.ny, nq, d.alpha, d.gamma};
     const YMat<double> m0 = ymat<double>(p, YM_T_T), m1 = ymat<double>(p, YM_TD_T);
 #define L64(KS)                                                                                \
-  hipLaunchKernelGGL((k_ycoef_mfma<double, KS, AdjSynthLoad<double>, true>), grid1, dim3(256), 0, \
-                     p->stream, ld, 2, 1, 2, m0, m1, x, a, out, d.nx, d.ny, d.nzh, d.nzm, nqb)
+  hipLaunchKernelGGL((k_adjsynth_mfma<double, KS>), grid, dim3(nthr), 0, p->stream, ld, m0, m1, \
+                     x, a, fa, fb, w, out, d.nx, d.ny, d.nzh, d.nzm, ncb)
     SP_KS_DISPATCH(d.ny, L64);
 #undef L64
   }
