@@ -16,19 +16,23 @@ def _fields(dims, count, seed0):
                         for i in range(count)]).contiguous()
 
 
-@pytest.mark.parametrize("dims,streams,precision", [((16, 17, 16), 3, 0), ((12, 21, 24), 8, 0),
-                                                    ((16, 17, 16), 4, SP_MIXED)])
-def test_batch_equals_single_calls(dims, streams, precision):
+@pytest.mark.parametrize("dims,streams,precision,count", [
+    ((16, 17, 16), 3, 0, 7), ((12, 21, 24), 8, 0, 7), ((16, 17, 16), 4, SP_MIXED, 7),
+    ((16, 17, 16), 3, 0, 37),        # more members than streams, several rounds
+    ((48, 65, 48), 2, 0, 18),        # the full grid
+    ((48, 65, 48), 3, SP_MIXED, 17),
+    ((18, 17, 16), 3, 0, 7)])        # x length 27: the LDS transform path
+def test_batch_equals_single_calls(dims, streams, precision, count):
     import torch
     from paper_1804_05087_amd import Plan
-    say("batch", dims, streams, precision)
+    say("batch", dims, streams, precision, count)
     P = Plan(*dims, *BOX, 400.0, 10.0, precision=precision)
-    u = _fields(dims, 7, 10)
+    u = _fields(dims, count, 10)
     out = P.befe_step_batch(u, streams=streams)
     for i in range(u.shape[0]):
         assert torch.equal(out[i], P.befe_step(u[i].contiguous())), i
     P.linearize(u[0].contiguous())
-    du = _fields(dims, 5, 30)
+    du = _fields(dims, min(count, 19), 30)
     for op in (SP_OP_PHI, SP_OP_RESIDUAL):
         jb = P.jvp_lin_batch(du, op, streams=streams)
         for i in range(du.shape[0]):
