@@ -897,6 +897,10 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-newton", action="store_true")
+    ap.add_argument("--no-rates", action="store_true",
+                    help="skip the multi-stream, batched, mixed, JVP and VJP rates: the FP64 "
+                         "Phi loop and the stage timing only (a kernel trace of this run "
+                         "averages the Phi kernels over back-to-back launches on one stream)")
     ap.add_argument("--newton-krylov", type=int, default=600,
                     help="Krylov cap per Newton step (from the continued equilibrium at "
                          "48x65x48, Re 1000: caps of 200-350 stall before 1e-10; 400 is "
@@ -1018,65 +1022,66 @@ def main():
     evals = args.steps / gpu_s
     log("phi fp64", evals, "evals/s", ms_per_step, "ms/eval; wall", wall_s)
     res = {}
-    steps2 = max(10, args.steps // 2)
-    # independent evaluations on 4 plans / 4 streams (default priority): the
-    # throughput available to callers with several fields (seeds, sweeps,
-    # Jacobian columns); not the headline, which is one field at a time
-    streams = [torch.cuda.Stream(device=dev) for _ in range(4)]
-    plans4, outs4 = [], []
-    for st in streams:
-        with torch.cuda.stream(st):
-            plans4.append(Plan(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], w["re"], w["dt"],
-                               device=dev))
-            outs4.append(plans4[-1].empty())
-    torch.cuda.synchronize()
+    if not args.no_rates:
+        steps2 = max(10, args.steps // 2)
+        # independent evaluations on 4 plans / 4 streams (default priority): the
+        # throughput available to callers with several fields (seeds, sweeps,
+        # Jacobian columns); not the headline, which is one field at a time
+        streams = [torch.cuda.Stream(device=dev) for _ in range(4)]
+        plans4, outs4 = [], []
+        for st in streams:
+            with torch.cuda.stream(st):
+                plans4.append(Plan(w["nx"], w["ny"], w["nz"], w["lx"], w["lz"], w["re"], w["dt"],
+                                   device=dev))
+                outs4.append(plans4[-1].empty())
+        torch.cuda.synchronize()
 
-    def four():
-        for k in range(4):
-            with torch.cuda.stream(streams[k]):
-                plans4[k].befe_step(u, outs4[k])
+        def four():
+            for k in range(4):
+                with torch.cuda.stream(streams[k]):
+                    plans4[k].befe_step(u, outs4[k])
 
-    four()
-    torch.cuda.synchronize()
-    t4 = time.perf_counter()
-    for _ in range(steps2):
         four()
-    torch.cuda.synchronize()
-    res["phi_fp64_4streams_evals_per_s"] = 4 * steps2 / (time.perf_counter() - t4)
-    del plans4, outs4
-    # the same from one plan: sp_befe_step_batch, 64 fields per call on 3 member
-    # streams (with the plan's own stream, the 4 hardware queues of the process)
-    ub = u.unsqueeze(0).expand(64, *u.shape).contiguous()
-    ob = torch.empty_like(ub)
-    P.befe_step_batch(ub, ob, streams=3)
-    torch.cuda.synchronize()
-    nb = max(1, steps2 // 64)
-    tb = time.perf_counter()
-    for _ in range(nb):
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        for _ in range(steps2):
+            four()
+        torch.cuda.synchronize()
+        res["phi_fp64_4streams_evals_per_s"] = 4 * steps2 / (time.perf_counter() - t4)
+        del plans4, outs4
+        # the same from one plan: sp_befe_step_batch, 64 fields per call on 3 member
+        # streams (with the plan's own stream, the 4 hardware queues of the process)
+        ub = u.unsqueeze(0).expand(64, *u.shape).contiguous()
+        ob = torch.empty_like(ub)
         P.befe_step_batch(ub, ob, streams=3)
-    torch.cuda.synchronize()
-    res["phi_fp64_batch64_3streams_evals_per_s"] = 64 * nb / (time.perf_counter() - tb)
-    del ub, ob
-    P.set_precision(SP_MIXED)
-    s, _ = time_loop(torch, lambda: P.befe_step(u, out), steps2, args.warmup)
-    res["phi_mixed_evals_per_s"] = steps2 / s
-    P.linearize(u)
-    s, _ = time_loop(torch, lambda: P.jvp_lin(du, SP_OP_RESIDUAL, out), steps2, args.warmup)
-    res["jvp_mixed_evals_per_s"] = steps2 / s
-    P.set_precision(SP_FP64)
-    P.linearize(u)
-    s, _ = time_loop(torch, lambda: P.jvp_lin(du, SP_OP_RESIDUAL, out), steps2, args.warmup)
-    res["jvp_fp64_evals_per_s"] = steps2 / s
-    # the vector-Jacobian product (the transposed pipeline), FP64 and mixed
-    s, _ = time_loop(torch, lambda: P.vjp_lin(du, SP_OP_RESIDUAL, out), steps2, args.warmup)
-    res["vjp_fp64_evals_per_s"] = steps2 / s
-    P.set_precision(SP_MIXED)
-    P.linearize(u)
-    s, _ = time_loop(torch, lambda: P.vjp_lin(du, SP_OP_RESIDUAL, out), steps2, args.warmup)
-    res["vjp_mixed_evals_per_s"] = steps2 / s
-    P.set_precision(SP_FP64)
-    P.linearize(u)
-    log("rates", res)
+        torch.cuda.synchronize()
+        nb = max(1, steps2 // 64)
+        tb = time.perf_counter()
+        for _ in range(nb):
+            P.befe_step_batch(ub, ob, streams=3)
+        torch.cuda.synchronize()
+        res["phi_fp64_batch64_3streams_evals_per_s"] = 64 * nb / (time.perf_counter() - tb)
+        del ub, ob
+        P.set_precision(SP_MIXED)
+        s, _ = time_loop(torch, lambda: P.befe_step(u, out), steps2, args.warmup)
+        res["phi_mixed_evals_per_s"] = steps2 / s
+        P.linearize(u)
+        s, _ = time_loop(torch, lambda: P.jvp_lin(du, SP_OP_RESIDUAL, out), steps2, args.warmup)
+        res["jvp_mixed_evals_per_s"] = steps2 / s
+        P.set_precision(SP_FP64)
+        P.linearize(u)
+        s, _ = time_loop(torch, lambda: P.jvp_lin(du, SP_OP_RESIDUAL, out), steps2, args.warmup)
+        res["jvp_fp64_evals_per_s"] = steps2 / s
+        # the vector-Jacobian product (the transposed pipeline), FP64 and mixed
+        s, _ = time_loop(torch, lambda: P.vjp_lin(du, SP_OP_RESIDUAL, out), steps2, args.warmup)
+        res["vjp_fp64_evals_per_s"] = steps2 / s
+        P.set_precision(SP_MIXED)
+        P.linearize(u)
+        s, _ = time_loop(torch, lambda: P.vjp_lin(du, SP_OP_RESIDUAL, out), steps2, args.warmup)
+        res["vjp_mixed_evals_per_s"] = steps2 / s
+        P.set_precision(SP_FP64)
+        P.linearize(u)
+        log("rates", res)
 
     # ---- per-kernel durations of the FP64 Phi step: each stage kernel launched
     # back to back between two HIP events on the plan's stream (sp_time_stage)
