@@ -195,7 +195,10 @@ __global__ void __launch_bounds__(64)
     if (vrow) SP_ROW_PAR(po, Pb[n] = Pb[n] + Tm[n];)
     __syncthreads();
     // P = Pois(div F), div F = i k F_par + D F_v
-    wsweep_T<E>(vrow ? pois : helm, hw, N, vrow ? po : pv, vrow ? Pb : Ub, vrow ? Db : Dm,
+    // the rows' operator chosen field by field (a per-lane choice between two
+    // records would be made through scratch memory)
+    const SweepRec pois_or_helm(rec + (vrow ? L.pois() : L.helm()), n1, vrow ? k2 : lam);
+    wsweep_T<E>(pois_or_helm, hw, N, vrow ? po : pv, vrow ? Pb : Ub, vrow ? Db : Dm,
                 vrow ? W : W2, l);
     if (vrow) SP_ROW_PAR(po, Fpb[n] = mul_i(-Db[n]) * k;)
     __syncthreads();
@@ -204,7 +207,11 @@ __global__ void __launch_bounds__(64)
     if (vrow) SP_ROW_PAR(pv, Fvb[n] = Fvb[n] + Tm[n];)
   }
   __syncthreads();
-  for (int n = tid; n < n1; n += 64) {
+  // n1 <= 32 E coefficients: a fixed, unrolled pass count
+#pragma unroll
+  for (int q = 0; q < (32 * E + 63) / 64; ++q) {
+    const int n = tid + 64 * q;
+    if (n >= n1) break;
     cd gu, gv, gw;
     if (n <= N - 2) {
       if (mean) {
