@@ -95,7 +95,11 @@ __global__ void __launch_bounds__(256)
   constexpr int NI = Op::NI;
   constexpr int NF = Op::NF;
   constexpr int S1 = P1 + 1;  // padded row of the exchange buffers
-  constexpr int E1 = (XL * NI * P2 * S1 > XL * NF * P) ? XL * NI * P2 * S1 : XL * NF * P;
+  // line slots per x-line in the exchange block: operators with a base state
+  // write their products in place over their input lines, so they need
+  // max(NI, NF) slots
+  constexpr int LS = (Op::kBase && NF > NI) ? NF : NI;
+  constexpr int E1 = (XL * LS * P2 * S1 > XL * NF * P) ? XL * LS * P2 * S1 : XL * NF * P;
   __shared__ C twl[P];
   __shared__ C ex1[E1];                          // inverse exchange, then forward output
   __shared__ C ex2[NF > 0 ? XL * NF * P2 * S1 : 1];  // forward exchange
@@ -137,7 +141,7 @@ __global__ void __launch_bounds__(256)
         v[n1] = mk(ar - bi, ai + br);
       }
       dft_reg<P1, P, C, R>(v, (R)1, twl);
-      C* e = ex1 + (li * P2 + n2) * S1;
+      C* e = ex1 + ((xl * LS + i) * P2 + n2) * S1;
 #pragma unroll
       for (int k1 = 0; k1 < P1; ++k1)
         e[k1] = (k1 == 0 || n2 == 0) ? v[k1] : cmul(v[k1], wpow<P, P, C, R>(n2 * k1, (R)1, twl));
@@ -152,8 +156,9 @@ __global__ void __launch_bounds__(256)
     const int k1 = task % P1;
     const int li = task / P1;  // xl * NI + i
     const int xl = li / NI;
+    const int il = li - xl * NI;
     if (xl < nxl) {
-      C* e = ex1 + (li * P2) * S1 + k1;
+      C* e = ex1 + ((xl * LS + il) * P2) * S1 + k1;
       C ph[P2];
 #pragma unroll
       for (int n2 = 0; n2 < P2; ++n2) ph[n2] = e[n2 * S1];
@@ -173,24 +178,60 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
-  if constexpr (NF > 0) {
+  if constexpr (NF > 0 && Op::kBase) {
+    __syncthreads();
+    // the pointwise stage for operators with a base state: task (xl, k1, k2), one
+    // physical point z = k1 + P1 k2 each, so that every wave reads base values
+    // (consecutive tasks read consecutive z); the products go in place over the
+    // point's input slots (slot f < NF of the x-line's LS slots)
+    for (int task = tid; task < XL * P1 * P2; task += 256) {
+      const int k1 = task % P1;
+      const int k2 = (task / P1) % P2;
+      const int xl = task / (P1 * P2);
+      if (xl < nxl) {
+        C pin[NI], pout[NF];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) pin[i] = ex1[((xl * LS + i) * P2 + k2) * S1 + k1];
+        const Op op{};
+        op(pin, pout, base, bs, ((size_t)y * px + x0 + xl) * P + k1 + (size_t)P1 * k2);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) ex1[((xl * LS + f) * P2 + k2) * S1 + k1] = pout[f];
+      }
+    }
+    __syncthreads();
+    // step 1 of the forward transforms: task (xl, k1, forward line f), f slowest
+    for (int task = tid; task < XL * P1 * NF; task += 256) {
+      const int f = task / (XL * P1);
+      const int k1 = task % P1;
+      const int xl = (task / P1) % XL;
+      if (xl < nxl) {
+        C fw[P2];
+#pragma unroll
+        for (int k2 = 0; k2 < P2; ++k2) fw[k2] = ex1[((xl * LS + f) * P2 + k2) * S1 + k1];
+        dft_reg<P2, P, C, R>(fw, (R)-1, twl);
+        C* e = ex2 + ((xl * NF + f) * P2) * S1 + k1;
+#pragma unroll
+        for (int m2 = 0; m2 < P2; ++m2)
+          e[m2 * S1] = (m2 == 0 || k1 == 0) ? fw[m2]
+                                            : cmul(fw[m2], wpow<P, P, C, R>(k1 * m2, (R)-1, twl));
+      }
+    }
+  }
+  if constexpr (NF > 0 && !Op::kBase) {
     __syncthreads();
     // the pointwise stage and step 1 of the forward transforms: task (xl, k1,
-    // forward line f) for operators that read no base state, else (xl, k1)
-    // with every f in one task, so the base state is read once per point
-    constexpr int NFT = Op::kBase ? 1 : NF;  // forward lines per task split
-    for (int task = tid; task < XL * P1 * NFT; task += 256) {
-      // f slowest: with XL * P1 a multiple of 64 it is uniform over a wave
+    // forward line f), f slowest (with XL * P1 a multiple of 64 it is uniform
+    // over a wave)
+    for (int task = tid; task < XL * P1 * NF; task += 256) {
       const int fsel = task / (XL * P1);
       const int k1 = task % P1;
       const int xl = (task / P1) % XL;
       if (xl < nxl) {
         const size_t bo0 = ((size_t)y * px + x0 + xl) * P + k1;
-        // forward lines F0 .. F0 + NFL - 1 (compile-time, so pout stays in registers)
+        // forward line F0 (compile-time, so pout stays in registers)
         auto run = [&](auto f0) {
           constexpr int F0 = decltype(f0)::value;
-          constexpr int NFL = Op::kBase ? NF : 1;
-          C fw[NFL][P2];
+          C fw[P2];
           const Op op{};
 #pragma unroll
           for (int k2 = 0; k2 < P2; ++k2) {
@@ -198,30 +239,21 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int i = 0; i < NI; ++i) pin[i] = ex1[((xl * NI + i) * P2 + k2) * S1 + k1];
             op(pin, pout, base, bs, bo0 + (size_t)P1 * k2);
-#pragma unroll
-            for (int q = 0; q < NFL; ++q) fw[q][k2] = pout[F0 + q];
+            fw[k2] = pout[F0];
           }
+          dft_reg<P2, P, C, R>(fw, (R)-1, twl);
+          C* e = ex2 + ((xl * NF + F0) * P2) * S1 + k1;
 #pragma unroll
-          for (int q = 0; q < NFL; ++q) {
-            dft_reg<P2, P, C, R>(fw[q], (R)-1, twl);
-            C* e = ex2 + ((xl * NF + F0 + q) * P2) * S1 + k1;
-#pragma unroll
-            for (int m2 = 0; m2 < P2; ++m2)
-              e[m2 * S1] = (m2 == 0 || k1 == 0)
-                               ? fw[q][m2]
-                               : cmul(fw[q][m2], wpow<P, P, C, R>(k1 * m2, (R)-1, twl));
-          }
+          for (int m2 = 0; m2 < P2; ++m2)
+            e[m2 * S1] = (m2 == 0 || k1 == 0) ? fw[m2]
+                                              : cmul(fw[m2], wpow<P, P, C, R>(k1 * m2, (R)-1, twl));
         };
-        if constexpr (Op::kBase) {
-          run(std::integral_constant<int, 0>{});
-        } else {
-          if (fsel == 0) run(std::integral_constant<int, 0>{});
-          if constexpr (NF > 1) {
-            if (fsel == 1) run(std::integral_constant<int, 1>{});
-          }
-          if constexpr (NF > 2) {
-            if (fsel == 2) run(std::integral_constant<int, 2>{});
-          }
+        if (fsel == 0) run(std::integral_constant<int, 0>{});
+        if constexpr (NF > 1) {
+          if (fsel == 1) run(std::integral_constant<int, 1>{});
+        }
+        if constexpr (NF > 2) {
+          if (fsel == 2) run(std::integral_constant<int, 2>{});
         }
       }
     }
