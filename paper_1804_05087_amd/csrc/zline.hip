@@ -95,10 +95,12 @@ __global__ void __launch_bounds__(256)
   constexpr int NI = Op::NI;
   constexpr int NF = Op::NF;
   constexpr int S1 = P1 + 1;  // padded row of the exchange buffers
-  // line slots per x-line in the exchange block: operators with a base state
-  // write their products in place over their input lines, so they need
-  // max(NI, NF) slots
-  constexpr int LS = (Op::kBase && NF > NI) ? NF : NI;
+  // operators with a base state and no more output than input lines take the
+  // pointwise stage one physical point per task, writing the products in place
+  // over their input slots (the others keep one task per (line, k1), which
+  // for base-state operators reads the base once per point)
+  constexpr bool kSplit = Op::kBase && NF > 0 && NF <= NI;
+  constexpr int LS = NI;  // line slots per x-line in the exchange block
   constexpr int E1 = (XL * LS * P2 * S1 > XL * NF * P) ? XL * LS * P2 * S1 : XL * NF * P;
   __shared__ C twl[P];
   __shared__ C ex1[E1];                          // inverse exchange, then forward output
@@ -178,9 +180,9 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
-  if constexpr (NF > 0 && Op::kBase) {
+  if constexpr (kSplit) {
     __syncthreads();
-    // the pointwise stage for operators with a base state: task (xl, k1, k2), one
+    // the pointwise stage, split: task (xl, k1, k2), one
     // physical point z = k1 + P1 k2 each, so that every wave reads base values
     // (consecutive tasks read consecutive z); the products go in place over the
     // point's input slots (slot f < NF of the x-line's LS slots)
@@ -217,21 +219,24 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
-  if constexpr (NF > 0 && !Op::kBase) {
+  if constexpr (NF > 0 && !kSplit) {
     __syncthreads();
     // the pointwise stage and step 1 of the forward transforms: task (xl, k1,
-    // forward line f), f slowest (with XL * P1 a multiple of 64 it is uniform
-    // over a wave)
-    for (int task = tid; task < XL * P1 * NF; task += 256) {
+    // forward line f) for operators that read no base state, f slowest (with
+    // XL * P1 a multiple of 64 it is uniform over a wave), else (xl, k1) with
+    // every f in one task, so the base state is read once per point
+    constexpr int NFT = Op::kBase ? 1 : NF;  // forward lines per task split
+    for (int task = tid; task < XL * P1 * NFT; task += 256) {
       const int fsel = task / (XL * P1);
       const int k1 = task % P1;
       const int xl = (task / P1) % XL;
       if (xl < nxl) {
         const size_t bo0 = ((size_t)y * px + x0 + xl) * P + k1;
-        // forward line F0 (compile-time, so pout stays in registers)
+        // forward lines F0 .. F0 + NFL - 1 (compile-time, so pout stays in registers)
         auto run = [&](auto f0) {
           constexpr int F0 = decltype(f0)::value;
-          C fw[P2];
+          constexpr int NFL = Op::kBase ? NF : 1;
+          C fw[NFL][P2];
           const Op op{};
 #pragma unroll
           for (int k2 = 0; k2 < P2; ++k2) {
@@ -239,21 +244,30 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int i = 0; i < NI; ++i) pin[i] = ex1[((xl * NI + i) * P2 + k2) * S1 + k1];
             op(pin, pout, base, bs, bo0 + (size_t)P1 * k2);
-            fw[k2] = pout[F0];
-          }
-          dft_reg<P2, P, C, R>(fw, (R)-1, twl);
-          C* e = ex2 + ((xl * NF + F0) * P2) * S1 + k1;
 #pragma unroll
-          for (int m2 = 0; m2 < P2; ++m2)
-            e[m2 * S1] = (m2 == 0 || k1 == 0) ? fw[m2]
-                                              : cmul(fw[m2], wpow<P, P, C, R>(k1 * m2, (R)-1, twl));
+            for (int q = 0; q < NFL; ++q) fw[q][k2] = pout[F0 + q];
+          }
+#pragma unroll
+          for (int q = 0; q < NFL; ++q) {
+            dft_reg<P2, P, C, R>(fw[q], (R)-1, twl);
+            C* e = ex2 + ((xl * NF + F0 + q) * P2) * S1 + k1;
+#pragma unroll
+            for (int m2 = 0; m2 < P2; ++m2)
+              e[m2 * S1] = (m2 == 0 || k1 == 0)
+                               ? fw[q][m2]
+                               : cmul(fw[q][m2], wpow<P, P, C, R>(k1 * m2, (R)-1, twl));
+          }
         };
-        if (fsel == 0) run(std::integral_constant<int, 0>{});
-        if constexpr (NF > 1) {
-          if (fsel == 1) run(std::integral_constant<int, 1>{});
-        }
-        if constexpr (NF > 2) {
-          if (fsel == 2) run(std::integral_constant<int, 2>{});
+        if constexpr (Op::kBase) {
+          run(std::integral_constant<int, 0>{});
+        } else {
+          if (fsel == 0) run(std::integral_constant<int, 0>{});
+          if constexpr (NF > 1) {
+            if (fsel == 1) run(std::integral_constant<int, 1>{});
+          }
+          if constexpr (NF > 2) {
+            if (fsel == 2) run(std::integral_constant<int, 2>{});
+          }
         }
       }
     }
