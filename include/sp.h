@@ -277,7 +277,7 @@ typedef struct {
 /* total_actions counts the residual evaluations and the Jacobian actions
  * performed. The device runs one Arnoldi iteration ahead of the host's stop
  * test, so a GMRES solve that stops before max_krylov performs two actions
- * beyond its last basis direction (one at max_krylov). */
+ * beyond its last basis direction; one that runs to max_krylov performs none. */
 typedef struct {
   int32_t converged, newton_iters, total_krylov, total_actions;
   double seconds;
