@@ -17,6 +17,8 @@
 // implicit solve is FP64 only.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <type_traits>
 
 #include "device_common.h"
@@ -320,12 +322,19 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
   cd* Dm = U + n1;  // output of the idle rows
   const int jh = (ny - 1) / 2 + 1;  // folded column length (AN != 0)
   const int jh8 = (jh + 7) & ~7;    // padded with zeros to whole groups of 8
-  cd* colE = Dm + n1;               // [3][jh8] even halves f_j + f_{N-j}
+  // The folded columns of the analysis share the space of the ten arrays
+  // above: both waves read them only before the analysis' last barrier, and
+  // the arrays are first written after it.
+  cd* colE = Fpar;  // [3][jh8] even halves f_j + f_{N-j}
   // odd halves f_j - f_{N-j} ([3][jh8]), 64 bytes past the even ones so that
   // the two addresses an analysis load broadcasts fall in different banks
   cd* colO = colE + 3 * jh8 + 4;
+  const int shared_len = (10 * n1 > 6 * jh8 + 4) ? 10 * n1 : 6 * jh8 + 4;
+  // [6][64] partial sums of wave 1 (which may still read them after the
+  // analysis' last barrier, so they have space of their own)
+  double* part_raw = reinterpret_cast<double*>(Fpar + shared_len);
   // x at n <= N for the residual form ([3][n1]), past wave 1's partial sums
-  cd* Yx = reinterpret_cast<cd*>(reinterpret_cast<double*>(colO + 3 * jh8) + 6 * 64);
+  cd* Yx = reinterpret_cast<cd*>(part_raw + 6 * 64);
 
   // logical order: x mode fastest, so the modes whose product-field entries
   // share a cache line (consecutive m_x at one m_z) run on one XCD
@@ -466,7 +475,7 @@ __global__ void __launch_bounds__(AN != 0 ? 128 : 64)
     const int gsplit = (NW == 2) ? ng / 2 : ng;
     const int gbeg = shadow ? gsplit : 0;
     const int gend = shadow ? ng : gsplit;
-    R* part = reinterpret_cast<R*>(colO + 3 * jh8);  // [6][64] partial sums of wave 1
+    R* part = reinterpret_cast<R*>(part_raw);  // [6][64] partial sums of wave 1
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       if constexpr (RES) {
@@ -896,10 +905,11 @@ int solve_lanes_per_chain(int ny) { return ((ny - 1) / 2 + 1 + 15) / 16; }
 
 static size_t solve_lds_bytes(const sp_plan* p, bool fused, bool res = false) {
   const Dims& d = p->d;
-  const int jh8 = (((d.ny - 1) / 2 + 1) + 7) & ~7;
+  const size_t jh8 = (((d.ny - 1) / 2 + 1) + 7) & ~7;
+  // ten arrays of ny entries, which the fused analysis' folded columns share
+  const size_t arrays = fused ? std::max<size_t>(10 * (size_t)d.ny, 6 * jh8 + 4) : 10 * (size_t)d.ny;
   return (size_t)p->mode_stride * sizeof(double) + 3 * (size_t)d.ny * sizeof(double) +
-         10 * (size_t)d.ny * sizeof(cd) +
-         (fused ? (6 * (size_t)jh8 + 4) * sizeof(cd) + 6 * 64 * sizeof(double) : 0) +
+         arrays * sizeof(cd) + (fused ? 6 * 64 * sizeof(double) : 0) +
          (res ? 3 * (size_t)d.ny * sizeof(cd) : 0);
 }
 
