@@ -46,28 +46,37 @@ DEFAULT = "couette_48x65x48_re1000_dt100"
 HBM_PEAK_GBS = 8000.0
 CAL_COPY_BYTES = 256 * 1024 * 1024
 
-# HBM traffic of the per-mode solve measured with rocprofv3 --pmc FETCH_SIZE and
-# --pmc WRITE_SIZE over this script (KiB per dispatch, see profiles/), the
-# calibration factors from the 256 MiB copy above, and the hash of the kernel
-# sources the counters were taken with: a changed source reports traffic null.
-SOLVE_SOURCES = ["kernels.hip", "solve_row.h", "solve_core.h", "device_common.h"]
+# HBM traffic of the longest Phi kernels measured with rocprofv3 --pmc FETCH_SIZE
+# and --pmc WRITE_SIZE over this script (KiB per dispatch, see profiles/), the
+# calibration factors from the 256 MiB copy above, and the hash of the kernel's
+# sources (KERNEL_SOURCES) the counters were taken with: a changed source
+# reports traffic null.
+KERNEL_SOURCES = {
+    "k_stokes_solve": ["kernels.hip", "solve_row.h", "solve_core.h", "device_common.h"],
+    "k_z_product": ["zline.hip", "device_common.h"],
+}
 MEASURED_TRAFFIC = {
     "couette_48x65x48_re1000_dt100": {
+        # 256 MiB copy: FETCH_SIZE 131092.3 KiB, WRITE_SIZE 262144.0 KiB
         "k_stokes_solve": {
             "fetch_kib": 5611.6, "write_kib": 3674.3,
-            # 256 MiB copy: FETCH_SIZE 131091.7 KiB, WRITE_SIZE 262144.0 KiB
-            "fetch_factor": 262144.0 / 131091.7, "write_factor": 1.0,
+            "fetch_factor": 262144.0 / 131092.3, "write_factor": 1.0,
             "sources_sha256": "6d8eab5a02c7bee69b1cf019c8fb8eb0cc3333c2d80294df2cb5a5525c6c53f6",
+        },
+        "k_z_product": {
+            "fetch_kib": 3341.1, "write_kib": 5265.0,
+            "fetch_factor": 262144.0 / 131092.3, "write_factor": 1.0,
+            "sources_sha256": "b067c40e0c0b16987084aacc448632f0e362ab5aae6f6b79a08c23b972436c78",
         },
     },
 }
 STAGE_OF_KERNEL = {}  # profiler kernel name -> sp_time_stage stage (filled in main)
 
 
-def solve_sources_sha256():
+def sources_sha256(kernel="k_stokes_solve"):
     import hashlib
     h = hashlib.sha256()
-    for f in SOLVE_SOURCES:
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1804_05087_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -88,8 +97,12 @@ def solve_modes(w):
     return w["nx"] * nzh - (nzh + w["nx"] - 1)
 
 
-def algorithmic_bytes(w, fp32=False, jvp=False):
+def algorithmic_bytes(w, fp32=False, jvp=False, fused=False):
     """Compulsory HBM bytes per launch of each kernel (read once + written once).
+
+    fused: the z-line kernel takes the inverse x transforms itself, reading
+    the five y-valued fields instead of the six x-physical ones, and there is
+    no separate inverse x launch.
 
     The per-mode solve follows the phase count of the whole step, 27 S per
     evaluation with S one spectral field: its phase (Chebyshev analysis, right-
@@ -103,13 +116,18 @@ def algorithmic_bytes(w, fp32=False, jvp=False):
     yv1 = ny * nzm * nx * c          # one y-valued spectral field
     xp1 = ny * px * nzm * c          # one x-physical field
     S = spectral_field_bytes(w)
-    return {
+    base = 6 * ny * px * pz * r if jvp else 0
+    ab = {
         "k_synth_y": 3 * nx * nzm * ny * 16 + 5 * yv1,
         "k_fft_x_inv": 5 * yv1 + 6 * xp1,
-        "k_z_product": 6 * xp1 + 3 * xp1 + (6 * ny * px * pz * r if jvp else 0),
+        "k_z_product": 6 * xp1 + 3 * xp1 + base,
         "k_fft_x_fwd": 3 * xp1 + 3 * yv1,
         "k_stokes_solve": 9 * S,
     }
+    if fused:
+        del ab["k_fft_x_inv"]
+        ab["k_z_product"] = 5 * yv1 + 3 * xp1 + base
+    return ab
 
 
 def record_bytes(w):
@@ -1085,20 +1103,25 @@ def main():
 
     # ---- per-kernel durations of the FP64 Phi step: each stage kernel launched
     # back to back between two HIP events on the plan's stream (sp_time_stage)
-    ab = algorithmic_bytes(w)
     reps = max(50, min(1000, args.steps))
+    stage_us = {name: P.time_stage(stage, u, out, reps=reps)
+                for name, stage in STAGE_OF_KERNEL.items()}
+    # a stage with no launch of its own (the inverse x transforms taken by the
+    # z-line kernel) reports 0
+    fused = stage_us["k_fft_x_inv"] == 0.0
+    ab = algorithmic_bytes(w, fused=fused)
     kernels = {}
-    for name, stage in STAGE_OF_KERNEL.items():
-        avg_us = P.time_stage(stage, u, out, reps=reps)
-        kernels[name] = {"avg_us": round(avg_us, 3), "alg_bytes": ab[name],
-                         "achieved_GBs": round(ab[name] / (avg_us * 1e-6) / 1e9, 1)}
+    for name, avg_us in stage_us.items():
+        if name in ab:
+            kernels[name] = {"avg_us": round(avg_us, 3), "alg_bytes": ab[name],
+                             "achieved_GBs": round(ab[name] / (avg_us * 1e-6) / 1e9, 1)}
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
     dom_us = kernels[dom]["avg_us"]
     alg = kernels[dom]["alg_bytes"]
     achieved = round(alg / (dom_us * 1e-6) / 1e9, 1)
     traffic = None
     mt = MEASURED_TRAFFIC.get(args.workload, {}).get(dom)
-    if mt and mt["sources_sha256"] == solve_sources_sha256():
+    if mt and mt["sources_sha256"] == sources_sha256(dom):
         traffic = round(1024 * (mt["fetch_kib"] * mt["fetch_factor"] +
                                 mt["write_kib"] * mt["write_factor"]))
     S = spectral_field_bytes(w)

@@ -371,11 +371,14 @@ sp_status sp_profile_read(sp_plan* plan, int32_t n_max, char* names, int64_t* co
  * buffer, so repeated launches recompute the same result). Synchronises and
  * writes the average duration per launch in microseconds to *avg_us. On
  * return out holds Phi_dt(u). stage: SP_STAGE_*; reps in [1, 100000]; u and
- * out as for sp_befe_step, out must not alias u. Uses the plan's precision. */
+ * out as for sp_befe_step, out must not alias u. Uses the plan's precision.
+ * Where the z-line kernel takes the inverse x transforms itself (it reads the
+ * y-valued fields; chosen per grid and precision), SP_STAGE_XINV launches
+ * nothing and writes 0 to *avg_us, and SP_STAGE_ZLINE covers both stages. */
 typedef enum {
   SP_STAGE_SYNTH = 0, /* y-synthesis of u, du/dy, v, w, dw/dy (Sec. 3.2) */
   SP_STAGE_XINV = 1,  /* curl factors, 3/2 padding, inverse x FFT */
-  SP_STAGE_ZLINE = 2, /* inverse z FFT, u x omega, forward z FFT */
+  SP_STAGE_ZLINE = 2, /* [inverse x FFT,] inverse z FFT, u x omega, forward z FFT */
   SP_STAGE_XFWD = 3,  /* forward x FFT, truncation */
   SP_STAGE_SOLVE = 4  /* Chebyshev analysis + u/dt + per-mode implicit solve */
 } sp_stage;

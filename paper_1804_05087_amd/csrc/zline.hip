@@ -15,6 +15,13 @@
 // Hermitian extension of both spectra, and the forward output is unpacked with
 // A[m] = (C[m] + conj C[P - m]) / 2, B[m] = (C[m] - conj C[P - m]) / (2i).
 // Block: XL x-lines of one y-plane.
+//
+// With XF the kernel also takes the inverse x transforms (3/2 padding in x)
+// that feed its lines, from the y-valued spectral fields [f][y][kz][mx]: the
+// block's lines are x = a + Q j (j < XL, Q = px / XL), for which
+//   X(a + Q j) = sum_r W_XL^(-r j) g_r,  g_r = sum_{m = r mod XL} c_m exp(2 pi i m a / px),
+// so each block forms XL partial sums per (field, kz) and one XL-point DFT,
+// and the x-physical fields never leave the block.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -85,11 +92,17 @@ struct ZLineMap {
   int fout_a[3], fout_b[3];
 };
 
-template <typename R, int P1, int P2, int XL, class Op>
+// XF: in = the five y-valued fields (u, du/dy, v, w, dw/dy) [f][y][kz][mx],
+// from which the six curl-combined fields of the x-lines are formed (the
+// line map must pair fields (0, 1), (2, 3), (4, 5)); requires px % XL == 0,
+// nzm == P / 3 and a 1-D grid of ny * (px / XL) blocks. Otherwise in = the
+// x-physical fields [f][y][x][kz] and the grid is (ny, ceil(px / XL)).
+template <typename R, int P1, int P2, int XL, class Op, bool XF = false>
 __global__ void __launch_bounds__(256)
     k_zline(const typename V2<R>::T* in, typename V2<R>::T* out,  // may alias (in place)
             R* __restrict__ base, const typename V2<R>::T* __restrict__ tw, ZLineMap map, int ny,
-            int px, int nzm, R scale) {
+            int px, int nzm, R scale, const typename V2<R>::T* __restrict__ twx = nullptr,
+            int nx = 0, R alpha = 0, R gamma = 0) {
   using C = typename V2<R>::T;
   constexpr int P = P1 * P2;
   constexpr int NI = Op::NI;
@@ -102,16 +115,83 @@ __global__ void __launch_bounds__(256)
   constexpr bool kSplit = Op::kBase && NF > 0 && NF <= NI;
   constexpr int LS = NI;  // line slots per x-line in the exchange block
   constexpr int E1 = (XL * LS * P2 * S1 > XL * NF * P) ? XL * LS * P2 * S1 : XL * NF * P;
+  constexpr int NXF = 6;  // x-physical fields formed by XF
+  constexpr int E2F = NF > 0 ? XL * NF * P2 * S1 : 1;
+  constexpr int E2X = XF ? XL * NXF * (P / 3) : 1;
+  static_assert(!XF || (XL == 8 && NI == 3 && E1 >= NXF * (P / 3) * (XL + 1)),
+                "XF: eight lines of three packed pairs; partial sums fit the exchange block");
   __shared__ C twl[P];
-  __shared__ C ex1[E1];                          // inverse exchange, then forward output
-  __shared__ C ex2[NF > 0 ? XL * NF * P2 * S1 : 1];  // forward exchange
-  const int y = blockIdx.x;
-  const int x0 = blockIdx.y * XL;
-  const int nxl = min(XL, px - x0);
+  __shared__ C ex1[E1];  // inverse exchange, then forward output (XF: first the partial sums)
+  __shared__ C ex2[E2F > E2X ? E2F : E2X];  // forward exchange (XF: first the x-physical lines)
   const int tid = threadIdx.x;
+  int y, x0, xq, nxl;  // line xl of the block is x = x0 + xq * xl
+  if constexpr (XF) {
+    const int nq = px / XL;
+    const int l = xcd_order(blockIdx.x, gridDim.x);  // the blocks of one y-plane share an L2
+    y = l / nq;
+    x0 = l - y * nq;
+    xq = nq;
+    nxl = XL;
+  } else {
+    y = blockIdx.x;
+    x0 = blockIdx.y * XL;
+    xq = 1;
+    nxl = min(XL, px - x0);
+  }
   const size_t fs = (size_t)ny * px * nzm;
-  const size_t lo = ((size_t)y * px + x0) * nzm;  // first line of the block in a field
+  // offset of line xl in a field of the x-physical layout (in units of nzm)
+  auto line_of = [&](int xl) { return (size_t)y * px + x0 + (size_t)xq * xl; };
   for (int t = tid; t < P; t += 256) twl[t] = tw[t];
+  if constexpr (XF) {
+    // partial sums g_r of the six curl-combined fields: task (kz, r), over the
+    // padded positions m = r + XL t (kept modes m < nx/2 and m > px - nx/2)
+    C* gl = ex1;  // [NXF][nzm][XL + 1]
+    const size_t fsy = (size_t)ny * nzm * nx;
+    const int h = nx / 2;
+    for (int task = tid; task < nzm * XL; task += 256) {
+      const int r = task % XL;
+      const int kz = task / XL;
+      const C* src = in + ((size_t)y * nzm + kz) * nx;
+      const R kzv = gamma * (R)kz;
+      C g[NXF];
+#pragma unroll
+      for (int f = 0; f < NXF; ++f) g[f] = mk((R)0, (R)0);
+      for (int pos = r; pos < px; pos += XL) {
+        const bool lo_m = pos < h;
+        if (lo_m || pos > px - h) {
+          const int i = lo_m ? pos : pos - px + nx;
+          const R kxv = alpha * (R)(lo_m ? i : i - nx);
+          const C s0 = src[i], s1 = src[fsy + i], s2 = src[2 * fsy + i];
+          const C s3 = src[3 * fsy + i], s4 = src[4 * fsy + i];
+          C val[NXF];
+          val[0] = s0;                                                     // u
+          val[1] = s2;                                                     // v
+          val[2] = s3;                                                     // w
+          val[3] = csub(s4, sidot(cscale(s2, kzv), (R)1));                 // dw/dy - i kz v
+          val[4] = sidot(csub(cscale(s0, kzv), cscale(s3, kxv)), (R)1);    // i kz u - i kx w
+          val[5] = csub(sidot(cscale(s2, kxv), (R)1), s1);                 // i kx v - du/dy
+          const C w = conjc(twx[(pos * x0) % px]);  // exp(2 pi i m a / px)
+#pragma unroll
+          for (int f = 0; f < NXF; ++f) g[f] = cadd(g[f], cmul(val[f], w));
+        }
+      }
+#pragma unroll
+      for (int f = 0; f < NXF; ++f) gl[(f * nzm + kz) * (XL + 1) + r] = g[f];
+    }
+    __syncthreads();
+    // XL-point inverse DFT over r: task (field, kz) -> the block's XL lines
+    C* xs = ex2;  // [XL][NXF][nzm]
+    for (int task = tid; task < NXF * nzm; task += 256) {
+      const int kz = task % nzm;
+      const int f = task / nzm;
+      C v[XL];
+#pragma unroll
+      for (int r = 0; r < XL; ++r) v[r] = gl[(f * nzm + kz) * (XL + 1) + r];
+      dft_reg<XL, P, C, R>(v, (R)1, twl);
+#pragma unroll
+      for (int j = 0; j < XL; ++j) xs[(j * NXF + f) * nzm + kz] = v[j];
+    }
+  }
   __syncthreads();
 
   // step 1 of the inverse transforms: task (xl, line i, n2)
@@ -121,9 +201,17 @@ __global__ void __launch_bounds__(256)
     const int i = li % NI;
     const int xl = li / NI;
     if (xl < nxl) {
-      const C* fa = in + (size_t)map.fin_a[i] * fs + lo + (size_t)xl * nzm;
       const int fb = map.fin_b[i];
-      const C* fbp = in + (size_t)(fb < 0 ? map.fin_a[i] : fb) * fs + lo + (size_t)xl * nzm;
+      const int fbi = fb < 0 ? map.fin_a[i] : fb;
+      const C* fa;
+      const C* fbp;
+      if constexpr (XF) {
+        fa = ex2 + (xl * NXF + map.fin_a[i]) * nzm;
+        fbp = ex2 + (xl * NXF + fbi) * nzm;
+      } else {
+        fa = in + (size_t)map.fin_a[i] * fs + line_of(xl) * nzm;
+        fbp = in + (size_t)fbi * fs + line_of(xl) * nzm;
+      }
       const R bk = (fb < 0) ? (R)0 : (R)1;
       C v[P1];
 #pragma unroll
@@ -167,7 +255,7 @@ __global__ void __launch_bounds__(256)
       dft_reg<P2, P, C, R>(ph, (R)1, twl);
       if constexpr (NF == 0) {  // the base state: packed line i holds fields 2i, 2i + 1
         const int i = li % NI;
-        const size_t bo0 = ((size_t)y * px + x0 + xl) * P + k1;
+        const size_t bo0 = line_of(xl) * P + k1;
 #pragma unroll
         for (int k2 = 0; k2 < P2; ++k2) {
           const size_t bo = bo0 + (size_t)P1 * k2;
@@ -195,7 +283,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int i = 0; i < NI; ++i) pin[i] = ex1[((xl * LS + i) * P2 + k2) * S1 + k1];
         const Op op{};
-        op(pin, pout, base, bs, ((size_t)y * px + x0 + xl) * P + k1 + (size_t)P1 * k2);
+        op(pin, pout, base, bs, line_of(xl) * P + k1 + (size_t)P1 * k2);
 #pragma unroll
         for (int f = 0; f < NF; ++f) ex1[((xl * LS + f) * P2 + k2) * S1 + k1] = pout[f];
       }
@@ -231,7 +319,7 @@ __global__ void __launch_bounds__(256)
       const int k1 = task % P1;
       const int xl = (task / P1) % XL;
       if (xl < nxl) {
-        const size_t bo0 = ((size_t)y * px + x0 + xl) * P + k1;
+        const size_t bo0 = line_of(xl) * P + k1;
         // forward lines F0 .. F0 + NFL - 1 (compile-time, so pout stays in registers)
         auto run = [&](auto f0) {
           constexpr int F0 = decltype(f0)::value;
@@ -300,7 +388,7 @@ __global__ void __launch_bounds__(256)
       if (xl < nxl) {
         const C* o = ex1 + lf * P;
         const C a = o[m];
-        const size_t off = lo + (size_t)xl * nzm + m;
+        const size_t off = line_of(xl) * nzm + m;
         if (map.fout_b[f] < 0) {
           out[(size_t)map.fout_a[f] * fs + off] = cscale(a, scale);
         } else {
@@ -322,20 +410,35 @@ hipError_t launch_adj_z_lds(sp_plan* p, bool fp32);
 
 constexpr int kZXL = 8;
 
-template <typename R, class Op>
+template <typename R, class Op, bool XF = false>
 static void zline_launch(sp_plan* p, const void* in, void* out, R* base, const void* tw,
-                         const ZLineMap& map, double scale) {
+                         const ZLineMap& map, double scale, const void* twx = nullptr) {
   const Dims& d = p->d;
   using C = typename V2<R>::T;
-  dim3 grid(d.ny, (d.px + kZXL - 1) / kZXL);
+  const dim3 grid = XF ? dim3(d.ny * (d.px / kZXL)) : dim3(d.ny, (d.px + kZXL - 1) / kZXL);
   const C* ci = (const C*)in;
   C* co = (C*)out;
   const C* ct = (const C*)tw;
+  const C* cx = (const C*)twx;
 #define ZL(A, B)                                                                              \
-  hipLaunchKernelGGL((k_zline<R, A, B, kZXL, Op>), grid, dim3(256), 0, p->stream, ci, co, base, \
-                     ct, map, d.ny, d.px, d.nzm, (R)scale)
+  hipLaunchKernelGGL((k_zline<R, A, B, kZXL, Op, XF>), grid, dim3(256), 0, p->stream, ci, co,  \
+                     base, ct, map, d.ny, d.px, d.nzm, (R)scale, cx, d.nx, (R)d.alpha,        \
+                     (R)d.gamma)
   SP_REG_FFT_DISPATCH(d.pz, ZL)
 #undef ZL
+}
+
+// Every block of the fused kernel reads its whole y-plane of the five y-valued
+// fields, so one plane is read px / kZXL times. Measured on MI355X: fused is
+// faster while those reads stay within one XCD's 4 MiB L2 (48x65x48 in FP64
+// and FP32: 0.8 and 0.4 MiB per plane; 96x97x96 in FP32: 3.2 MiB) and slower
+// beyond (96x97x96 in FP64: 6.3 MiB per plane, 146 us against 57 + 61 us for
+// the two kernels).
+bool zline_fuses_x_inverse(const sp_plan* p, bool fp32) {
+  const Dims& d = p->d;
+  if (reg_fft_split(d.pz) == 0 || d.px % kZXL != 0 || 3 * d.nzm != d.pz) return false;
+  const size_t plane = (size_t)5 * d.nzm * d.nx * (fp32 ? sizeof(float2) : sizeof(double2));
+  return (size_t)(d.px / kZXL) * plane <= ((size_t)4 << 20);
 }
 
 hipError_t launch_z_product(sp_plan* p, int mode, bool fp32) {
@@ -344,21 +447,36 @@ hipError_t launch_z_product(sp_plan* p, int mode, bool fp32) {
   const double scale = 1.0 / ((double)d.px * d.pz);
   const ZLineMap map{{0, 2, 4}, {1, 3, 5}, {0, 2, -1}, {1, -1, -1}};
   SP_PROF_BEGIN(p, KID_Z_PRODUCT);
-  if (fp32) {
-    if (mode == 0)
-      zline_launch<float, OpCross<float>>(p, p->xp, p->np, p->base32, p->f_twz, map, scale);
-    else if (mode == 1)
-      zline_launch<float, OpCrossLin<float>>(p, p->xp, p->np, p->base32, p->f_twz, map, scale);
-    else
-      zline_launch<float, OpStoreBase<float>>(p, p->xp, p->np, p->base32, p->f_twz, map, scale);
-  } else {
-    if (mode == 0)
-      zline_launch<double, OpCross<double>>(p, p->xp, p->np, p->base, p->d_twz, map, scale);
-    else if (mode == 1)
-      zline_launch<double, OpCrossLin<double>>(p, p->xp, p->np, p->base, p->d_twz, map, scale);
-    else
-      zline_launch<double, OpStoreBase<double>>(p, p->xp, p->np, p->base, p->d_twz, map, scale);
-  }
+  // fused: the y-valued fields in, the inverse x transforms taken in the kernel
+  auto run = [&](auto xf) {
+    constexpr bool XF = decltype(xf)::value;
+    const void* in = XF ? p->yv : p->xp;
+    if (fp32) {
+      if (mode == 0)
+        zline_launch<float, OpCross<float>, XF>(p, in, p->np, p->base32, p->f_twz, map, scale,
+                                                p->f_twx);
+      else if (mode == 1)
+        zline_launch<float, OpCrossLin<float>, XF>(p, in, p->np, p->base32, p->f_twz, map,
+                                                   scale, p->f_twx);
+      else
+        zline_launch<float, OpStoreBase<float>, XF>(p, in, p->np, p->base32, p->f_twz, map,
+                                                    scale, p->f_twx);
+    } else {
+      if (mode == 0)
+        zline_launch<double, OpCross<double>, XF>(p, in, p->np, p->base, p->d_twz, map, scale,
+                                                  p->d_twx);
+      else if (mode == 1)
+        zline_launch<double, OpCrossLin<double>, XF>(p, in, p->np, p->base, p->d_twz, map,
+                                                     scale, p->d_twx);
+      else
+        zline_launch<double, OpStoreBase<double>, XF>(p, in, p->np, p->base, p->d_twz, map,
+                                                      scale, p->d_twx);
+    }
+  };
+  if (zline_fuses_x_inverse(p, fp32))
+    run(std::true_type{});
+  else
+    run(std::false_type{});
   SP_PROF_END(p, KID_Z_PRODUCT);
   return hipGetLastError();
 }

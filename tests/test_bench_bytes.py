@@ -42,6 +42,13 @@ def test_algorithmic_bytes_48x65x48():
     assert bench.record_bytes(w) == 3_629_208
     assert ab["k_synth_y"] == 9_584_640
     assert math.isclose(ab["k_fft_x_inv"] / 1e6, 16.77, abs_tol=0.005)
+    # the z-line kernel that takes the inverse x transforms reads the five
+    # y-valued fields and writes the three product fields; no x-inverse launch
+    abf = bench.algorithmic_bytes(w, fused=True)
+    assert "k_fft_x_inv" not in abf
+    assert abf["k_z_product"] == 5 * yv + 3 * xp
+    assert {k: v for k, v in abf.items() if k != "k_z_product"} == \
+        {k: v for k, v in ab.items() if k not in ("k_z_product", "k_fft_x_inv")}
 
 
 def test_mixed_path_halves_transform_bytes():

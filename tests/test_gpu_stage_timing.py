@@ -1,6 +1,8 @@
 """sp_time_stage: every stage kernel of the FP64 and mixed Phi evaluation can be
 relaunched back to back on the scratch state of one evaluation without
-changing the result, and reports a positive duration."""
+changing the result, and reports a positive duration. Where the z-line kernel
+takes the inverse x transforms itself (3nx/2 a multiple of 8 on these small
+grids), the inverse x stage has no launch of its own and reports 0."""
 import pytest
 
 from gpu_util import BOX, rel, say, to_dev, to_np
@@ -13,11 +15,12 @@ STAGES = [SP_STAGE_SYNTH, SP_STAGE_XINV, SP_STAGE_ZLINE, SP_STAGE_XFWD, SP_STAGE
 
 
 @pytest.mark.parametrize("prec", [SP_FP64, SP_MIXED])
-def test_stage_relaunch_keeps_phi(prec):
+@pytest.mark.parametrize("dims,fused", [((16, 17, 16), True), ((12, 17, 16), False)])
+def test_stage_relaunch_keeps_phi(prec, dims, fused):
     import torch
     from paper_1804_05087_amd import Plan
-    nx, ny, nz = 16, 17, 16
-    say("time_stage", prec)
+    nx, ny, nz = dims
+    say("time_stage", prec, dims)
     P = Plan(nx, ny, nz, *BOX, 400.0, 100.0)
     P.set_precision(prec)
     u = to_dev(synth.perturbation_field(nx, ny, nz, *BOX, seed=0))
@@ -25,7 +28,10 @@ def test_stage_relaunch_keeps_phi(prec):
     for st in STAGES:
         out = P.empty()
         us = P.time_stage(st, u, out, reps=5)
-        assert us > 0.0, (st, us)
+        if st == SP_STAGE_XINV and fused:
+            assert us == 0.0, us
+        else:
+            assert us > 0.0, (st, us)
         # out = Phi(u); relaunching a stage recomputes its own output from unchanged
         # input, so the solve stage rewrites out with the same values
         assert rel(to_np(out), ref) == 0.0, st
