@@ -94,8 +94,8 @@ struct ZLineMap {
 
 // XF: in = the five y-valued fields (u, du/dy, v, w, dw/dy) [f][y][kz][mx],
 // from which the six curl-combined fields of the x-lines are formed (the
-// line map must pair fields (0, 1), (2, 3), (4, 5)); requires px % XL == 0,
-// nzm == P / 3 and a 1-D grid of ny * (px / XL) blocks. Otherwise in = the
+// line map must pair fields (0, 1), (2, 3), (4, 5)); requires nx % 16 == 0
+// (so px % XL == 0), nzm == P / 3 and a 1-D grid of ny * (px / XL) blocks. Otherwise in = the
 // x-physical fields [f][y][x][kz] and the grid is (ny, ceil(px / XL)).
 template <typename R, int P1, int P2, int XL, class Op, bool XF = false>
 __global__ void __launch_bounds__(256)
@@ -144,10 +144,16 @@ __global__ void __launch_bounds__(256)
   for (int t = tid; t < P; t += 256) twl[t] = tw[t];
   if constexpr (XF) {
     // partial sums g_r of the six curl-combined fields: task (kz, r), over the
-    // padded positions m = r + XL t (kept modes m < nx/2 and m > px - nx/2)
+    // kept padded positions m = r mod XL. With nx a multiple of 16 these are,
+    // for t < nx/16, m = r + XL t (mode i = m) in the low half and
+    // m = nx + r + XL t (mode i = m - nx/2) in the high half, except the empty
+    // position m = nx; taken in pairs with unconditional loads (the empty one
+    // loads mode nx/2 and is weighted 0) so that each pair's loads are in
+    // flight together.
     C* gl = ex1;  // [NXF][nzm][XL + 1]
     const size_t fsy = (size_t)ny * nzm * nx;
     const int h = nx / 2;
+    const int h8 = nx / (2 * XL);
     for (int task = tid; task < nzm * XL; task += 256) {
       const int r = task % XL;
       const int kz = task / XL;
@@ -156,11 +162,12 @@ __global__ void __launch_bounds__(256)
       C g[NXF];
 #pragma unroll
       for (int f = 0; f < NXF; ++f) g[f] = mk((R)0, (R)0);
-      for (int pos = r; pos < px; pos += XL) {
-        const bool lo_m = pos < h;
-        if (lo_m || pos > px - h) {
-          const int i = lo_m ? pos : pos - px + nx;
-          const R kxv = alpha * (R)(lo_m ? i : i - nx);
+      for (int t = 0; t < h8; ++t) {
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          const int pos = (half ? nx : 0) + r + XL * t;
+          const int i = half ? pos - h : pos;
+          const R kxv = alpha * (R)(half ? i - nx : i);
           const C s0 = src[i], s1 = src[fsy + i], s2 = src[2 * fsy + i];
           const C s3 = src[3 * fsy + i], s4 = src[4 * fsy + i];
           C val[NXF];
@@ -170,7 +177,9 @@ __global__ void __launch_bounds__(256)
           val[3] = csub(s4, sidot(cscale(s2, kzv), (R)1));                 // dw/dy - i kz v
           val[4] = sidot(csub(cscale(s0, kzv), cscale(s3, kxv)), (R)1);    // i kz u - i kx w
           val[5] = csub(sidot(cscale(s2, kxv), (R)1), s1);                 // i kx v - du/dy
-          const C w = conjc(twx[(pos * x0) % px]);  // exp(2 pi i m a / px)
+          // exp(2 pi i m a / px), zero at the empty position
+          const R keep = (half && pos == nx) ? (R)0 : (R)1;
+          const C w = cscale(conjc(twx[(pos * x0) % px]), keep);
 #pragma unroll
           for (int f = 0; f < NXF; ++f) g[f] = cadd(g[f], cmul(val[f], w));
         }
@@ -436,7 +445,7 @@ static void zline_launch(sp_plan* p, const void* in, void* out, R* base, const v
 // the two kernels).
 bool zline_fuses_x_inverse(const sp_plan* p, bool fp32) {
   const Dims& d = p->d;
-  if (reg_fft_split(d.pz) == 0 || d.px % kZXL != 0 || 3 * d.nzm != d.pz) return false;
+  if (reg_fft_split(d.pz) == 0 || d.nx % (2 * kZXL) != 0 || 3 * d.nzm != d.pz) return false;
   const size_t plane = (size_t)5 * d.nzm * d.nx * (fp32 ? sizeof(float2) : sizeof(double2));
   return (size_t)(d.px / kZXL) * plane <= ((size_t)4 << 20);
 }
