@@ -138,7 +138,10 @@ __global__ void __launch_bounds__(256)
     xq = 1;
     nxl = min(XL, px - x0);
   }
-  const size_t fs = (size_t)ny * px * nzm;
+  // kept z modes per line: P / 3 for XF (checked by the launcher), so that the
+  // Hermitian extension's masks fold at compile time where they are uniform
+  const int nzk = XF ? P / 3 : nzm;
+  const size_t fs = (size_t)ny * px * nzk;
   // offset of line xl in a field of the x-physical layout (in units of nzm)
   auto line_of = [&](int xl) { return (size_t)y * px + x0 + (size_t)xq * xl; };
   for (int t = tid; t < P; t += 256) twl[t] = tw[t];
@@ -150,18 +153,22 @@ __global__ void __launch_bounds__(256)
     // position m = nx; taken in pairs with unconditional loads (the empty one
     // loads mode nx/2 and is weighted 0) so that each pair's loads are in
     // flight together.
+    // The curl combination is linear, so the sums run over the five input
+    // fields (A_k = sum w s_k) and, for the two terms with a factor i k_x,
+    // over k_x w s_k (B_2, B_3); the six fields are formed from them once.
     C* gl = ex1;  // [NXF][nzm][XL + 1]
-    const size_t fsy = (size_t)ny * nzm * nx;
+    const size_t fsy = (size_t)ny * nzk * nx;
     const int h = nx / 2;
     const int h8 = nx / (2 * XL);
-    for (int task = tid; task < nzm * XL; task += 256) {
+    const int dq = (XL * x0) % px;  // step of the twiddle index m a mod px per t
+    for (int task = tid; task < nzk * XL; task += 256) {
       const int r = task % XL;
       const int kz = task / XL;
-      const C* src = in + ((size_t)y * nzm + kz) * nx;
-      const R kzv = gamma * (R)kz;
-      C g[NXF];
+      const C* src = in + ((size_t)y * nzk + kz) * nx;
+      C A[5], B2 = mk((R)0, (R)0), B3 = mk((R)0, (R)0);
 #pragma unroll
-      for (int f = 0; f < NXF; ++f) g[f] = mk((R)0, (R)0);
+      for (int k = 0; k < 5; ++k) A[k] = mk((R)0, (R)0);
+      int q[2] = {(r * x0) % px, ((nx + r) * x0) % px};
       for (int t = 0; t < h8; ++t) {
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
@@ -170,35 +177,44 @@ __global__ void __launch_bounds__(256)
           const R kxv = alpha * (R)(half ? i - nx : i);
           const C s0 = src[i], s1 = src[fsy + i], s2 = src[2 * fsy + i];
           const C s3 = src[3 * fsy + i], s4 = src[4 * fsy + i];
-          C val[NXF];
-          val[0] = s0;                                                     // u
-          val[1] = s2;                                                     // v
-          val[2] = s3;                                                     // w
-          val[3] = csub(s4, sidot(cscale(s2, kzv), (R)1));                 // dw/dy - i kz v
-          val[4] = sidot(csub(cscale(s0, kzv), cscale(s3, kxv)), (R)1);    // i kz u - i kx w
-          val[5] = csub(sidot(cscale(s2, kxv), (R)1), s1);                 // i kx v - du/dy
           // exp(2 pi i m a / px), zero at the empty position
           const R keep = (half && pos == nx) ? (R)0 : (R)1;
-          const C w = cscale(conjc(twx[(pos * x0) % px]), keep);
-#pragma unroll
-          for (int f = 0; f < NXF; ++f) g[f] = cadd(g[f], cmul(val[f], w));
+          const C w = cscale(conjc(twx[q[half]]), keep);
+          const C wk = cscale(w, kxv);
+          A[0] = cadd(A[0], cmul(s0, w));
+          A[1] = cadd(A[1], cmul(s1, w));
+          A[2] = cadd(A[2], cmul(s2, w));
+          A[3] = cadd(A[3], cmul(s3, w));
+          A[4] = cadd(A[4], cmul(s4, w));
+          B2 = cadd(B2, cmul(s2, wk));
+          B3 = cadd(B3, cmul(s3, wk));
+          q[half] += dq;
+          q[half] -= (q[half] >= px) ? px : 0;
         }
       }
+      const R kzv = gamma * (R)kz;
+      C g[NXF];
+      g[0] = A[0];                                               // u
+      g[1] = A[2];                                               // v
+      g[2] = A[3];                                               // w
+      g[3] = csub(A[4], sidot(cscale(A[2], kzv), (R)1));         // dw/dy - i kz v
+      g[4] = sidot(csub(cscale(A[0], kzv), B3), (R)1);           // i kz u - i kx w
+      g[5] = csub(sidot(B2, (R)1), A[1]);                        // i kx v - du/dy
 #pragma unroll
-      for (int f = 0; f < NXF; ++f) gl[(f * nzm + kz) * (XL + 1) + r] = g[f];
+      for (int f = 0; f < NXF; ++f) gl[(f * nzk + kz) * (XL + 1) + r] = g[f];
     }
     __syncthreads();
     // XL-point inverse DFT over r: task (field, kz) -> the block's XL lines
     C* xs = ex2;  // [XL][NXF][nzm]
-    for (int task = tid; task < NXF * nzm; task += 256) {
-      const int kz = task % nzm;
-      const int f = task / nzm;
+    for (int task = tid; task < NXF * nzk; task += 256) {
+      const int kz = task % nzk;
+      const int f = task / nzk;
       C v[XL];
 #pragma unroll
-      for (int r = 0; r < XL; ++r) v[r] = gl[(f * nzm + kz) * (XL + 1) + r];
+      for (int r = 0; r < XL; ++r) v[r] = gl[(f * nzk + kz) * (XL + 1) + r];
       dft_reg<XL, P, C, R>(v, (R)1, twl);
 #pragma unroll
-      for (int j = 0; j < XL; ++j) xs[(j * NXF + f) * nzm + kz] = v[j];
+      for (int j = 0; j < XL; ++j) xs[(j * NXF + f) * nzk + kz] = v[j];
     }
   }
   __syncthreads();
@@ -215,11 +231,11 @@ __global__ void __launch_bounds__(256)
       const C* fa;
       const C* fbp;
       if constexpr (XF) {
-        fa = ex2 + (xl * NXF + map.fin_a[i]) * nzm;
-        fbp = ex2 + (xl * NXF + fbi) * nzm;
+        fa = ex2 + (xl * NXF + map.fin_a[i]) * nzk;
+        fbp = ex2 + (xl * NXF + fbi) * nzk;
       } else {
-        fa = in + (size_t)map.fin_a[i] * fs + line_of(xl) * nzm;
-        fbp = in + (size_t)fbi * fs + line_of(xl) * nzm;
+        fa = in + (size_t)map.fin_a[i] * fs + line_of(xl) * nzk;
+        fbp = in + (size_t)fbi * fs + line_of(xl) * nzk;
       }
       const R bk = (fb < 0) ? (R)0 : (R)1;
       C v[P1];
@@ -228,8 +244,8 @@ __global__ void __launch_bounds__(256)
         const int m = P2 * n1 + n2;
         // Hermitian extension: m < nzm direct, m > P - nzm mirrored, else zero;
         // masks multiply loaded values so the loads stay unconditional
-        const bool lo_half = m < nzm;
-        const bool hi_half = m > P - nzm;
+        const bool lo_half = m < nzk;
+        const bool hi_half = m > P - nzk;
         const int mm = lo_half ? m : (hi_half ? P - m : 0);
         const C a = fa[mm];
         const C b = fbp[mm];
@@ -389,15 +405,15 @@ __global__ void __launch_bounds__(256)
     }
     __syncthreads();
     // unpack, scale and store the kept modes m < nzm: task (xl, line f, m)
-    for (int task = tid; task < XL * NF * nzm; task += 256) {
-      const int m = task % nzm;
-      const int lf = task / nzm;
+    for (int task = tid; task < XL * NF * nzk; task += 256) {
+      const int m = task % nzk;
+      const int lf = task / nzk;
       const int f = lf % NF;
       const int xl = lf / NF;
       if (xl < nxl) {
         const C* o = ex1 + lf * P;
         const C a = o[m];
-        const size_t off = line_of(xl) * nzm + m;
+        const size_t off = line_of(xl) * nzk + m;
         if (map.fout_b[f] < 0) {
           out[(size_t)map.fout_a[f] * fs + off] = cscale(a, scale);
         } else {
