@@ -414,7 +414,8 @@ sp_status vjp_lin(sp_plan* p, int op, const double2* w, double2* out) {
   // entry, and forms the residual's (. - w)/dt
   SP_TRY_HIP(launch_stokes_solve_adj(p, w, p->t2), "stokes_solve_adj");
   SP_TRY_HIP(launch_synth_tab(p, p->t2, 1, p->nv, fp32), "analysis^T");
-  SP_TRY_HIP(launch_fft_x_inv_gen(p, p->nv, p->xp, 3, 1, fp32), "pad+ifft_x");
+  if (!zline_fuses_x_inverse(p, fp32, 3))
+    SP_TRY_HIP(launch_fft_x_inv_gen(p, p->nv, p->xp, 3, 1, fp32), "pad+ifft_x");
   SP_TRY_HIP(launch_adj_z(p, fp32), "adj_z");
   SP_TRY_HIP(launch_fft_x_fwd_gen(p, p->xp, p->yv, 6, fp32), "fft_x+truncate");
   const bool res = (op == SP_OP_RESIDUAL);

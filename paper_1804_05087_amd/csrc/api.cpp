@@ -24,7 +24,7 @@ namespace sp {
 // a2-a5: N(u) (or its linearisation, mode 1) into p->nv (y-valued spectral).
 static sp_status nonlinear_to_nv(sp_plan* p, const double2* u, int mode, bool fp32) {
   SP_TRY_HIP(launch_synth_y(p, u, fp32), "synth_y");
-  if (!zline_fuses_x_inverse(p, fp32)) SP_TRY_HIP(launch_fft_x_inv(p, fp32), "fft_x_inv");
+  if (!zline_fuses_x_inverse(p, fp32, 5)) SP_TRY_HIP(launch_fft_x_inv(p, fp32), "fft_x_inv");
   SP_TRY_HIP(launch_z_product(p, mode, fp32), "z_product");
   SP_TRY_HIP(launch_fft_x_fwd(p, fp32), "fft_x_fwd");
   return SP_OK;
@@ -146,7 +146,7 @@ sp_status residual_into(sp_plan* p, const double2* u, double2* r) {
 static sp_status cache_base(sp_plan* p, const double2* u) {
   const bool fp32 = (p->precision == SP_MIXED);
   SP_TRY_HIP(launch_synth_y(p, u, fp32), "synth_y");
-  if (!zline_fuses_x_inverse(p, fp32)) SP_TRY_HIP(launch_fft_x_inv(p, fp32), "fft_x_inv");
+  if (!zline_fuses_x_inverse(p, fp32, 5)) SP_TRY_HIP(launch_fft_x_inv(p, fp32), "fft_x_inv");
   SP_TRY_HIP(launch_z_product(p, 2, fp32), "z_product(base)");
   return SP_OK;
 }
@@ -689,7 +689,7 @@ extern "C" sp_status sp_time_stage(sp_plan* p, int32_t stage, const double* u, d
   double2* oo = (double2*)out;
   sp_status s = befe_into(p, uu, oo, fp32);
   if (s) return s;
-  if (stage == SP_STAGE_XINV && zline_fuses_x_inverse(p, fp32)) {  // no launch of its own
+  if (stage == SP_STAGE_XINV && zline_fuses_x_inverse(p, fp32, 5)) {  // no launch of its own
     *avg_us = 0.0;
     return SP_OK;
   }

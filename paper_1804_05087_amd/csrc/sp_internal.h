@@ -234,9 +234,10 @@ hipError_t launch_fft_x_inv(sp_plan* p, bool fp32);
 // mode 0: u x omega ; 1: linearised du x Omega + U x dw (needs base) ;
 // 2: store U, Omega into base (no product) ; 3: adjoint (see kernels.hip)
 hipError_t launch_z_product(sp_plan* p, int mode, bool fp32);
-// true when launch_z_product takes the inverse x transforms itself (reading the
-// y-valued fields), so that launch_fft_x_inv is not part of the forward chain
-bool zline_fuses_x_inverse(const sp_plan* p, bool fp32);
+// true when the z-line kernels take the inverse x transforms themselves,
+// reading nfields y-valued fields (5: launch_z_product, from p->yv; 3:
+// launch_adj_z, from p->nv), so that no separate inverse x launch precedes them
+bool zline_fuses_x_inverse(const sp_plan* p, bool fp32, int nfields);
 hipError_t launch_fft_x_fwd(sp_plan* p, bool fp32);
 // which = 0: forward synthesis table into p->yv; 1: Tinv^T on 3 components into out
 hipError_t launch_synth_tab(sp_plan* p, const double2* u, int which, void* out, bool fp32);

@@ -38,6 +38,7 @@ namespace sp {
 template <typename R>
 struct OpCross {  // n = u x omega; in = (u + i v, w + i ox, oy + i oz); out = (nx + i ny, nz)
   static constexpr int NI = 3, NF = 2;
+  static constexpr int kXIn = 5;        // XF: y-valued fields in (curl-combined to six)
   static constexpr bool kBase = false;  // reads no base state
   template <typename C>
   __device__ void operator()(const C (&in)[3], C (&out)[2], const R*, size_t, size_t) const {
@@ -50,6 +51,7 @@ struct OpCross {  // n = u x omega; in = (u + i v, w + i ox, oy + i oz); out = (
 template <typename R>
 struct OpCrossLin {  // n = du x Omega + U x domega with (U, Omega) from base
   static constexpr int NI = 3, NF = 2;
+  static constexpr int kXIn = 5;
   static constexpr bool kBase = true;
   template <typename C>
   __device__ void operator()(const C (&in)[3], C (&out)[2], const R* base, size_t bs,
@@ -65,12 +67,14 @@ struct OpCrossLin {  // n = du x Omega + U x domega with (U, Omega) from base
 template <typename R>
 struct OpStoreBase {  // cache U, Omega of the base state; no forward transform
   static constexpr int NI = 3, NF = 0;
+  static constexpr int kXIn = 5;
   static constexpr bool kBase = true;
 };
 
 template <typename R>
 struct OpAdjCross {  // in = (lam_x + i lam_y, lam_z); out = adjoint of the linearised product
   static constexpr int NI = 2, NF = 3;
+  static constexpr int kXIn = 3;  // XF: the three fields as they are
   static constexpr bool kBase = true;
   template <typename C>
   __device__ void operator()(const C (&in)[2], C (&out)[3], const R* base, size_t bs,
@@ -92,10 +96,12 @@ struct ZLineMap {
   int fout_a[3], fout_b[3];
 };
 
-// XF: in = the five y-valued fields (u, du/dy, v, w, dw/dy) [f][y][kz][mx],
-// from which the six curl-combined fields of the x-lines are formed (the
-// line map must pair fields (0, 1), (2, 3), (4, 5)); requires nx % 16 == 0
-// (so px % XL == 0), nzm == P / 3 and a 1-D grid of ny * (px / XL) blocks. Otherwise in = the
+// XF: in = y-valued fields [f][y][kz][mx]: for Op::kXIn == 5 the five fields
+// (u, du/dy, v, w, dw/dy), from which the six curl-combined fields of the
+// x-lines are formed (the line map pairs fields (0, 1), (2, 3), (4, 5)); for
+// kXIn == 3 three fields taken as they are (pairs (0, 1), (2)). Requires
+// nx % 16 == 0 (so px % XL == 0), nzm == P / 3 and a 1-D grid of
+// ny * (px / XL) blocks. Otherwise in = the
 // x-physical fields [f][y][x][kz] and the grid is (ny, ceil(px / XL)).
 template <typename R, int P1, int P2, int XL, class Op, bool XF = false>
 __global__ void __launch_bounds__(256)
@@ -115,11 +121,11 @@ __global__ void __launch_bounds__(256)
   constexpr bool kSplit = Op::kBase && NF > 0 && NF <= NI;
   constexpr int LS = NI;  // line slots per x-line in the exchange block
   constexpr int E1 = (XL * LS * P2 * S1 > XL * NF * P) ? XL * LS * P2 * S1 : XL * NF * P;
-  constexpr int NXF = 6;  // x-physical fields formed by XF
+  constexpr int NXF = Op::kXIn == 5 ? 6 : Op::kXIn;  // x-physical fields formed by XF
   constexpr int E2F = NF > 0 ? XL * NF * P2 * S1 : 1;
   constexpr int E2X = XF ? XL * NXF * (P / 3) : 1;
-  static_assert(!XF || (XL == 8 && NI == 3 && E1 >= NXF * (P / 3) * (XL + 1)),
-                "XF: eight lines of three packed pairs; partial sums fit the exchange block");
+  static_assert(!XF || (XL == 8 && 2 * NI >= NXF && E1 >= NXF * (P / 3) * (XL + 1)),
+                "XF: eight lines of packed pairs; partial sums fit the exchange block");
   __shared__ C twl[P];
   __shared__ C ex1[E1];  // inverse exchange, then forward output (XF: first the partial sums)
   __shared__ C ex2[E2F > E2X ? E2F : E2X];  // forward exchange (XF: first the x-physical lines)
@@ -165,41 +171,47 @@ __global__ void __launch_bounds__(256)
       const int r = task % XL;
       const int kz = task / XL;
       const C* src = in + ((size_t)y * nzk + kz) * nx;
-      C A[5], B2 = mk((R)0, (R)0), B3 = mk((R)0, (R)0);
+      constexpr int NA = Op::kXIn;
+      C A[NA], B2 = mk((R)0, (R)0), B3 = mk((R)0, (R)0);
 #pragma unroll
-      for (int k = 0; k < 5; ++k) A[k] = mk((R)0, (R)0);
+      for (int k = 0; k < NA; ++k) A[k] = mk((R)0, (R)0);
       int q[2] = {(r * x0) % px, ((nx + r) * x0) % px};
       for (int t = 0; t < h8; ++t) {
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
           const int pos = (half ? nx : 0) + r + XL * t;
           const int i = half ? pos - h : pos;
-          const R kxv = alpha * (R)(half ? i - nx : i);
-          const C s0 = src[i], s1 = src[fsy + i], s2 = src[2 * fsy + i];
-          const C s3 = src[3 * fsy + i], s4 = src[4 * fsy + i];
+          C sk[NA];
+#pragma unroll
+          for (int k = 0; k < NA; ++k) sk[k] = src[k * fsy + i];
           // exp(2 pi i m a / px), zero at the empty position
           const R keep = (half && pos == nx) ? (R)0 : (R)1;
           const C w = cscale(conjc(twx[q[half]]), keep);
-          const C wk = cscale(w, kxv);
-          A[0] = cadd(A[0], cmul(s0, w));
-          A[1] = cadd(A[1], cmul(s1, w));
-          A[2] = cadd(A[2], cmul(s2, w));
-          A[3] = cadd(A[3], cmul(s3, w));
-          A[4] = cadd(A[4], cmul(s4, w));
-          B2 = cadd(B2, cmul(s2, wk));
-          B3 = cadd(B3, cmul(s3, wk));
+#pragma unroll
+          for (int k = 0; k < NA; ++k) A[k] = cadd(A[k], cmul(sk[k], w));
+          if constexpr (NA == 5) {
+            const R kxv = alpha * (R)(half ? i - nx : i);
+            const C wk = cscale(w, kxv);
+            B2 = cadd(B2, cmul(sk[2], wk));
+            B3 = cadd(B3, cmul(sk[3], wk));
+          }
           q[half] += dq;
           q[half] -= (q[half] >= px) ? px : 0;
         }
       }
-      const R kzv = gamma * (R)kz;
       C g[NXF];
-      g[0] = A[0];                                               // u
-      g[1] = A[2];                                               // v
-      g[2] = A[3];                                               // w
-      g[3] = csub(A[4], sidot(cscale(A[2], kzv), (R)1));         // dw/dy - i kz v
-      g[4] = sidot(csub(cscale(A[0], kzv), B3), (R)1);           // i kz u - i kx w
-      g[5] = csub(sidot(B2, (R)1), A[1]);                        // i kx v - du/dy
+      if constexpr (NA == 5) {
+        const R kzv = gamma * (R)kz;
+        g[0] = A[0];                                             // u
+        g[1] = A[2];                                             // v
+        g[2] = A[3];                                             // w
+        g[3] = csub(A[4], sidot(cscale(A[2], kzv), (R)1));       // dw/dy - i kz v
+        g[4] = sidot(csub(cscale(A[0], kzv), B3), (R)1);         // i kz u - i kx w
+        g[5] = csub(sidot(B2, (R)1), A[1]);                      // i kx v - du/dy
+      } else {
+#pragma unroll
+        for (int f = 0; f < NXF; ++f) g[f] = A[f];
+      }
 #pragma unroll
       for (int f = 0; f < NXF; ++f) gl[(f * nzk + kz) * (XL + 1) + r] = g[f];
     }
@@ -453,17 +465,22 @@ static void zline_launch(sp_plan* p, const void* in, void* out, R* base, const v
 #undef ZL
 }
 
-// Every block of the fused kernel reads its whole y-plane of the five y-valued
-// fields, so one plane is read px / kZXL times. Measured on MI355X: fused is
-// faster while those reads stay within one XCD's 4 MiB L2 (48x65x48 in FP64
-// and FP32: 0.8 and 0.4 MiB per plane; 96x97x96 in FP32: 3.2 MiB) and slower
-// beyond (96x97x96 in FP64: 6.3 MiB per plane, 146 us against 57 + 61 us for
-// the two kernels).
-bool zline_fuses_x_inverse(const sp_plan* p, bool fp32) {
+// Every block of the fused kernel reads its whole y-plane of the y-valued
+// fields, so one plane is read px / kZXL times. Measured on MI355X, forward
+// (five fields): fused is faster while those reads stay within one XCD's
+// 4 MiB L2 (48x65x48 in FP64 and FP32: 0.8 and 0.4 MiB per plane; 96x97x96
+// in FP32: 3.2 MiB) and slower beyond (96x97x96 in FP64: 6.3 MiB per plane,
+// 146 us against 57 + 61 us for the two kernels). The adjoint kernel (three
+// fields) holds two waves per SIMD instead of three and hides less of that
+// latency: fused it was 6-10 % faster at 48x65x48 (0.5 and 0.2 MiB) and 1-2 %
+// slower at 96x97x96 (3.8 and 1.9 MiB), so its bound is 1 MiB.
+bool zline_fuses_x_inverse(const sp_plan* p, bool fp32, int nfields) {
   const Dims& d = p->d;
   if (reg_fft_split(d.pz) == 0 || d.nx % (2 * kZXL) != 0 || 3 * d.nzm != d.pz) return false;
-  const size_t plane = (size_t)5 * d.nzm * d.nx * (fp32 ? sizeof(float2) : sizeof(double2));
-  return (size_t)(d.px / kZXL) * plane <= ((size_t)4 << 20);
+  const size_t plane =
+      (size_t)nfields * d.nzm * d.nx * (fp32 ? sizeof(float2) : sizeof(double2));
+  const size_t bound = (nfields == 5 ? (size_t)4 : (size_t)1) << 20;
+  return (size_t)(d.px / kZXL) * plane <= bound;
 }
 
 hipError_t launch_z_product(sp_plan* p, int mode, bool fp32) {
@@ -498,7 +515,7 @@ hipError_t launch_z_product(sp_plan* p, int mode, bool fp32) {
                                                       scale, p->d_twx);
     }
   };
-  if (zline_fuses_x_inverse(p, fp32))
+  if (zline_fuses_x_inverse(p, fp32, 5))
     run(std::true_type{});
   else
     run(std::false_type{});
@@ -512,10 +529,22 @@ hipError_t launch_adj_z(sp_plan* p, bool fp32) {
   const double scale = 1.0 / ((double)d.px * d.pz);
   const ZLineMap map{{0, 2, -1}, {1, -1, -1}, {0, 2, 4}, {1, 3, 5}};
   SP_PROF_BEGIN(p, KID_ADJ_Z);
-  if (fp32)
-    zline_launch<float, OpAdjCross<float>>(p, p->xp, p->xp, p->base32, p->f_twz, map, scale);
+  // fused: the three y-valued fields in p->nv, the inverse x transforms taken
+  // in the kernel; else the x-physical fields in p->xp, transformed in place
+  auto run = [&](auto xf) {
+    constexpr bool XF = decltype(xf)::value;
+    const void* in = XF ? p->nv : p->xp;
+    if (fp32)
+      zline_launch<float, OpAdjCross<float>, XF>(p, in, p->xp, p->base32, p->f_twz, map, scale,
+                                                 p->f_twx);
+    else
+      zline_launch<double, OpAdjCross<double>, XF>(p, in, p->xp, p->base, p->d_twz, map, scale,
+                                                   p->d_twx);
+  };
+  if (zline_fuses_x_inverse(p, fp32, 3))
+    run(std::true_type{});
   else
-    zline_launch<double, OpAdjCross<double>>(p, p->xp, p->xp, p->base, p->d_twz, map, scale);
+    run(std::false_type{});
   SP_PROF_END(p, KID_ADJ_Z);
   return hipGetLastError();
 }
