@@ -20,11 +20,13 @@ TOL = 1e-12
 # even ny: 12x20x12 (one element per scan lane, an odd Chebyshev degree) and
 # 8x64x8 (the largest ny with two elements per lane, the longest mode record
 # for that case). nx a multiple of 16 takes the z-line kernel that forms the
-# inverse x transforms itself: 16x17x16 and 32x33x32 with nx = nz, 16x17x32
-# and 32x25x16 with x and z lines of different lengths; the other grids run
-# the separate inverse x kernel.
+# inverse x transforms itself: 16x17x16 and 32x33x32 with nx = nz, 16x17x32,
+# 32x25x16 and 16x9x8 (the shortest z-lines it takes, 12 points) with x and z
+# lines of different lengths; the other grids run the separate inverse x
+# kernel.
 GRIDS = [(8, 9, 8, 400.0, 100.0), (16, 17, 16, 400.0, 100.0), (12, 21, 24, 1000.0, 1.0),
          (32, 33, 32, 400.0, 10.0), (16, 17, 32, 400.0, 100.0), (32, 25, 16, 1000.0, 10.0),
+         (16, 9, 8, 400.0, 100.0),
          (8, 97, 8, 400.0, 100.0), (8, 129, 8, 1000.0, 10.0),
          (12, 20, 12, 400.0, 100.0), (8, 64, 8, 1000.0, 10.0)]
 
