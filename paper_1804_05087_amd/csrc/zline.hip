@@ -101,11 +101,12 @@ struct ZLineMap {
 // x-lines are formed (the line map pairs fields (0, 1), (2, 3), (4, 5)); for
 // kXIn == 3 three fields taken as they are (pairs (0, 1), (2)). Requires
 // nx % 16 == 0 (so px % XL == 0), nzm == P / 3 and a 1-D grid of
-// ny * (px / XL) blocks. Otherwise in = the
-// x-physical fields [f][y][x][kz] and the grid is (ny, ceil(px / XL)).
+// ny * (px / XL) blocks; in and out do not alias.
+// Otherwise in = the x-physical fields [f][y][x][kz] (out may alias it) and
+// the grid is (ny, ceil(px / XL)).
 template <typename R, int P1, int P2, int XL, class Op, bool XF = false>
 __global__ void __launch_bounds__(256)
-    k_zline(const typename V2<R>::T* in, typename V2<R>::T* out,  // may alias (in place)
+    k_zline(const typename V2<R>::T* in, typename V2<R>::T* out,
             R* __restrict__ base, const typename V2<R>::T* __restrict__ tw, ZLineMap map, int ny,
             int px, int nzm, R scale, const typename V2<R>::T* __restrict__ twx = nullptr,
             int nx = 0, R alpha = 0, R gamma = 0) {
@@ -152,16 +153,15 @@ __global__ void __launch_bounds__(256)
   auto line_of = [&](int xl) { return (size_t)y * px + x0 + (size_t)xq * xl; };
   for (int t = tid; t < P; t += 256) twl[t] = tw[t];
   if constexpr (XF) {
-    // partial sums g_r of the six curl-combined fields: task (kz, r), over the
-    // kept padded positions m = r mod XL. With nx a multiple of 16 these are,
-    // for t < nx/16, m = r + XL t (mode i = m) in the low half and
-    // m = nx + r + XL t (mode i = m - nx/2) in the high half, except the empty
-    // position m = nx; taken in pairs with unconditional loads (the empty one
-    // loads mode nx/2 and is weighted 0) so that each pair's loads are in
-    // flight together.
-    // The curl combination is linear, so the sums run over the five input
-    // fields (A_k = sum w s_k) and, for the two terms with a factor i k_x,
-    // over k_x w s_k (B_2, B_3); the six fields are formed from them once.
+    // Partial sums g_r of the NXF x-line fields: task (kz, r), over the kept
+    // padded positions m = r mod XL. With nx a multiple of 16 these are, for
+    // t < nx/16, m = r + XL t (mode i = m) in the low half and m = nx + r + XL t
+    // (mode i = m - nx/2) in the high half, except the empty position m = nx;
+    // taken in pairs with unconditional loads (the empty one loads mode nx/2
+    // and is weighted 0) so that each pair's loads are in flight together.
+    // The curl combination is linear, so the sums run over the input fields
+    // (A_k = sum w s_k) and, for the two curl terms with a factor i k_x, over
+    // k_x w s_k (B_2, B_3); the six fields are formed from them once.
     C* gl = ex1;  // [NXF][nzm][XL + 1]
     const size_t fsy = (size_t)ny * nzk * nx;
     const int h = nx / 2;
