@@ -57,16 +57,16 @@ KERNEL_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     "couette_48x65x48_re1000_dt100": {
-        # 256 MiB copy: FETCH_SIZE 131091.8 KiB, WRITE_SIZE 262144.0 KiB
+        # 256 MiB copy: FETCH_SIZE 131095.3 KiB, WRITE_SIZE 262144.0 KiB
         "k_stokes_solve": {
             "fetch_kib": 5611.6, "write_kib": 3674.3,
-            "fetch_factor": 262144.0 / 131091.8, "write_factor": 1.0,
+            "fetch_factor": 262144.0 / 131095.3, "write_factor": 1.0,
             "sources_sha256": "6d8eab5a02c7bee69b1cf019c8fb8eb0cc3333c2d80294df2cb5a5525c6c53f6",
         },
         "k_z_product": {
             "fetch_kib": 3337.1, "write_kib": 5265.0,
-            "fetch_factor": 262144.0 / 131091.8, "write_factor": 1.0,
-            "sources_sha256": "0fbe38d5c82e331a4fefd54e3ac98fee0ef3a83fb749dfbe5095d33b33271028",
+            "fetch_factor": 262144.0 / 131095.3, "write_factor": 1.0,
+            "sources_sha256": "9a914b3f355c42eb20a1920283f7ef6e70b740bf1c393267c7e68a08b5f87e08",
         },
     },
 }
